@@ -1,0 +1,133 @@
+/*
+ * oracle.h -- plain FP64 CPU reference of the cylindrical envelope PIC step.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This library is the checker for the HIP path:
+ * only the test suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or constant with
+ * the GPU library; the two are developed against the same written method
+ * (Massimo et al., "Efficient cylindrical envelope modeling for laser
+ * wakefield acceleration", arXiv:1912.04674) and compared by value.
+ *
+ * Units are those of the paper (Sec. 2): lengths in c/w0, time in 1/w0,
+ * momenta in m_e c, fields in m_e c w0 / e, densities in n_c.
+ *
+ * Conventions (all host memory, caller-owned buffers):
+ *   - grids are window-relative arrays of (nx+1) x (nr+1) entries, row-major
+ *     [i][j] with j (radius) fastest.  A quantity staggered by half a cell in
+ *     x (resp. r) at index (i, j) lives at x = (i+1/2)dx (resp. r = (j+1/2)dr).
+ *     Complex grids are interleaved (re, im) doubles, 2 (nx+1)(nr+1) values.
+ *   - particles are exchanged as separate FP64 arrays in lab-frame Cartesian
+ *     coordinates plus a uint32 identifier.
+ *   - every call returns 0 on success or a negative code.
+ */
+#ifndef ENVPIC_ORACLE_H
+#define ENVPIC_ORACLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORACLE_PARAMS_VERSION 1
+
+enum {
+  ORACLE_OK = 0,
+  ORACLE_EINVAL = -1,
+  ORACLE_ENUMERIC = -5,
+};
+
+/* plasma profile kinds */
+enum {
+  ORACLE_PROFILE_NONE = 0,      /* vacuum */
+  ORACLE_PROFILE_UNIFORM = 1,   /* n0 everywhere */
+  ORACLE_PROFILE_RAMP = 2,      /* linear 0 -> n0 over lab x in [0, ramp_len], then n0 */
+  ORACLE_PROFILE_PERTURB = 3,   /* n0 (1 + perturb (2u-1)), u uniform per cell */
+  ORACLE_PROFILE_BUMP = 4,      /* n0 (1 + exp(-((x-bump_x)/bump_w)^2)) */
+};
+
+typedef struct oracle_params {
+  int32_t size, version;
+  int32_t nx, nr;        /* cells along x and r */
+  int32_t n_modes;       /* 1: azimuthal mode 0 only; 2: modes 0 and 1 */
+  int32_t ppc_x, ppc_r, ppc_t;
+  int32_t profile;
+  int32_t moving_window; /* 1: window follows the pulse at c */
+  int32_t env_bc_x;      /* test hook: 0 Dirichlet ends, 1 periodic in x */
+  int32_t env_bc_r;      /* test hook: 0 Dirichlet at r_max, 1 even mirror */
+  uint64_t seed;
+  double dx, dr, dt;
+  double a0, w0, tau, x_c, x_f; /* tau = FWHM duration of |A| */
+  double n0, ramp_len, perturb, bump_x, bump_w;
+} oracle_params;
+
+/* grid identifiers (window-relative (nx+1) x (nr+1) arrays) */
+enum {
+  ORACLE_F_ENV = 0,      /* A^n          complex, (i, j)          */
+  ORACLE_F_ENV_PREV = 1, /* A^{n-1}      complex, (i, j)          */
+  ORACLE_F_CHI = 2,      /* chi^n        real,    (i, j)          */
+  ORACLE_F_EX = 3,       /* E_x^n        real,    (i+1/2, j)      */
+  ORACLE_F_ER = 4,       /* E_r^n        real,    (i, j+1/2)      */
+  ORACLE_F_BT = 5,       /* B_t^{n+1/2}  real,    (i+1/2, j+1/2)  */
+  ORACLE_F_BT_BAR = 6,   /* Bbar_t^n     real,    (i+1/2, j+1/2)  */
+  ORACLE_F_JX = 7,       /* J_x^{n+1/2}  real,    (i+1/2, j)      */
+  ORACLE_F_JR = 8,       /* J_r^{n+1/2}  real,    (i, j+1/2)      */
+  ORACLE_F_EX1 = 9,      /* mode-1 fields, complex */
+  ORACLE_F_ER1 = 10,
+  ORACLE_F_ET1 = 11,     /* (i, j) */
+  ORACLE_F_BX1 = 12,     /* (i, j+1/2) */
+  ORACLE_F_BR1 = 13,     /* (i+1/2, j) */
+  ORACLE_F_BT1 = 14,
+  ORACLE_F_BX1_BAR = 15,
+  ORACLE_F_BR1_BAR = 16,
+  ORACLE_F_BT1_BAR = 17,
+  ORACLE_F_JX1 = 18,
+  ORACLE_F_JR1 = 19,
+  ORACLE_F_JT1 = 20,
+  ORACLE_NFIELDS = 21
+};
+
+/* diagnostics vector (all FP64) */
+enum {
+  ORACLE_D_COUNT = 0,    /* live macro-particles */
+  ORACLE_D_CHARGE = 1,   /* sum q w */
+  ORACLE_D_CHI_V = 2,    /* sum over nodes chi V */
+  ORACLE_D_KIN = 3,      /* sum w (gamma - 1), gamma = sqrt(1 + |p|^2) */
+  ORACLE_D_UEM = 4,      /* low-frequency field energy */
+  ORACLE_D_ENV2_V = 5,   /* sum over nodes |A|^2 V */
+  ORACLE_D_LX = 6,       /* sum w (y p_z - z p_y) */
+  ORACLE_D_PX = 7,       /* sum w p_x */
+  ORACLE_D_NONFINITE = 8,/* number of non-finite state values */
+  ORACLE_NDIAG = 9
+};
+
+int oracle_create(const oracle_params* p, void** out);
+void oracle_destroy(void* sim);
+
+/* the step, split into the stages of one PIC cycle */
+int oracle_momentum_chi(void* sim); /* p^{n-1/2} -> p^{n+1/2}, deposit chi^n      */
+int oracle_envelope(void* sim);     /* A^{n+1} from A^n, A^{n-1}, chi^n           */
+int oracle_position_J(void* sim);   /* x^n -> x^{n+1}, deposit J^{n+1/2}         */
+int oracle_field_step(void* sim);   /* E^{n+1}, B^{n+3/2}, Bbar^{n+1}, window; n+1 */
+int oracle_step(void* sim, int nsteps);
+
+int oracle_state(void* sim, int64_t* n, int64_t* shift, int64_t* n_particles);
+int oracle_get_particles(void* sim, double* x, double* y, double* z, double* px,
+                         double* py, double* pz, double* w, uint32_t* id);
+int oracle_set_particles(void* sim, int64_t n, const double* x, const double* y,
+                         const double* z, const double* px, const double* py,
+                         const double* pz, const double* w, const uint32_t* id);
+/* gbar^n of each particle as left by the last momentum stage (particle order) */
+int oracle_get_gbar(void* sim, double* gbar);
+int oracle_get_field(void* sim, int field, double* out);
+int oracle_set_field(void* sim, int field, const double* in);
+int oracle_diagnostics(void* sim, double* out);
+
+/* counter-based uniform deviate in [0,1) used for loading (SplitMix64) */
+double oracle_uniform(uint64_t seed, uint64_t stream, int64_t col, int64_t j);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

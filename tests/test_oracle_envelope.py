@@ -1,0 +1,126 @@
+"""Pins of the oracle's envelope solver against closed forms.
+
+Envelope equation: Sec. 2, Eq. envelope_equation; scheme: Sec. 3,
+Eq. envelope_solver with the cylindrical Laplacian printed after it.
+"""
+import numpy as np
+import pytest
+from scipy.optimize import brentq
+
+
+def _vac(nx, nr, dx=0.8, dr=1.5, dt=0.6, **kw):
+    cfg = dict(nx=nx, nr=nr, dx=dx, dr=dr, dt=dt, profile="none", a0=0.0)
+    cfg.update(kw)
+    return cfg
+
+
+def _discrete_omega(k, chi, dx, dt):
+    """Root of the dispersion relation of the centred scheme for A = e^{i(kx - wt)}:
+    (4/dt^2) sin^2(w dt/2) + (2/dt) sin(w dt) = (4/dx^2) sin^2(k dx/2) + (2/dx) sin(k dx) + chi
+    (derived by substituting the plane wave into the two-level scheme)."""
+    rhs = 4 / dx**2 * np.sin(k * dx / 2) ** 2 + 2 / dx * np.sin(k * dx) + chi
+    f = lambda w: 4 / dt**2 * np.sin(w * dt / 2) ** 2 + 2 / dt * np.sin(w * dt) - rhs
+    w_cont = np.sqrt((k + 1) ** 2 + chi) - 1  # continuum: (w+1)^2 = (k+1)^2 + chi
+    return brentq(f, w_cont - 0.4, w_cont + 0.4, xtol=1e-18, rtol=1e-15, maxiter=200)
+
+
+@pytest.mark.parametrize("m,chi", [(1, 0.0), (3, 0.002), (-2, 0.01), (5, 0.05)])
+def test_discrete_dispersion(oracle_mod, m, chi):
+    """A plane envelope wave advances by exactly the phase the discrete
+    dispersion relation predicts (x part, 2i d/dx, 2i d/dt, d2/dt2, chi)."""
+    nx, nr, dx, dt = 64, 3, 0.8, 0.6
+    s = oracle_mod.OracleSim(_vac(nx, nr, dx=dx, dt=dt, env_bc_x=1, env_bc_r=1))
+    k = 2 * np.pi * m / (nx * dx)
+    w = _discrete_omega(k, chi, dx, dt)
+    x = np.arange(nx + 1)[:, None] * dx * np.ones((1, nr + 1))
+    s.set_field("env", np.exp(1j * k * x))
+    s.set_field("env_prev", np.exp(1j * (k * x + w * dt)))
+    s.set_field("chi", np.full((nx + 1, nr + 1), chi))
+    nsteps = 1000
+    for _ in range(nsteps):
+        s.envelope()
+    expect = np.exp(1j * (k * x - w * nsteps * dt))
+    assert np.abs(s.get_field("env") - expect).max() < 1e-11
+
+
+def _radial_laplacian(oracle_mod, dr, wgauss=20.0):
+    """Discrete transverse Laplacian of exp(-r^2/w^2), read off one envelope
+    step: with A^n = A^{n-1} = G and chi = 0 the scheme gives
+    A^{n+1} = G + (1+i dt)/(1+dt^2) dt^2 lap G."""
+    nr = int(round(120 / dr))
+    nx, dt = 8, 0.5 * dr
+    s = oracle_mod.OracleSim(_vac(nx, nr, dx=1.0, dr=dr, dt=dt, env_bc_x=1))
+    r = np.arange(nr + 1) * dr
+    G = np.exp(-r**2 / wgauss**2)[None, :] * np.ones((nx + 1, 1))
+    s.set_field("env", G.astype(complex))
+    s.set_field("env_prev", G.astype(complex))
+    s.envelope()
+    pref = (1 + 1j * dt) / (1 + dt**2)
+    lap = ((s.get_field("env") - G) / (pref * dt**2))[3]
+    exact = (4 * r**2 / wgauss**4 - 4 / wgauss**2) * np.exp(-r**2 / wgauss**2)
+    return r, lap, exact
+
+
+def test_radial_operator_and_axis(oracle_mod):
+    """lap_perp exp(-r^2/w^2) = (4r^2/w^4 - 4/w^2) exp(-r^2/w^2), -4/w^2 on the
+    axis; the printed 5-point operator with the on-axis limit converges at
+    second order (the 1/r term of the printed Laplacian is singular at r=0,
+    the axis row uses the limit 2 d2/dr2)."""
+    r1, lap1, ex1 = _radial_laplacian(oracle_mod, 1.5)
+    r2, lap2, ex2 = _radial_laplacian(oracle_mod, 0.75)
+    assert np.abs(lap1.imag).max() < 1e-12
+    # axis value at dr = 1.5, w = 20: 4 (exp(-dr^2/w^2) - 1)/dr^2 = -0.0099719
+    assert lap1[0].real == pytest.approx(-0.01, rel=3e-3)
+    assert lap1[0].real == pytest.approx(4 * (np.exp(-1.5**2 / 400) - 1) / 1.5**2, rel=1e-9)
+    e1 = np.abs(lap1.real - ex1)[:-2].max()
+    e2 = np.abs(lap2.real - ex2)[:-2].max()
+    assert e1 / e2 > 3.5  # second order
+    assert e1 < 5e-5
+
+
+def _paraxial_run(oracle_mod, dx, dr, dt, travel=60.0):
+    nx, nr = int(round(256 / dx)), int(round(96 / dr))
+    x_c = round(90.4 / dx) * dx
+    cfg = _vac(nx, nr, dx=dx, dr=dr, dt=dt, a0=1.0, w0=20.0, tau=30.0, x_c=x_c, x_f=x_c)
+    s = oracle_mod.OracleSim(cfg)
+    r = np.arange(nr + 1) * dr
+
+    def measure(xpk):
+        col = s.get_field("env")[int(round(xpk / dx))]
+        i2 = np.abs(col) ** 2
+        w = np.sqrt(2 * np.trapezoid(i2 * r**3, r) / np.trapezoid(i2 * r, r))
+        return w, np.abs(col[0]), np.angle(col[0])
+
+    w0m, a0m, ph0 = measure(x_c)
+    nsteps = int(round(travel / dt))
+    for _ in range(nsteps):
+        s.envelope()
+    w1, a1, ph1 = measure(x_c + nsteps * dt)
+    return nsteps * dt, w1 / w0m, a1 / a0m, ph1 - ph0
+
+
+def test_paraxial_vacuum_diffraction(oracle_mod):
+    """Gaussian pulse from focus in vacuum (the paper's first benchmark, Sec. 4,
+    scaled to w0 = 20): waist w(X) = w0 sqrt(1 + X^2/Z_R^2), on-axis amplitude
+    a0 w0/w and Gouy phase -atan(X/Z_R), Z_R = w0^2/2 (k0 = 1).  The residual
+    offset (~1e-3) is the non-paraxial / finite-duration physics of the full
+    envelope equation: it is resolution independent."""
+    X, wr, ar, dph = _paraxial_run(oracle_mod, 0.8, 1.5, 0.6)
+    zr = 200.0
+    assert X == pytest.approx(60.0)
+    assert wr == pytest.approx(np.sqrt(1 + (X / zr) ** 2), abs=2e-3)     # 1.04403
+    assert ar == pytest.approx(1 / np.sqrt(1 + (X / zr) ** 2), abs=3e-3)  # 0.95783
+    assert dph == pytest.approx(-np.arctan(X / zr), abs=5e-3)             # -0.29146
+    # discretisation part: halving every step size moves the result by < 5e-4
+    _, wr2, ar2, dph2 = _paraxial_run(oracle_mod, 0.4, 0.75, 0.3)
+    assert abs(wr2 - wr) < 5e-4 and abs(ar2 - ar) < 5e-4 and abs(dph2 - dph) < 1e-3
+
+
+def test_envelope_boundaries_stay_zero(oracle_mod):
+    cfg = _vac(64, 16, a0=1.0, w0=10.0, tau=8.0, x_c=25.6, x_f=25.6)
+    s = oracle_mod.OracleSim(cfg)
+    for _ in range(40):
+        s.envelope()
+    A = s.get_field("env")
+    assert np.all(A[0] == 0) and np.all(A[-1] == 0) and np.all(A[:, -1] == 0)
+    assert np.abs(A).max() > 0.1

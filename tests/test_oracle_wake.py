@@ -1,0 +1,49 @@
+"""End-to-end pin of the oracle loop: the linear wake of a weak Gaussian pulse
+(the paper's second benchmark, Sec. 4: a0 = 0.01, w0 = 90, FWHM field
+duration 70, n0 = 0.0017 n_c, dx = 0.7, dr = 5, dt = 0.8 dx, 6 particles per
+cell), propagated 300 c/w0 instead of 1000 to keep the CPU suite short.
+
+Reference: cold-fluid, quasi-static linear theory.  With xi = x - t and the
+ponderomotive source |A|^2/4, (d2/dxi2 + kp^2) phi = kp^2 |A|^2/4, E_x =
+-d phi/d xi, causal Green's function:
+    E_x(xi, r) = kp^2 int_xi^inf cos(kp (xi' - xi)) |A(xi', r)|^2 / 4 dxi'
+(no transverse derivative enters, so it holds at each radius; far behind the
+pulse its amplitude is kp^2 (a0^2/4) sigma sqrt(pi/2) exp(-kp^2 sigma^2/8) =
+1.54e-6 on the axis).
+"""
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+
+@pytest.mark.slow
+def test_linear_wake_matches_quasistatic_theory(oracle_mod):
+    dx, dr, dt = 0.7, 5.0, 0.56
+    nx, nr = 700, 20
+    a0, w0, tau, n0 = 0.01, 90.0, 70.0, 0.0017
+    sig = tau / (2 * np.sqrt(np.log(2)))
+    x_c = nx * dx - 130.0
+    cfg = dict(nx=nx, nr=nr, dx=dx, dr=dr, dt=dt, profile="uniform", n0=n0, ppc=(2, 3, 1),
+               a0=a0, w0=w0, tau=tau, x_c=x_c, x_f=x_c, moving_window=1)
+    s = oracle_mod.OracleSim(cfg)
+    s.step(536)
+    n, shift, _ = s.state()
+    Ex = s.get_field("ex")
+    kp = np.sqrt(n0)
+    xs = (np.arange(nx) + 0.5) * dx + shift * dx
+    xi_c = x_c + n * dt
+    amp_far = kp**2 * (a0**2 / 4) * sig * np.sqrt(np.pi / 2) * np.exp(-kp**2 * sig**2 / 8)
+    assert amp_far == pytest.approx(1.54e-6, rel=2e-3)
+    sel = (xs > xi_c - 250) & (xs < xi_c - 2 * sig)
+    for j in (0, 1, 2):
+        r = j * dr
+
+        def src(u):
+            return a0**2 * np.exp(-2 * r**2 / w0**2) * np.exp(-2 * ((u - xi_c) / sig) ** 2) / 4
+
+        ana = np.array([kp**2 * quad(lambda u: np.cos(kp * (u - x)) * src(u), x,
+                                     xi_c + 8 * sig, limit=200)[0] for x in xs[sel]])
+        num = Ex[:nx, j][sel]
+        amp = np.abs(ana).max()
+        assert np.abs(num).max() == pytest.approx(amp, rel=1e-2)
+        assert np.abs(num - ana).max() < 3e-2 * amp
