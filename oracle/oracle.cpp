@@ -615,7 +615,7 @@ void shift_grid(Sim& s, std::vector<T>& f, bool dual_x) {
 
 void window(Sim& s) {
   if (!s.p.moving_window) return;
-  if ((double)(s.n + 1) * s.dt < (double)(s.shift + 1) * s.dx) return;
+  if ((double)(s.n + 1) * s.dt < (double)(s.shift - s.p.start_col + 1) * s.dx) return;
   const double xcut = (double)(s.shift + 1) * s.dx;
   size_t m = 0;
   for (size_t k = 0; k < s.x.size(); ++k) {
@@ -674,6 +674,7 @@ bool check_params(const oracle_params* p) {
   if (!(p->dx > 0 && p->dr > 0 && p->dt > 0)) return false;
   /* one cell at most per step along each axis (the current deposit needs it) */
   if (!(p->dt < p->dx && p->dt < p->dr)) return false;
+  if (p->start_col < 0) return false;
   return true;
 }
 
@@ -699,11 +700,11 @@ int oracle_create(const oracle_params* p, void** out) {
   s->dr = p->dr;
   s->dt = p->dt;
   s->n = 0;
-  s->shift = 0;
+  s->shift = p->start_col;
   init_fields(*s);
   if (p->profile != ORACLE_PROFILE_NONE)
     for (int64_t c = 0; c < p->nx; ++c)
-      for (int j = 0; j < p->nr; ++j) load_cell(*s, c, j);
+      for (int j = 0; j < p->nr; ++j) load_cell(*s, p->start_col + c, j);
   *out = s;
   return ORACLE_OK;
 }

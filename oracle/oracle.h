@@ -60,6 +60,8 @@ typedef struct oracle_params {
   double dx, dr, dt;
   double a0, w0, tau, x_c, x_f; /* tau = FWHM duration of |A| */
   double n0, ramp_len, perturb, bump_x, bump_w;
+  int64_t start_col;     /* lab column of the window's left edge at n = 0 (a slab
+                            of a larger run: same positions, angles and ids) */
 } oracle_params;
 
 /* grid identifiers (window-relative (nx+1) x (nr+1) arrays) */

@@ -45,6 +45,7 @@ class OracleParams(ctypes.Structure):
         ("n0", ctypes.c_double), ("ramp_len", ctypes.c_double),
         ("perturb", ctypes.c_double), ("bump_x", ctypes.c_double),
         ("bump_w", ctypes.c_double),
+        ("start_col", ctypes.c_int64),
     ]
 
 
@@ -117,6 +118,7 @@ def make_params(cfg):
     p.perturb = float(cfg.get("perturb", 0.0))
     p.bump_x = float(cfg.get("bump_x", 0.0))
     p.bump_w = float(cfg.get("bump_w", 1.0))
+    p.start_col = int(cfg.get("start_col", 0))
     return p
 
 

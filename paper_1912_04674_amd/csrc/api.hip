@@ -1,0 +1,977 @@
+// api.hip -- host implementation of the envpic C ABI (include/envpic.h).
+//
+// The library never allocates device memory: every array lives in the
+// caller's arena, carved by `plan()` below.  Kernel launches are
+// asynchronous on the simulation's stream; IO and diagnostics synchronise.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/envpic.h"
+#include "common.hpp"
+#include "launch.hpp"
+
+using namespace envpic;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int hip_check(hipError_t e, const char* what) {
+  if (e == hipSuccess) return ENVPIC_OK;
+  return fail(ENVPIC_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// ------------------------------------------------------------ geometry --
+struct Sizes {
+  int nxa, pitch, ntxa, ntr, ntiles, ppc, max_items;
+  long long capacity;
+  size_t ngrid;  // elements per grid
+};
+
+Sizes sizes_of(const envpic_params& p) {
+  Sizes s;
+  s.ntxa = (p.nx + 2 + TX - 1) / TX + 3;
+  s.nxa = s.ntxa * TX;
+  s.pitch = (int)align_up((size_t)p.nr + 1, 16);
+  s.ntr = (p.nr + TR - 1) / TR;
+  s.ntiles = s.ntxa * s.ntr;
+  s.ppc = p.ppc_x * p.ppc_r * p.ppc_t;
+  const long long window = (long long)p.nx * p.nr * s.ppc;
+  s.capacity = p.capacity > 0 ? p.capacity : window + 2LL * p.nr * s.ppc + 1024;
+  s.max_items = (int)(s.ntiles + s.capacity / CHUNK + s.ntr + 16);
+  s.ngrid = (size_t)s.nxa * s.pitch;
+  return s;
+}
+
+int validate(const envpic_params* p) {
+  if (!p) return fail(ENVPIC_EINVAL, "params is NULL");
+  if (p->size != (int32_t)sizeof(envpic_params) || p->version != ENVPIC_PARAMS_VERSION)
+    return fail(ENVPIC_EINVAL, "params size/version mismatch");
+  if (p->nx < 4 || p->nr < 2) return fail(ENVPIC_EINVAL, "grid needs nx >= 4 and nr >= 2");
+  if (p->nr > NR_MAX) return fail(ENVPIC_EINVAL, "nr exceeds the 12-bit radial cell index");
+  if (p->nx > COL_MAX / 2) return fail(ENVPIC_EINVAL, "nx exceeds the 20-bit lab column index");
+  if (p->n_modes < 1 || p->n_modes > 2) return fail(ENVPIC_EINVAL, "n_modes must be 1 or 2");
+  if (p->ppc_x < 1 || p->ppc_r < 1 || p->ppc_t < 1 || p->ppc_x * p->ppc_r * p->ppc_t > 256)
+    return fail(ENVPIC_EINVAL, "particles per cell must be in [1, 256]");
+  if ((p->tile_x != 0 && p->tile_x != TX) || (p->tile_r != 0 && p->tile_r != TR))
+    return fail(ENVPIC_EINVAL, "tile shape must be 16 x 16 (or 0 for the default)");
+  if (!(p->dx > 0 && p->dr > 0 && p->dt > 0)) return fail(ENVPIC_EINVAL, "dx, dr, dt must be positive");
+  if (!(p->dt < p->dx && p->dt < p->dr))
+    return fail(ENVPIC_EINVAL, "dt must be below dx and dr (particles move at most one cell per step)");
+  // Stability: both the envelope scheme and the cylindrical Yee scheme are
+  // about 2 % stricter than the Cartesian bound 1/sqrt(1/dx^2 + 1/dr^2) once
+  // the axis rows are included; 0.97 of that bound keeps a margin.
+  const double cart = 1.0 / std::sqrt(1.0 / (p->dx * p->dx) + 1.0 / (p->dr * p->dr));
+  if (p->dt > 0.97 * cart) {
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "dt = %g exceeds the stability limit ~%.4f for dx = %g, dr = %g", p->dt,
+                  0.97 * cart, p->dx, p->dr);
+    return fail(ENVPIC_EINVAL, buf);
+  }
+  if (p->profile < 0 || p->profile > 4) return fail(ENVPIC_EINVAL, "unknown plasma profile");
+  if (p->n0 < 0) return fail(ENVPIC_EINVAL, "n0 must be >= 0");
+  if (p->profile == ENVPIC_PROFILE_RAMP && !(p->ramp_len > 0)) return fail(ENVPIC_EINVAL, "ramp_len must be > 0");
+  if (p->profile == ENVPIC_PROFILE_BUMP && !(p->bump_w > 0)) return fail(ENVPIC_EINVAL, "bump_w must be > 0");
+  if (p->a0 < 0 || (p->a0 > 0 && !(p->w0 > 0 && p->tau > 0))) return fail(ENVPIC_EINVAL, "bad laser parameters");
+  const Sizes s = sizes_of(*p);
+  if (s.capacity >= (1LL << 31) - 1) return fail(ENVPIC_EINVAL, "too many particles for int32 slots");
+  if (s.capacity < (long long)p->nx * p->nr * s.ppc + (long long)p->nr * s.ppc)
+    return fail(ENVPIC_EINVAL, "capacity below one window of particles plus one column");
+  return ENVPIC_OK;
+}
+
+// -------------------------------------------------------- arena layout --
+struct Carver {
+  char* base;
+  size_t off = 0;
+  template <class T> T* take(size_t count) {
+    off = align_up(off, 256);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+template <class R> struct State {
+  using C = typename cplx_of<R>::type;
+  Parts<R> parts[2], scr;
+  Grids<R> grids;
+  DepositBufs<R> dep[2];
+  Layout lay[2];
+  int* hist;
+  int* err;
+  double* diag_scratch;
+  double* diag_out;
+};
+
+template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64_rows, char* base, State<R>* st) {
+  using C = typename cplx_of<R>::type;
+  Carver cv{base};
+  State<R> S{};
+  const size_t cap = (size_t)s.capacity;
+  for (int b = 0; b < 2; ++b) {
+    Parts<R>& P = S.parts[b];
+    P.cell = cv.take<unsigned>(cap);
+    P.fx = cv.take<R>(cap);
+    P.fr = cv.take<R>(cap);
+    P.th = cv.take<R>(cap);
+    P.px = cv.take<R>(cap);
+    P.py = cv.take<R>(cap);
+    P.pz = cv.take<R>(cap);
+    P.w = cv.take<R>(cap);
+    P.id = cv.take<uint32_t>(cap);
+  }
+  S.scr.cell = cv.take<unsigned>(cap);
+  S.scr.fx = cv.take<R>(cap);
+  S.scr.fr = cv.take<R>(cap);
+  S.scr.th = cv.take<R>(cap);
+  S.scr.w = cv.take<R>(cap);
+  const size_t ng = s.ngrid;
+  Grids<R>& f = S.grids;
+  f.ex = cv.take<R>(ng);
+  f.er = cv.take<R>(ng);
+  f.bt = cv.take<R>(ng);
+  f.btb = cv.take<R>(ng);
+  f.env = cv.take<C>(ng);
+  f.envp = cv.take<C>(ng);
+  f.ax = fp64_rows ? cv.take<double2>((size_t)s.nxa * 2) : nullptr;
+  f.axp = fp64_rows ? cv.take<double2>((size_t)s.nxa * 2) : nullptr;
+  const bool m1 = p.n_modes >= 2;
+  const size_t n1 = m1 ? ng : 0;
+  f.ex1 = cv.take<C>(n1);
+  f.er1 = cv.take<C>(n1);
+  f.et1 = cv.take<C>(n1);
+  f.bx1 = cv.take<C>(n1);
+  f.br1 = cv.take<C>(n1);
+  f.bt1 = cv.take<C>(n1);
+  f.bxb1 = cv.take<C>(n1);
+  f.brb1 = cv.take<C>(n1);
+  f.btb1 = cv.take<C>(n1);
+  for (int b = 0; b < 2; ++b) {
+    DepositBufs<R>& d = S.dep[b];
+    d.chi = cv.take<R>(ng);
+    d.jx = cv.take<R>(ng);
+    d.jr = cv.take<R>(ng);
+    d.jx1 = cv.take<C>(n1);
+    d.jr1 = cv.take<C>(n1);
+    d.jt1 = cv.take<C>(n1);
+  }
+  f.chi = nullptr;
+  f.jx = nullptr;
+  f.jr = nullptr;
+  f.jx1 = f.jr1 = f.jt1 = nullptr;
+  for (int b = 0; b < 2; ++b) {
+    Layout& L = S.lay[b];
+    L.offsets = cv.take<int>((size_t)s.ntiles + 1);
+    L.cursor = cv.take<int>((size_t)s.ntiles);
+    L.items = cv.take<int4>((size_t)s.max_items);
+    L.n_items = cv.take<int>(1);
+  }
+  S.hist = cv.take<int>((size_t)s.ntiles);
+  S.err = cv.take<int>(1);
+  Geo g{};
+  g.nx = p.nx;
+  g.nr = p.nr;
+  S.diag_scratch = cv.take<double>((size_t)diag_scratch_doubles(s.max_items, g));
+  S.diag_out = cv.take<double>(ENVPIC_NDIAG);
+  if (st) *st = S;
+  return align_up(cv.off, 256);
+}
+
+size_t footprint_bytes(const envpic_params& p, int prec) {
+  const Sizes s = sizes_of(p);
+  if (prec == ENVPIC_FP64) return plan<double>(p, s, false, nullptr, nullptr);
+  return plan<float>(p, s, true, nullptr, nullptr);
+}
+
+}  // namespace
+
+// ================================================================ sim ==
+struct envpic_sim {
+  envpic_params p;
+  int prec;
+  hipStream_t stream;
+  Sizes sz;
+  int64_t n = 0, shift = 0;
+  int stage = 0;     // next expected stage: 0 momentum, 1 envelope, 2 position, 3 field
+  int cur = 0;       // particle buffer holding the current state
+  bool deferred = false, deposit_done = true;
+  int chi_last = 0;  // deposit buffer of the last momentum stage
+  virtual ~envpic_sim() {}
+  virtual int init() = 0;
+  virtual int momentum(bool defer) = 0;
+  virtual int project(int what) = 0;
+  virtual int envelope() = 0;
+  virtual int position(bool defer) = 0;
+  virtual int field() = 0;
+  virtual int get_field(int f, double* out) = 0;
+  virtual int set_field(int f, const double* in) = 0;
+  virtual int get_particles(std::vector<double>* cols, std::vector<uint32_t>* ids) = 0;
+  virtual int set_particles(int64_t n, const double* const* cols, const uint32_t* id) = 0;
+  virtual int diagnostics(double* out) = 0;
+  virtual int poison(int f) = 0;
+  virtual int check_err() = 0;
+  virtual int clear_deposits() = 0;
+
+  bool shift_due() const {
+    return p.moving_window && (double)(n + 1) * p.dt >= (double)(shift + 1) * p.dx;
+  }
+  int step() {
+    int rc;
+    if ((rc = momentum(false))) return rc;
+    if ((rc = envelope())) return rc;
+    if ((rc = position(false))) return rc;
+    return field();
+  }
+};
+
+namespace {
+
+template <class R> struct SimT : envpic_sim {
+  using C = typename cplx_of<R>::type;
+  State<R> S;
+  bool fp64_rows;
+  char* arena;
+
+  Geo geo() const {
+    Geo g{};
+    g.nx = p.nx;
+    g.nr = p.nr;
+    g.nxa = sz.nxa;
+    g.pitch = sz.pitch;
+    g.ntxa = sz.ntxa;
+    g.ntr = sz.ntr;
+    g.ntiles = sz.ntiles;
+    g.modes = p.n_modes;
+    g.ppc_x = p.ppc_x;
+    g.ppc_r = p.ppc_r;
+    g.ppc_t = p.ppc_t;
+    g.shift = shift;
+    g.cap = sz.capacity;
+    g.base = (int)(shift % sz.nxa);
+    const long long c = shift - 2;
+    g.t_lo = (int)(c >= 0 ? c / TX : -((-c + TX - 1) / TX));
+    g.dx = p.dx;
+    g.dr = p.dr;
+    g.dt = p.dt;
+    return g;
+  }
+  Plasma plasma() const {
+    Plasma pl;
+    pl.profile = p.profile;
+    pl.n0 = p.n0;
+    pl.ramp_len = p.ramp_len;
+    pl.perturb = p.perturb;
+    pl.bump_x = p.bump_x;
+    pl.bump_w = p.bump_w;
+    pl.seed = p.seed;
+    return pl;
+  }
+  Laser laser() const {
+    Laser L;
+    L.a0 = p.a0;
+    L.w0 = p.w0;
+    L.tau = p.tau;
+    L.x_c = p.x_c;
+    L.x_f = p.x_f;
+    return L;
+  }
+  int launched(const char* what) { return hip_check(hipGetLastError(), what); }
+
+  // host-built layout of a particle set sorted by tile key: offsets per key
+  // and work items of <= CHUNK particles
+  int upload_layout(int b, const std::vector<int>& counts) {
+    std::vector<int> off(sz.ntiles + 1, 0);
+    std::vector<int4> items;
+    for (int t = 0; t < sz.ntiles; ++t) {
+      off[t + 1] = off[t] + counts[t];
+      for (int k = 0; k < counts[t]; k += CHUNK) items.push_back(make_int4(t, off[t] + k, std::min(CHUNK, counts[t] - k), 0));
+    }
+    if ((int)items.size() > sz.max_items - sz.ntr) return fail(ENVPIC_ENOMEM, "work-item list overflow");
+    const int ni = (int)items.size();
+    int rc;
+    if ((rc = hip_check(hipMemcpyAsync(S.lay[b].offsets, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, stream), "upload offsets"))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(S.lay[b].cursor, off.data(), (size_t)sz.ntiles * sizeof(int), hipMemcpyHostToDevice, stream), "upload cursor"))) return rc;
+    if (ni && (rc = hip_check(hipMemcpyAsync(S.lay[b].items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, stream), "upload items"))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(S.lay[b].n_items, &ni, sizeof(int), hipMemcpyHostToDevice, stream), "upload n_items"))) return rc;
+    return hip_check(hipStreamSynchronize(stream), "layout upload");
+  }
+
+  // layout of the other buffer from the live particles of P[cur]
+  int rebuild_next_layout() {
+    const Geo g = geo();
+    launch_hist<R>(g, S.parts[cur], S.lay[cur], S.hist, sz.max_items, stream);
+    launch_scan(g, S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.err, stream);
+    return launched("hist/scan");
+  }
+
+  int init() override {
+    int rc;
+    if ((rc = hip_check(hipMemsetAsync(arena, 0, footprint_bytes(p, prec), stream), "arena clear"))) return rc;
+    const Geo g = geo();
+    // initial layout: window cells in tile-major order, ppc slots per cell
+    std::vector<int> counts(sz.ntiles, 0);
+    if (p.profile != ENVPIC_PROFILE_NONE)
+      for (int T = 0; T * TX < p.nx; ++T)
+        for (int tr = 0; tr < sz.ntr; ++tr) {
+          const int cols = std::min(TX, p.nx - T * TX), rows = std::min(TR, p.nr - tr * TR);
+          counts[(T % sz.ntxa) * sz.ntr + tr] = cols * rows * sz.ppc;
+        }
+    if ((rc = upload_layout(cur, counts))) return rc;
+    if (p.profile != ENVPIC_PROFILE_NONE) launch_init_particles<R>(g, plasma(), S.parts[cur], S.lay[cur].offsets, stream);
+    launch_init_envelope<R>(g, S.grids, laser(), fp64_rows ? 1 : 0, stream);
+    if ((rc = launched("init kernels"))) return rc;
+    if ((rc = rebuild_next_layout())) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "init"))) return rc;
+    return check_err();
+  }
+
+  int clear_deposits() override {
+    const size_t ng = sz.ngrid;
+    const size_t n1 = p.n_modes >= 2 ? ng : 0;
+    for (int b = 0; b < 2; ++b) {
+      int rc;
+      if ((rc = hip_check(hipMemsetAsync(S.dep[b].chi, 0, ng * sizeof(R), stream), "clear chi"))) return rc;
+      if ((rc = hip_check(hipMemsetAsync(S.dep[b].jx, 0, ng * sizeof(R), stream), "clear jx"))) return rc;
+      if ((rc = hip_check(hipMemsetAsync(S.dep[b].jr, 0, ng * sizeof(R), stream), "clear jr"))) return rc;
+      if (n1) {
+        if ((rc = hip_check(hipMemsetAsync(S.dep[b].jx1, 0, n1 * sizeof(C), stream), "clear jx1"))) return rc;
+        if ((rc = hip_check(hipMemsetAsync(S.dep[b].jr1, 0, n1 * sizeof(C), stream), "clear jr1"))) return rc;
+        if ((rc = hip_check(hipMemsetAsync(S.dep[b].jt1, 0, n1 * sizeof(C), stream), "clear jt1"))) return rc;
+      }
+    }
+    return hip_check(hipStreamSynchronize(stream), "clear deposits");
+  }
+
+  int check_err() override {
+    int e = 0;
+    int rc = hip_check(hipMemcpyAsync(&e, S.err, sizeof(int), hipMemcpyDeviceToHost, stream), "read error word");
+    if (rc) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
+    if (e & ERR_CAPACITY) return fail(ENVPIC_ENOMEM, "particle capacity exceeded");
+    if (e & ERR_ITEMS) return fail(ENVPIC_ENOMEM, "work-item list overflow");
+    if (e & ERR_HALO) return fail(ENVPIC_ENUMERIC, "a particle moved beyond its tile halo (non-finite or super-luminal state)");
+    return ENVPIC_OK;
+  }
+
+  int momentum(bool defer) override {
+    if (stage != 0) return fail(ENVPIC_EORDER, "momentum stage out of order");
+    const Geo g = geo();
+    const int d = (int)(n & 1);
+    launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.scr.w,
+                       S.err, sz.max_items, defer, stream);
+    cur = 1 - cur;
+    chi_last = d;
+    stage = 1;
+    deferred = defer;
+    deposit_done = !defer;
+    return launched("momentum pass");
+  }
+
+  int project(int what) override {
+    const Geo g = geo();
+    const int d = (int)(n & 1);
+    if (what == ENVPIC_CHI) {
+      if (stage != 1 || !deferred || deposit_done) return fail(ENVPIC_EORDER, "chi deposit needs a deferred momentum stage");
+      launch_deposit_chi<R>(g, S.dep[d].chi, S.parts[cur], S.lay[cur], S.scr.w, S.err, sz.max_items, stream);
+    } else if (what == ENVPIC_J) {
+      if (stage != 3 || !deferred || deposit_done) return fail(ENVPIC_EORDER, "J deposit needs a deferred position stage");
+      launch_deposit_J<R>(g, S.dep[d], S.parts[cur], S.lay[cur], shift_due() ? 1 : 0, S.scr, S.err, sz.max_items, stream);
+    } else {
+      return fail(ENVPIC_EINVAL, "project_chi_J: what must be ENVPIC_CHI or ENVPIC_J");
+    }
+    deposit_done = true;
+    return launched("deposit");
+  }
+
+  int envelope() override {
+    if (stage != 1 || !deposit_done) return fail(ENVPIC_EORDER, "envelope stage out of order");
+    const Geo g = geo();
+    launch_envelope<R>(g, S.grids, S.dep[n & 1].chi, fp64_rows ? 1 : 0, stream);
+    std::swap(S.grids.env, S.grids.envp);
+    std::swap(S.grids.ax, S.grids.axp);
+    stage = 2;
+    return launched("envelope");
+  }
+
+  int position(bool defer) override {
+    if (stage != 2) return fail(ENVPIC_EORDER, "position stage out of order");
+    const Geo g = geo();
+    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.hist, shift_due() ? 1 : 0, S.scr, S.err,
+                       sz.max_items, defer, stream);
+    stage = 3;
+    deferred = defer;
+    deposit_done = !defer;
+    return launched("position pass");
+  }
+
+  int field() override {
+    if (stage != 3 || !deposit_done) return fail(ENVPIC_EORDER, "field stage out of order");
+    launch_maxwell<R>(geo(), S.grids, S.dep[n & 1], S.dep[(n + 1) & 1], stream);
+    if (shift_due()) {
+      shift += 1;
+      const Geo g = geo();
+      launch_window<R>(g, S.grids, S.dep[0], S.dep[1], fp64_rows ? 1 : 0, stream);
+      if (p.profile != ENVPIC_PROFILE_NONE)
+        launch_inject<R>(g, plasma(), S.parts[cur], S.lay[cur], S.hist, sz.capacity, sz.max_items, S.err, stream);
+    }
+    launch_scan(geo(), S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.err, stream);
+    n += 1;
+    stage = 0;
+    return launched("field stage");
+  }
+
+  // ---------------------------------------------------------------- IO --
+  struct FieldRef {
+    void* ptr;
+    bool cplx, dual_x, dual_r;
+  };
+  int field_ref(int f, FieldRef& r) {
+    const bool m1 = p.n_modes >= 2;
+    Grids<R>& G = S.grids;
+    switch (f) {
+      case ENVPIC_F_ENV: r = {G.env, true, false, false}; return 0;
+      case ENVPIC_F_ENV_PREV: r = {G.envp, true, false, false}; return 0;
+      case ENVPIC_F_CHI: r = {S.dep[chi_last].chi, false, false, false}; return 0;
+      case ENVPIC_F_EX: r = {G.ex, false, true, false}; return 0;
+      case ENVPIC_F_ER: r = {G.er, false, false, true}; return 0;
+      case ENVPIC_F_BT: r = {G.bt, false, true, true}; return 0;
+      case ENVPIC_F_BT_BAR: r = {G.btb, false, true, true}; return 0;
+      case ENVPIC_F_JX: r = {S.dep[chi_last].jx, false, true, false}; return 0;
+      case ENVPIC_F_JR: r = {S.dep[chi_last].jr, false, false, true}; return 0;
+      default: break;
+    }
+    if (!m1 || f < ENVPIC_F_EX1 || f >= ENVPIC_NFIELDS) return fail(ENVPIC_EINVAL, "unknown field (or mode 1 not enabled)");
+    switch (f) {
+      case ENVPIC_F_EX1: r = {G.ex1, true, true, false}; return 0;
+      case ENVPIC_F_ER1: r = {G.er1, true, false, true}; return 0;
+      case ENVPIC_F_ET1: r = {G.et1, true, false, false}; return 0;
+      case ENVPIC_F_BX1: r = {G.bx1, true, false, true}; return 0;
+      case ENVPIC_F_BR1: r = {G.br1, true, true, false}; return 0;
+      case ENVPIC_F_BT1: r = {G.bt1, true, true, true}; return 0;
+      case ENVPIC_F_BX1_BAR: r = {G.bxb1, true, false, true}; return 0;
+      case ENVPIC_F_BR1_BAR: r = {G.brb1, true, true, false}; return 0;
+      case ENVPIC_F_BT1_BAR: r = {G.btb1, true, true, true}; return 0;
+      case ENVPIC_F_JX1: r = {S.dep[chi_last].jx1, true, true, false}; return 0;
+      case ENVPIC_F_JR1: r = {S.dep[chi_last].jr1, true, false, true}; return 0;
+      case ENVPIC_F_JT1: r = {S.dep[chi_last].jt1, true, false, false}; return 0;
+    }
+    return fail(ENVPIC_EINVAL, "unknown field");
+  }
+
+  int get_field(int f, double* out) override {
+    FieldRef r;
+    int rc = field_ref(f, r);
+    if (rc) return rc;
+    const int comp = r.cplx ? 2 : 1;
+    std::vector<R> buf(sz.ngrid * comp);
+    if ((rc = hip_check(hipMemcpyAsync(buf.data(), r.ptr, buf.size() * sizeof(R), hipMemcpyDeviceToHost, stream), "get_field"))) return rc;
+    std::vector<double2> ax;
+    const bool env = f == ENVPIC_F_ENV || f == ENVPIC_F_ENV_PREV;
+    if (fp64_rows && env) {
+      ax.resize((size_t)sz.nxa * 2);
+      const double2* src = f == ENVPIC_F_ENV ? S.grids.ax : S.grids.axp;
+      if ((rc = hip_check(hipMemcpyAsync(ax.data(), src, ax.size() * sizeof(double2), hipMemcpyDeviceToHost, stream), "get_field rows"))) return rc;
+    }
+    if ((rc = hip_check(hipStreamSynchronize(stream), "get_field sync"))) return rc;
+    const Geo g = geo();
+    const int nr1 = p.nr + 1;
+    for (int i = 0; i <= p.nx; ++i) {
+      const int pc = phys_col(g, i);
+      for (int j = 0; j <= p.nr; ++j) {
+        const bool valid = (!r.dual_x || i <= p.nx - 1) && (!r.dual_r || j <= p.nr - 1);
+        const size_t o = (size_t)pc * sz.pitch + j;
+        const size_t k = (size_t)i * nr1 + j;
+        if (r.cplx) {
+          double re = valid ? (double)buf[2 * o] : 0.0, im = valid ? (double)buf[2 * o + 1] : 0.0;
+          if (fp64_rows && env && j <= 1) {
+            re = ax[pc * 2 + j].x;
+            im = ax[pc * 2 + j].y;
+          }
+          out[2 * k] = re;
+          out[2 * k + 1] = im;
+        } else {
+          out[k] = valid ? (double)buf[o] : 0.0;
+        }
+      }
+    }
+    return ENVPIC_OK;
+  }
+
+  int set_field(int f, const double* in) override {
+    FieldRef r;
+    int rc = field_ref(f, r);
+    if (rc) return rc;
+    const int comp = r.cplx ? 2 : 1;
+    std::vector<R> buf(sz.ngrid * comp, (R)0);
+    if ((rc = hip_check(hipMemcpyAsync(buf.data(), r.ptr, buf.size() * sizeof(R), hipMemcpyDeviceToHost, stream), "set_field read"))) return rc;
+    const bool env = f == ENVPIC_F_ENV || f == ENVPIC_F_ENV_PREV;
+    std::vector<double2> ax;
+    double2* axdev = nullptr;
+    if (fp64_rows && env) {
+      ax.resize((size_t)sz.nxa * 2);
+      axdev = f == ENVPIC_F_ENV ? S.grids.ax : S.grids.axp;
+      if ((rc = hip_check(hipMemcpyAsync(ax.data(), axdev, ax.size() * sizeof(double2), hipMemcpyDeviceToHost, stream), "set_field rows"))) return rc;
+    }
+    if ((rc = hip_check(hipStreamSynchronize(stream), "set_field sync"))) return rc;
+    const Geo g = geo();
+    const int nr1 = p.nr + 1;
+    for (int i = 0; i <= p.nx; ++i) {
+      const int pc = phys_col(g, i);
+      for (int j = 0; j <= p.nr; ++j) {
+        const size_t o = (size_t)pc * sz.pitch + j, k = (size_t)i * nr1 + j;
+        if (r.cplx) {
+          buf[2 * o] = (R)in[2 * k];
+          buf[2 * o + 1] = (R)in[2 * k + 1];
+          if (axdev && j <= 1) ax[pc * 2 + j] = make_double2(in[2 * k], in[2 * k + 1]);
+        } else {
+          buf[o] = (R)in[k];
+        }
+      }
+    }
+    if ((rc = hip_check(hipMemcpyAsync(r.ptr, buf.data(), buf.size() * sizeof(R), hipMemcpyHostToDevice, stream), "set_field write"))) return rc;
+    if (axdev && (rc = hip_check(hipMemcpyAsync(axdev, ax.data(), ax.size() * sizeof(double2), hipMemcpyHostToDevice, stream), "set_field rows write"))) return rc;
+    return hip_check(hipStreamSynchronize(stream), "set_field sync");
+  }
+
+  // slots of P[cur] covered by work items
+  int used_slots(int& used) {
+    int ni = 0;
+    int rc = hip_check(hipMemcpyAsync(&ni, S.lay[cur].n_items, sizeof(int), hipMemcpyDeviceToHost, stream), "n_items");
+    if (rc) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
+    std::vector<int4> items(ni);
+    if (ni && (rc = hip_check(hipMemcpyAsync(items.data(), S.lay[cur].items, ni * sizeof(int4), hipMemcpyDeviceToHost, stream), "items"))) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
+    used = 0;
+    for (const int4& it : items) used = std::max(used, it.y + it.z);
+    return ENVPIC_OK;
+  }
+
+  int get_particles(std::vector<double>* cols, std::vector<uint32_t>* ids) override {
+    int used = 0;
+    int rc = used_slots(used);
+    if (rc) return rc;
+    const Parts<R>& P = S.parts[cur];
+    std::vector<unsigned> cell(used);
+    std::vector<R> a[7];
+    const R* src[7] = {P.fx, P.fr, P.th, P.px, P.py, P.pz, P.w};
+    std::vector<uint32_t> id(used);
+    if (used) {
+      if ((rc = hip_check(hipMemcpyAsync(cell.data(), P.cell, used * sizeof(unsigned), hipMemcpyDeviceToHost, stream), "cell"))) return rc;
+      for (int k = 0; k < 7; ++k) {
+        a[k].resize(used);
+        if ((rc = hip_check(hipMemcpyAsync(a[k].data(), src[k], used * sizeof(R), hipMemcpyDeviceToHost, stream), "parts"))) return rc;
+      }
+      if ((rc = hip_check(hipMemcpyAsync(id.data(), P.id, used * sizeof(uint32_t), hipMemcpyDeviceToHost, stream), "id"))) return rc;
+    }
+    if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
+    std::vector<int> order;
+    for (int k = 0; k < used; ++k)
+      if (cell[k] != kDead) order.push_back(k);
+    std::sort(order.begin(), order.end(), [&](int u, int v) { return id[u] < id[v]; });
+    for (int c = 0; c < 7; ++c) cols[c].resize(order.size());
+    ids->resize(order.size());
+    for (size_t m = 0; m < order.size(); ++m) {
+      const int k = order[m];
+      const double r = ((double)cell_jr(cell[k]) + (double)a[1][k]) * p.dr;
+      const double th = (double)a[2][k];
+      cols[0][m] = ((double)cell_ix(cell[k]) + (double)a[0][k]) * p.dx;
+      cols[1][m] = r * std::cos(th);
+      cols[2][m] = r * std::sin(th);
+      for (int c = 3; c < 7; ++c) cols[c][m] = (double)a[c][k];
+      (*ids)[m] = id[k];
+    }
+    return ENVPIC_OK;
+  }
+
+  int set_particles(int64_t np, const double* const* in, const uint32_t* id) override {
+    if (stage != 0) return fail(ENVPIC_EORDER, "set_particles only between steps");
+    if (np < 0 || np + (long long)p.nr * sz.ppc > sz.capacity) return fail(ENVPIC_ENOMEM, "too many particles for the capacity");
+    const Geo g = geo();
+    const double rmax = p.nr * p.dr;
+    std::vector<int> key(np), counts(sz.ntiles, 0);
+    std::vector<int> ixv(np), jrv(np);
+    std::vector<double> fxv(np), frv(np), thv(np);
+    for (int64_t k = 0; k < np; ++k) {
+      const double u = in[0][k] / p.dx;
+      const double c = std::floor(u);
+      const double r = std::sqrt(in[1][k] * in[1][k] + in[2][k] * in[2][k]);
+      if (!(c >= (double)shift && c < (double)(shift + p.nx)) || !(r <= rmax))
+        return fail(ENVPIC_EINVAL, "particle outside the window or beyond r_max");
+      ixv[k] = (int)c;
+      fxv[k] = u - c;
+      const double ur = r / p.dr;
+      int jr = (int)std::floor(ur);
+      if (jr > p.nr - 1) jr = p.nr - 1;
+      jrv[k] = jr;
+      frv[k] = ur - jr;
+      thv[k] = std::atan2(in[2][k], in[1][k]);
+      key[k] = tile_key(g, ixv[k], jr);
+      counts[key[k]]++;
+    }
+    std::vector<int> off(sz.ntiles + 1, 0);
+    for (int t = 0; t < sz.ntiles; ++t) off[t + 1] = off[t] + counts[t];
+    std::vector<int> pos(off.begin(), off.end() - 1);
+    std::vector<unsigned> hcell(np);
+    std::vector<R> h[7];
+    for (int c = 0; c < 7; ++c) h[c].resize(np);
+    std::vector<uint32_t> hid(np);
+    for (int64_t k = 0; k < np; ++k) {
+      const int d = pos[key[k]]++;
+      int ix = ixv[k], jr = jrv[k];
+      R fx = (R)fxv[k], fr = (R)frv[k];
+      if (fx >= (R)1) fx = (R)0, ix += 1;  // rounding of the offsets
+      if (fr > (R)1) fr = (R)1;
+      hcell[d] = pack_cell(ix, jr);
+      h[0][d] = fx;
+      h[1][d] = fr;
+      h[2][d] = (R)thv[k];
+      for (int c = 3; c < 7; ++c) h[c][d] = (R)in[c][k];
+      hid[d] = id[k];
+    }
+    int rc;
+    if ((rc = upload_layout(cur, counts))) return rc;
+    Parts<R>& P = S.parts[cur];
+    R* dst[7] = {P.fx, P.fr, P.th, P.px, P.py, P.pz, P.w};
+    if (np) {
+      if ((rc = hip_check(hipMemcpyAsync(P.cell, hcell.data(), np * sizeof(unsigned), hipMemcpyHostToDevice, stream), "cell"))) return rc;
+      for (int c = 0; c < 7; ++c)
+        if ((rc = hip_check(hipMemcpyAsync(dst[c], h[c].data(), np * sizeof(R), hipMemcpyHostToDevice, stream), "parts"))) return rc;
+      if ((rc = hip_check(hipMemcpyAsync(P.id, hid.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, stream), "id"))) return rc;
+    }
+    if ((rc = rebuild_next_layout())) return rc;
+    return hip_check(hipStreamSynchronize(stream), "set_particles");
+  }
+
+  int diagnostics(double* out) override {
+    const Geo g = geo();
+    launch_diag<R>(g, S.parts[cur], S.lay[cur], sz.max_items, S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0,
+                   S.diag_scratch, S.diag_out, stream);
+    int rc = launched("diagnostics");
+    if (rc) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(out, S.diag_out, ENVPIC_NDIAG * sizeof(double), hipMemcpyDeviceToHost, stream), "diag read"))) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "diag sync"))) return rc;
+    return check_err();
+  }
+
+  int poison(int f) override {
+    std::vector<double> buf;
+    FieldRef r;
+    int rc = field_ref(f, r);
+    if (rc) return rc;
+    buf.resize((size_t)(p.nx + 1) * (p.nr + 1) * (r.cplx ? 2 : 1));
+    if ((rc = get_field(f, buf.data()))) return rc;
+    const size_t k = (size_t)(p.nx / 2) * (p.nr + 1) + p.nr / 2;
+    buf[r.cplx ? 2 * k : k] = std::nan("");
+    return set_field(f, buf.data());
+  }
+};
+
+template <class R>
+int create(const envpic_params* p, int prec, void* arena, size_t bytes, void* stream, envpic_sim** out) {
+  SimT<R>* s = new (std::nothrow) SimT<R>();
+  if (!s) return fail(ENVPIC_ENOMEM, "host allocation failed");
+  s->p = *p;
+  s->prec = prec;
+  s->stream = (hipStream_t)stream;
+  s->sz = sizes_of(*p);
+  s->fp64_rows = (prec == ENVPIC_FP32_BULK);
+  s->arena = (char*)arena;
+  plan<R>(*p, s->sz, s->fp64_rows, (char*)arena, &s->S);
+  int rc = s->init();
+  if (rc) {
+    delete s;
+    return rc;
+  }
+  *out = s;
+  return ENVPIC_OK;
+}
+
+}  // namespace
+
+// ============================================================== C ABI ==
+extern "C" {
+
+void envpic_params_default(envpic_params* p, int preset) {
+  if (!p) return;
+  std::memset(p, 0, sizeof *p);
+  p->size = sizeof(envpic_params);
+  p->version = ENVPIC_PARAMS_VERSION;
+  p->dx = 0.8;
+  p->dr = 1.5;
+  p->dt = 0.6;
+  p->n_modes = 1;
+  p->ppc_x = 2;
+  p->ppc_r = 2;
+  p->ppc_t = 1;
+  p->seed = 191204674ull + (uint64_t)preset;
+  p->w0 = 1.0;
+  p->tau = 1.0;
+  p->bump_w = 1.0;
+  switch (preset) {
+    case 1:  // mode-0 parity case
+      p->nx = 256; p->nr = 32; p->profile = ENVPIC_PROFILE_UNIFORM; p->n0 = 0.002;
+      p->a0 = 1.0; p->w0 = 20.0; p->tau = 30.0; p->x_c = p->x_f = 102.4;
+      break;
+    case 2:  // LWFA-shaped run with a moving window
+      p->nx = 2048; p->nr = 256; p->n_modes = 2; p->ppc_t = 4; p->profile = ENVPIC_PROFILE_RAMP;
+      p->n0 = 0.0017; p->ramp_len = 200.0; p->a0 = 2.0; p->w0 = 100.0; p->tau = 60.0;
+      p->x_c = p->x_f = 2048 * 0.8 - 180.0; p->moving_window = 1;
+      break;
+    case 3:  // bandwidth case
+      p->nx = 4096; p->nr = 512; p->n_modes = 2; p->ppc_t = 4; p->profile = ENVPIC_PROFILE_PERTURB;
+      p->n0 = 0.001; p->perturb = 0.01; p->a0 = 2.5; p->w0 = 150.0; p->tau = 80.0;
+      p->x_c = p->x_f = 4096 * 0.8 / 2;
+      break;
+    case 4:  // largest scan-job shape
+      p->nx = 2048; p->nr = 256; p->ppc_t = 2; p->profile = ENVPIC_PROFILE_UNIFORM; p->n0 = 0.0025;
+      p->a0 = 1.75; p->w0 = 80.0; p->tau = 30.0; p->x_c = p->x_f = 2048 * 0.8 - 90.0; p->moving_window = 1;
+      break;
+    case 5:  // scale case
+      p->nx = 8192; p->nr = 768; p->n_modes = 2; p->ppc_t = 6; p->profile = ENVPIC_PROFILE_BUMP;
+      p->n0 = 0.0015; p->bump_x = 8192 * 0.8 + 400.0; p->bump_w = 100.0; p->a0 = 3.0; p->w0 = 200.0;
+      p->tau = 90.0; p->x_c = p->x_f = 8192 * 0.8 - 270.0; p->moving_window = 1;
+      break;
+    default:  // small vacuum grid
+      p->nx = 64; p->nr = 16; p->profile = ENVPIC_PROFILE_NONE;
+      break;
+  }
+}
+
+int envpic_footprint(const envpic_params* p, int precision, size_t* bytes) {
+  int rc = validate(p);
+  if (rc) return rc;
+  if (precision != ENVPIC_FP32_BULK && precision != ENVPIC_FP64) return fail(ENVPIC_EINVAL, "unknown precision");
+  if (!bytes) return fail(ENVPIC_EINVAL, "bytes is NULL");
+  *bytes = footprint_bytes(*p, precision);
+  return ENVPIC_OK;
+}
+
+int envpic_sim_init(const envpic_params* p, int precision, void* dev_arena, size_t arena_bytes, void* hip_stream,
+                    envpic_sim** out) {
+  size_t need = 0;
+  int rc = envpic_footprint(p, precision, &need);
+  if (rc) return rc;
+  if (!out || !dev_arena) return fail(ENVPIC_EINVAL, "NULL arena or output handle");
+  if (((uintptr_t)dev_arena & 255) != 0) return fail(ENVPIC_EINVAL, "arena must be 256-byte aligned");
+  if (arena_bytes < need) {
+    char buf[128];
+    std::snprintf(buf, sizeof buf, "arena of %zu bytes is smaller than the footprint %zu", arena_bytes, need);
+    return fail(ENVPIC_ENOMEM, buf);
+  }
+  if (precision == ENVPIC_FP64) return create<double>(p, precision, dev_arena, arena_bytes, hip_stream, out);
+  return create<float>(p, precision, dev_arena, arena_bytes, hip_stream, out);
+}
+
+int envpic_gather_push(envpic_sim* s, int stage) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  const bool defer = (stage & ENVPIC_DEFER_DEPOSIT) != 0;
+  stage &= ~ENVPIC_DEFER_DEPOSIT;
+  if (stage == ENVPIC_MOMENTUM) return s->momentum(defer);
+  if (stage == ENVPIC_POSITION) return s->position(defer);
+  return fail(ENVPIC_EINVAL, "stage must be ENVPIC_MOMENTUM or ENVPIC_POSITION");
+}
+
+int envpic_envelope_step(envpic_sim* s) { return s ? s->envelope() : fail(ENVPIC_EINVAL, "NULL sim"); }
+int envpic_project_chi_J(envpic_sim* s, int what) { return s ? s->project(what) : fail(ENVPIC_EINVAL, "NULL sim"); }
+int envpic_field_step(envpic_sim* s) { return s ? s->field() : fail(ENVPIC_EINVAL, "NULL sim"); }
+
+int envpic_step_n(envpic_sim* s, int nsteps) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  if (s->stage != 0) return fail(ENVPIC_EORDER, "step_n called in the middle of a step");
+  for (int k = 0; k < nsteps; ++k) {
+    int rc = s->step();
+    if (rc) return rc;
+  }
+  return ENVPIC_OK;
+}
+
+int envpic_batch_step(envpic_sim* const* sims, int count, int nsteps, void* hip_stream) {
+  if (count < 0 || (count > 0 && !sims)) return fail(ENVPIC_EINVAL, "bad simulation list");
+  for (int k = 0; k < count; ++k)
+    if (!sims[k] || sims[k]->stage != 0) return fail(ENVPIC_EORDER, "batch_step needs every simulation between steps");
+  // interleave: step k of every simulation before step k+1 of any, each on
+  // its own stream so that the kernels of different simulations overlap
+  for (int st = 0; st < nsteps; ++st)
+    for (int k = 0; k < count; ++k) {
+      int rc = sims[k]->step();
+      if (rc) return rc;
+    }
+  hipStream_t join = (hipStream_t)hip_stream;
+  for (int k = 0; k < count; ++k) {
+    if (sims[k]->stream == join) continue;
+    hipEvent_t ev;
+    int rc = hip_check(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "event");
+    if (rc) return rc;
+    if ((rc = hip_check(hipEventRecord(ev, sims[k]->stream), "event record"))) return rc;
+    if ((rc = hip_check(hipStreamWaitEvent(join, ev, 0), "stream wait"))) return rc;
+    if ((rc = hip_check(hipEventDestroy(ev), "event destroy"))) return rc;
+  }
+  return hip_check(hipGetLastError(), "batch_step");
+}
+
+int envpic_get_field(const envpic_sim* s, int field, double* out) {
+  if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
+  return const_cast<envpic_sim*>(s)->get_field(field, out);
+}
+int envpic_set_field(envpic_sim* s, int field, const double* in) {
+  if (!s || !in) return fail(ENVPIC_EINVAL, "NULL argument");
+  return s->set_field(field, in);
+}
+
+int envpic_state(const envpic_sim* s, int64_t* n, int64_t* shift, int64_t* n_particles) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  if (n) *n = s->n;
+  if (shift) *shift = s->shift;
+  if (n_particles) {
+    double d[ENVPIC_NDIAG];
+    int rc = const_cast<envpic_sim*>(s)->diagnostics(d);
+    if (rc) return rc;
+    *n_particles = (int64_t)d[ENVPIC_D_COUNT];
+  }
+  return ENVPIC_OK;
+}
+
+int envpic_get_particles(const envpic_sim* s, double* x, double* y, double* z, double* px, double* py, double* pz,
+                         double* w, uint32_t* id) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  std::vector<double> cols[7];
+  std::vector<uint32_t> ids;
+  int rc = const_cast<envpic_sim*>(s)->get_particles(cols, &ids);
+  if (rc) return rc;
+  double* outs[7] = {x, y, z, px, py, pz, w};
+  for (int c = 0; c < 7; ++c)
+    if (outs[c] && !cols[c].empty()) std::memcpy(outs[c], cols[c].data(), cols[c].size() * sizeof(double));
+  if (id && !ids.empty()) std::memcpy(id, ids.data(), ids.size() * sizeof(uint32_t));
+  return ENVPIC_OK;
+}
+
+int envpic_set_particles(envpic_sim* s, int64_t n, const double* x, const double* y, const double* z,
+                         const double* px, const double* py, const double* pz, const double* w, const uint32_t* id) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  if (n > 0 && (!x || !y || !z || !px || !py || !pz || !w || !id)) return fail(ENVPIC_EINVAL, "NULL particle array");
+  const double* cols[7] = {x, y, z, px, py, pz, w};
+  return s->set_particles(n, cols, id);
+}
+
+int envpic_diagnostics(const envpic_sim* s, double* out) {
+  if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
+  return const_cast<envpic_sim*>(s)->diagnostics(out);
+}
+
+// checkpoint blob: header, the persistent grids (FP64, window-relative),
+// particles (FP64 columns ordered by id)
+namespace {
+struct BlobHeader {
+  char magic[8];
+  int32_t version, prec, nx, nr, modes, nfields;
+  int64_t n, shift, nparticles;
+  envpic_params params;
+};
+const int kCkptFields[] = {ENVPIC_F_ENV, ENVPIC_F_ENV_PREV, ENVPIC_F_EX, ENVPIC_F_ER, ENVPIC_F_BT, ENVPIC_F_BT_BAR,
+                           ENVPIC_F_EX1, ENVPIC_F_ER1, ENVPIC_F_ET1, ENVPIC_F_BX1, ENVPIC_F_BR1, ENVPIC_F_BT1,
+                           ENVPIC_F_BX1_BAR, ENVPIC_F_BR1_BAR, ENVPIC_F_BT1_BAR};
+int n_ckpt_fields(const envpic_params& p) { return p.n_modes >= 2 ? 15 : 6; }
+size_t field_doubles(const envpic_params& p, int f) {
+  const bool c = f == ENVPIC_F_ENV || f == ENVPIC_F_ENV_PREV || f >= ENVPIC_F_EX1;
+  return (size_t)(p.nx + 1) * (p.nr + 1) * (c ? 2 : 1);
+}
+}  // namespace
+
+int envpic_save(const envpic_sim* cs, void* blob, size_t* bytes) {
+  envpic_sim* s = const_cast<envpic_sim*>(cs);
+  if (!s || !bytes) return fail(ENVPIC_EINVAL, "NULL argument");
+  if (s->stage != 0) return fail(ENVPIC_EORDER, "save only between steps");
+  std::vector<double> cols[7];
+  std::vector<uint32_t> ids;
+  int rc = s->get_particles(cols, &ids);
+  if (rc) return rc;
+  size_t need = sizeof(BlobHeader);
+  for (int k = 0; k < n_ckpt_fields(s->p); ++k) need += field_doubles(s->p, kCkptFields[k]) * sizeof(double);
+  need += ids.size() * (7 * sizeof(double) + sizeof(uint32_t));
+  if (!blob) {
+    *bytes = need;
+    return ENVPIC_OK;
+  }
+  if (*bytes < need) return fail(ENVPIC_ENOMEM, "checkpoint buffer too small");
+  char* q = (char*)blob;
+  BlobHeader h{};
+  std::memcpy(h.magic, "ENVPIC01", 8);
+  h.version = 1;
+  h.prec = s->prec;
+  h.nx = s->p.nx;
+  h.nr = s->p.nr;
+  h.modes = s->p.n_modes;
+  h.nfields = n_ckpt_fields(s->p);
+  h.n = s->n;
+  h.shift = s->shift;
+  h.nparticles = (int64_t)ids.size();
+  h.params = s->p;
+  std::memcpy(q, &h, sizeof h);
+  q += sizeof h;
+  for (int k = 0; k < h.nfields; ++k) {
+    if ((rc = s->get_field(kCkptFields[k], (double*)q))) return rc;
+    q += field_doubles(s->p, kCkptFields[k]) * sizeof(double);
+  }
+  for (int c = 0; c < 7; ++c) {
+    if (!ids.empty()) std::memcpy(q, cols[c].data(), ids.size() * sizeof(double));
+    q += ids.size() * sizeof(double);
+  }
+  if (!ids.empty()) std::memcpy(q, ids.data(), ids.size() * sizeof(uint32_t));
+  *bytes = need;
+  return ENVPIC_OK;
+}
+
+int envpic_load(envpic_sim* s, const void* blob, size_t bytes) {
+  if (!s || !blob) return fail(ENVPIC_EINVAL, "NULL argument");
+  if (s->stage != 0) return fail(ENVPIC_EORDER, "load only between steps");
+  if (bytes < sizeof(BlobHeader)) return fail(ENVPIC_EINVAL, "checkpoint too short");
+  BlobHeader h;
+  std::memcpy(&h, blob, sizeof h);
+  if (std::memcmp(h.magic, "ENVPIC01", 8) != 0 || h.prec != s->prec || h.nx != s->p.nx || h.nr != s->p.nr ||
+      h.modes != s->p.n_modes)
+    return fail(ENVPIC_EINVAL, "checkpoint does not match this simulation");
+  const char* q = (const char*)blob + sizeof h;
+  size_t need = sizeof h;
+  for (int k = 0; k < h.nfields; ++k) need += field_doubles(s->p, kCkptFields[k]) * sizeof(double);
+  need += (size_t)h.nparticles * (7 * sizeof(double) + sizeof(uint32_t));
+  if (bytes < need) return fail(ENVPIC_EINVAL, "checkpoint truncated");
+  // step counter and window first: the IO below is window-relative
+  s->n = h.n;
+  s->shift = h.shift;
+  s->chi_last = (int)((h.n + 1) & 1);
+  int rc;
+  if ((rc = s->clear_deposits())) return rc;
+  for (int k = 0; k < h.nfields; ++k) {
+    if ((rc = s->set_field(kCkptFields[k], (const double*)q))) return rc;
+    q += field_doubles(s->p, kCkptFields[k]) * sizeof(double);
+  }
+  const double* cols[7];
+  for (int c = 0; c < 7; ++c) {
+    cols[c] = (const double*)q;
+    q += (size_t)h.nparticles * sizeof(double);
+  }
+  return s->set_particles(h.nparticles, cols, (const uint32_t*)q);
+}
+
+int envpic_debug_poison(envpic_sim* s, int field) { return s ? s->poison(field) : fail(ENVPIC_EINVAL, "NULL sim"); }
+
+void envpic_sim_destroy(envpic_sim* s) { delete s; }
+
+const char* envpic_last_error(const envpic_sim*) { return g_last_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,350 @@
+// grid.hip -- grid kernels of the cylindrical envelope PIC step
+// (arXiv:1912.04674): the explicit envelope update (Sec. 3, Eq.
+// envelope_solver with the cylindrical Laplacian), the Yee/FDTD update of the
+// low-frequency fields (Sec. 2, Eq. MaxwellEqsCylindrical; Sec. 3), the
+// moving-window column reset and the initial envelope.
+//
+// One thread per window node (i, j), radius fastest, so a wavefront reads a
+// contiguous run of one column; columns live in a ring indexed by lab column
+// mod nxa.  All kernels are bound by HBM bandwidth (a few flops per byte).
+#include "common.hpp"
+#include "cplx.hpp"
+#include "launch.hpp"
+
+namespace envpic {
+
+// -------------------------------------------------------------- envelope --
+// A^{n+1} = (1 + i dt)/(1 + dt^2) [2 A^n - (1 + i dt) A^{n-1}
+//            + dt^2 (lap A^n - chi^n A^n + 2i (A_{i+1} - A_{i-1})/(2 dx))]
+// radial Laplacian: 5-point form with (1/r_j)(A_{j+1} - A_{j-1})/(2 dr) for
+// j >= 1, and its on-axis limit 4 (A_1 - A_0)/dr^2 at j = 0.  Dirichlet at
+// the x ends and at r_max.  A^{n+1} overwrites A^{n-1} in place.  With
+// fp64_rows the rows j = 0, 1 are advanced in FP64 from their own FP64
+// copies and rounded into the FP32 bulk array for the gathers.
+template <class R>
+__global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp64_rows) {
+  using C = typename cplx_of<R>::type;
+  const int nr1 = g.nr + 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(g.nx + 1) * nr1) return;
+  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
+  const int pc = phys_col(g, i);
+  const size_t o = (size_t)pc * g.pitch + j;
+  const bool rows64 = fp64_rows && j <= 1;
+  if (i == 0 || i == g.nx || j == g.nr) {
+    f.envp[o] = mk<C>((R)0, (R)0);
+    if (rows64) f.axp[pc * 2 + j] = make_double2(0.0, 0.0);
+    return;
+  }
+  const int pp = phys_col(g, i + 1), pm = phys_col(g, i - 1);
+  const double dt = g.dt;
+  const double pre_r = 1.0 / (1.0 + dt * dt), pre_i = dt / (1.0 + dt * dt);
+  if (rows64) {
+    const double2 a = f.ax[pc * 2 + j], aip = f.ax[pp * 2 + j], aim = f.ax[pm * 2 + j];
+    const double idx2 = 1.0 / (g.dx * g.dx), idr2 = 1.0 / (g.dr * g.dr);
+    double2 lap = make_double2((aip.x - 2.0 * a.x + aim.x) * idx2, (aip.y - 2.0 * a.y + aim.y) * idx2);
+    if (j == 0) {
+      const double2 up = f.ax[pc * 2 + 1];
+      lap.x += 4.0 * (up.x - a.x) * idr2;
+      lap.y += 4.0 * (up.y - a.y) * idr2;
+    } else {
+      const C u = f.env[o + 1];
+      const double2 up = make_double2((double)u.x, (double)u.y), dn = f.ax[pc * 2 + 0];
+      const double ir = 1.0 / (2.0 * g.dr * g.dr);  // 1/(2 r_1 dr), r_1 = dr
+      lap.x += (up.x - 2.0 * a.x + dn.x) * idr2 + (up.x - dn.x) * ir;
+      lap.y += (up.y - 2.0 * a.y + dn.y) * idr2 + (up.y - dn.y) * ir;
+    }
+    const double ch = (double)chi[o];
+    const double i2dx = 1.0 / g.dx;  // 2i (d)/(2 dx) = i d / dx
+    const double rr = lap.x - ch * a.x - (aip.y - aim.y) * i2dx;
+    const double ri = lap.y - ch * a.y + (aip.x - aim.x) * i2dx;
+    const double2 ap = f.axp[pc * 2 + j];
+    const double br = 2.0 * a.x - (ap.x - dt * ap.y) + dt * dt * rr;
+    const double bi = 2.0 * a.y - (ap.y + dt * ap.x) + dt * dt * ri;
+    const double2 an = make_double2(pre_r * br - pre_i * bi, pre_r * bi + pre_i * br);
+    f.axp[pc * 2 + j] = an;
+    f.envp[o] = mk<C>((R)an.x, (R)an.y);
+    return;
+  }
+  const R rdt = (R)dt;
+  const C a = f.env[o], aip = f.env[(size_t)pp * g.pitch + j], aim = f.env[(size_t)pm * g.pitch + j];
+  const R idx2 = (R)(1.0 / (g.dx * g.dx)), idr2 = (R)(1.0 / (g.dr * g.dr));
+  R lx = (aip.x - (R)2 * a.x + aim.x) * idx2, ly = (aip.y - (R)2 * a.y + aim.y) * idx2;
+  const C up = f.env[o + 1];
+  if (j == 0) {
+    lx += (R)4 * (up.x - a.x) * idr2;
+    ly += (R)4 * (up.y - a.y) * idr2;
+  } else {
+    const C dn = f.env[o - 1];
+    const R ir = (R)(1.0 / (2.0 * j * g.dr * g.dr));
+    lx += (up.x - (R)2 * a.x + dn.x) * idr2 + (up.x - dn.x) * ir;
+    ly += (up.y - (R)2 * a.y + dn.y) * idr2 + (up.y - dn.y) * ir;
+  }
+  const R ch = chi[o];
+  const R i2dx = (R)(1.0 / g.dx);
+  const R rr = lx - ch * a.x - (aip.y - aim.y) * i2dx;
+  const R ri = ly - ch * a.y + (aip.x - aim.x) * i2dx;
+  const C ap = f.envp[o];
+  const R br = (R)2 * a.x - (ap.x - rdt * ap.y) + rdt * rdt * rr;
+  const R bi = (R)2 * a.y - (ap.y + rdt * ap.x) + rdt * rdt * ri;
+  f.envp[o] = mk<C>((R)pre_r * br - (R)pre_i * bi, (R)pre_r * bi + (R)pre_i * br);
+}
+
+// ----------------------------------------------------- Ampere: E^{n+1} --
+// E_r(i, j+1/2) -= dt [(B_t(i+1/2) - B_t(i-1/2))/dx + J_r];   E_r = 0 at x ends
+// E_x(i+1/2, j) += dt [(r_{j+1/2} B_t(j+1/2) - r_{j-1/2} B_t(j-1/2))/(r_j dr) - J_x]
+//   axis: (1/r) d(r B_t)/dr -> 4 B_t(1/2)/dr (flux through the disc r < dr/2);
+//   E_x = 0 at r_max (perfect conductor).
+// Mode 1: d/dtheta -> -i (F = Re[F_1 e^{-i theta}]); axial components vanish
+// on the axis, E_t there from the odd ghost B_x(-1/2) = -B_x(1/2).
+// The deposits for the next step (chi, J) are cleared here.
+template <class R, bool M1>
+__global__ void k_maxwell_E(Geo g, Grids<R> f, DepositBufs<R> din, DepositBufs<R> dnext) {
+  using C = typename cplx_of<R>::type;
+  const int nr1 = g.nr + 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(g.nx + 1) * nr1) return;
+  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
+  const int pc = phys_col(g, i);
+  const size_t o = (size_t)pc * g.pitch + j;
+  const size_t om = i > 0 ? (size_t)phys_col(g, i - 1) * g.pitch + j : o;
+  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  const bool xin = i > 0 && i < g.nx;
+  if (j <= g.nr - 1) {
+    f.er[o] = xin ? f.er[o] - dt * ((f.bt[o] - f.bt[om]) * idx_ + din.jr[o]) : (R)0;
+  }
+  if (i <= g.nx - 1) {
+    R e;
+    if (j == g.nr) {
+      e = 0;
+    } else if (j == 0) {
+      e = f.ex[o] + dt * ((R)4 * f.bt[o] * idr - din.jx[o]);
+    } else {
+      e = f.ex[o] + dt * (((R)(j + 0.5) * f.bt[o] - (R)(j - 0.5) * f.bt[o - 1]) * ((R)(1.0 / j) * idr) - din.jx[o]);
+    }
+    f.ex[o] = e;
+  }
+  if (M1) {
+    const C z = mk<C>((R)0, (R)0);
+    if (i <= g.nx - 1) {
+      C e = z;
+      if (j >= 1 && j <= g.nr - 1) {
+        const R irj = (R)(1.0 / (j * g.dr));
+        const C curl = cadd(cscale(csub(cscale(f.bt1[o], (R)(j + 0.5)), cscale(f.bt1[o - 1], (R)(j - 0.5))), irj),
+                            cscale(cmuli(f.br1[o]), irj));
+        e = cadd(f.ex1[o], cscale(csub(curl, din.jx1[o]), dt));
+      }
+      f.ex1[o] = e;
+    }
+    if (j <= g.nr - 1) {
+      C e = z;
+      if (xin) {
+        const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+        const C curl = csub(cscale(cmuli(f.bx1[o]), -irh), cscale(csub(f.bt1[o], f.bt1[om]), idx_));
+        e = cadd(f.er1[o], cscale(csub(curl, din.jr1[o]), dt));
+      }
+      f.er1[o] = e;
+    }
+    {
+      C e = z;
+      if (xin && j <= g.nr - 1) {
+        const C dbr = cscale(csub(f.br1[o], f.br1[om]), idx_);
+        const C dbx = j == 0 ? cscale(f.bx1[o], (R)2 * idr) : cscale(csub(f.bx1[o], f.bx1[o - 1]), idr);
+        e = cadd(f.et1[o], cscale(csub(csub(dbr, dbx), din.jt1[o]), dt));
+      }
+      f.et1[o] = e;
+    }
+  }
+  dnext.chi[o] = 0;
+  dnext.jx[o] = 0;
+  dnext.jr[o] = 0;
+  if (M1) {
+    const C z = mk<C>((R)0, (R)0);
+    dnext.jx1[o] = z;
+    dnext.jr1[o] = z;
+    dnext.jt1[o] = z;
+  }
+}
+
+// ---------------------------------------------- Faraday: B^{n+3/2}, Bbar --
+// B_t(i+1/2, j+1/2) += dt [(E_x(j+1) - E_x(j))/dr - (E_r(i+1) - E_r(i))/dx]
+// Bbar^{n+1} = (B^{n+1/2} + B^{n+3/2}) / 2
+template <class R, bool M1>
+__global__ void k_maxwell_B(Geo g, Grids<R> f) {
+  using C = typename cplx_of<R>::type;
+  const int nr1 = g.nr + 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(g.nx + 1) * nr1) return;
+  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
+  const int pc = phys_col(g, i);
+  const size_t o = (size_t)pc * g.pitch + j;
+  const size_t op = i < g.nx ? (size_t)phys_col(g, i + 1) * g.pitch + j : o;
+  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  if (i <= g.nx - 1 && j <= g.nr - 1) {
+    const R b0 = f.bt[o];
+    const R b1 = b0 + dt * ((f.ex[o + 1] - f.ex[o]) * idr - (f.er[op] - f.er[o]) * idx_);
+    f.bt[o] = b1;
+    f.btb[o] = (R)0.5 * (b0 + b1);
+  }
+  if (M1) {
+    if (j <= g.nr - 1) {
+      // B_x(i, j+1/2) -= dt [((j+1) E_t(j+1) - j E_t(j))/((j+1/2) dr) + (i/r_{j+1/2}) E_r]
+      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+      const C b0 = f.bx1[o];
+      const C curl = cadd(cscale(csub(cscale(f.et1[o + 1], (R)(j + 1)), cscale(f.et1[o], (R)j)), irh),
+                          cscale(cmuli(f.er1[o]), irh));
+      const C b1 = csub(b0, cscale(curl, dt));
+      f.bx1[o] = b1;
+      f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
+    }
+    if (i <= g.nx - 1) {
+      // B_r(i+1/2, j) += dt [(i/r) E_x + (E_t(i+1) - E_t(i))/dx]; on the axis E_x/r -> E_x(1)/dr
+      const C exr = j == 0 ? cscale(f.ex1[o + 1], idr) : cscale(f.ex1[o], (R)(1.0 / (j * g.dr)));
+      const C b0 = f.br1[o];
+      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(f.et1[op], f.et1[o]), idx_)), dt));
+      f.br1[o] = b1;
+      f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
+      if (j <= g.nr - 1) {
+        const C c0 = f.bt1[o];
+        const C c1 = cadd(c0, cscale(csub(cscale(csub(f.ex1[o + 1], f.ex1[o]), idr),
+                                          cscale(csub(f.er1[op], f.er1[o]), idx_)), dt));
+        f.bt1[o] = c1;
+        f.btb1[o] = cscale(cadd(c0, c1), (R)0.5);
+      }
+    }
+  }
+}
+
+// ----------------------------------------------------- window shift --
+// After the shift (g holds the new shift): the primal column entering at the
+// right (rel = nx) and the half-shifted column entering (rel = nx - 1) start
+// at zero, and the new left edge (rel = 0) takes its boundary values.
+template <class R, bool M1>
+__global__ void k_window(Geo g, Grids<R> f, DepositBufs<R> d0, DepositBufs<R> d1, int fp64_rows) {
+  using C = typename cplx_of<R>::type;
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j > g.nr) return;
+  const C z = mk<C>((R)0, (R)0);
+  const int pn = phys_col(g, g.nx), pd = phys_col(g, g.nx - 1), pl = phys_col(g, 0);
+  const size_t on = (size_t)pn * g.pitch + j, od = (size_t)pd * g.pitch + j, ol = (size_t)pl * g.pitch + j;
+  // primal-x grids at the entering column
+  f.env[on] = z;
+  f.envp[on] = z;
+  f.er[on] = 0;
+  d0.chi[on] = 0; d1.chi[on] = 0;
+  d0.jr[on] = 0; d1.jr[on] = 0;
+  // half-shifted-x grids at the entering column
+  f.ex[od] = 0;
+  f.bt[od] = 0;
+  f.btb[od] = 0;
+  d0.jx[od] = 0; d1.jx[od] = 0;
+  // boundary values at the new left edge
+  f.env[ol] = z;
+  f.envp[ol] = z;
+  f.er[ol] = 0;
+  if (fp64_rows && j <= 1) {
+    f.ax[pn * 2 + j] = make_double2(0.0, 0.0);
+    f.axp[pn * 2 + j] = make_double2(0.0, 0.0);
+    f.ax[pl * 2 + j] = make_double2(0.0, 0.0);
+    f.axp[pl * 2 + j] = make_double2(0.0, 0.0);
+  }
+  if (M1) {
+    f.er1[on] = z; f.et1[on] = z; f.bx1[on] = z; f.bxb1[on] = z;
+    d0.jr1[on] = z; d1.jr1[on] = z; d0.jt1[on] = z; d1.jt1[on] = z;
+    f.ex1[od] = z; f.br1[od] = z; f.bt1[od] = z; f.brb1[od] = z; f.btb1[od] = z;
+    d0.jx1[od] = z; d1.jx1[od] = z;
+    f.er1[ol] = z; f.et1[ol] = z;
+  }
+}
+
+// ---------------------------------------------------- initial envelope --
+// Paraxial Gaussian: a0 exp(-r^2/(w0^2 q))/q exp(-(x - x_c - t)^2/sigma^2),
+// q = 1 + i (x - x_f)/Z_R, Z_R = w0^2/2, sigma = tau/(2 sqrt(ln 2)), at
+// t = 0 (A^0) and t = -dt (A^{-1}); zero on the Dirichlet boundary nodes.
+__device__ inline double2 pulse_at(const Laser& L, double x, double r, double t) {
+  if (L.a0 == 0.0) return make_double2(0.0, 0.0);
+  const double zr = 0.5 * L.w0 * L.w0;
+  const double qi = (x - L.x_f) / zr;  // q = 1 + i qi
+  const double den = 1.0 + qi * qi;
+  // 1/q = (1 - i qi)/den ; -r^2/(w0^2 q) = -r^2 (1 - i qi)/(w0^2 den)
+  const double er = -r * r / (L.w0 * L.w0 * den), ei = r * r * qi / (L.w0 * L.w0 * den);
+  const double sig = L.tau / (2.0 * sqrt(log(2.0)));
+  const double xi = x - L.x_c - t;
+  const double mag = L.a0 * exp(er) * exp(-xi * xi / (sig * sig)) / den;
+  double sn, cs;
+  sincos(ei, &sn, &cs);
+  // (cs + i sn)(1 - i qi)
+  return make_double2(mag * (cs + sn * qi), mag * (sn - cs * qi));
+}
+
+template <class R>
+__global__ void k_init_envelope(Geo g, Grids<R> f, Laser L, int fp64_rows) {
+  using C = typename cplx_of<R>::type;
+  const int nr1 = g.nr + 1;
+  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (long long)(g.nx + 1) * nr1) return;
+  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
+  const int pc = phys_col(g, i);
+  const size_t o = (size_t)pc * g.pitch + j;
+  const bool edge = i == 0 || i == g.nx || j == g.nr;
+  const double x = (double)(g.shift + i) * g.dx, r = j * g.dr;
+  const double2 a0 = edge ? make_double2(0.0, 0.0) : pulse_at(L, x, r, 0.0);
+  const double2 am = edge ? make_double2(0.0, 0.0) : pulse_at(L, x, r, -g.dt);
+  f.env[o] = mk<C>((R)a0.x, (R)a0.y);
+  f.envp[o] = mk<C>((R)am.x, (R)am.y);
+  if (fp64_rows && j <= 1) {
+    f.ax[pc * 2 + j] = a0;
+    f.axp[pc * 2 + j] = am;
+  }
+}
+
+// ------------------------------------------------------------ launchers --
+static inline int node_blocks(const Geo& g) {
+  const long long n = (long long)(g.nx + 1) * (g.nr + 1);
+  return (int)((n + 255) / 256);
+}
+
+template <class R>
+void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st) {
+  hipLaunchKernelGGL((k_envelope<R>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, chi, fp64_rows);
+}
+
+template <class R>
+void launch_maxwell(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
+                    hipStream_t st) {
+  if (g.modes >= 2) {
+    hipLaunchKernelGGL((k_maxwell_E<R, true>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, din, dnext);
+    hipLaunchKernelGGL((k_maxwell_B<R, true>), dim3(node_blocks(g)), dim3(256), 0, st, g, f);
+  } else {
+    hipLaunchKernelGGL((k_maxwell_E<R, false>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, din, dnext);
+    hipLaunchKernelGGL((k_maxwell_B<R, false>), dim3(node_blocks(g)), dim3(256), 0, st, g, f);
+  }
+}
+
+template <class R>
+void launch_window(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d0, const DepositBufs<R>& d1,
+                   int fp64_rows, hipStream_t st) {
+  const int blocks = (g.nr + 1 + 255) / 256;
+  if (g.modes >= 2)
+    hipLaunchKernelGGL((k_window<R, true>), dim3(blocks), dim3(256), 0, st, g, f, d0, d1, fp64_rows);
+  else
+    hipLaunchKernelGGL((k_window<R, false>), dim3(blocks), dim3(256), 0, st, g, f, d0, d1, fp64_rows);
+}
+
+template <class R>
+void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st) {
+  hipLaunchKernelGGL((k_init_envelope<R>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, L, fp64_rows);
+}
+
+#define ENVPIC_INST(R)                                                                                      \
+  template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, hipStream_t);                \
+  template void launch_maxwell<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&, \
+                                  hipStream_t);                                                             \
+  template void launch_window<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&, \
+                                 int, hipStream_t);                                                         \
+  template void launch_init_envelope<R>(const Geo&, const Grids<R>&, const Laser&, int, hipStream_t);
+ENVPIC_INST(float)
+ENVPIC_INST(double)
+#undef ENVPIC_INST
+
+}  // namespace envpic

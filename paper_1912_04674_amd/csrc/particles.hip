@@ -1,0 +1,920 @@
+// particles.hip -- per-macroparticle kernels of the cylindrical envelope PIC
+// step (arXiv:1912.04674): the momentum pass (gather of E, Bbar, Phi and
+// grad Phi, ponderomotive Boris push, chi deposit, scatter into the tile
+// order of the next pass), the position pass (gather of Phi^{n+1/2}, push,
+// current deposit, tile histogram), loading and injection.
+//
+// Work decomposition: particles are counting-sorted by 16 x 16-cell tiles
+// every step; a work item is (tile, contiguous range of <= CHUNK particles).
+// A work group stages the fields of its tile plus a 2-cell halo in LDS,
+// accumulates the deposits of its particles in LDS and flushes them to HBM
+// once (atomic adds, since halos overlap).  Particles drift at most one cell
+// per step (dt < dx, dt < dr), which the halo covers.
+//
+// Positions: lab cell (column, row) in one word plus offsets in the cell
+// along x and r and the azimuth; the push is Cartesian (Sec. 3), and the
+// new radius is obtained from the radial and azimuthal components of the
+// displacement without cancellation, so the offsets keep their resolution at
+// any radius.
+#include "common.hpp"
+#include "cplx.hpp"
+#include "launch.hpp"
+
+namespace envpic {
+
+// ------------------------------------------------------------ shapes --
+template <class R> struct Lin {
+  int i;   // first node (local LDS index)
+  R a, b;  // weights of nodes i and i+1
+};
+
+template <class R> __device__ inline Lin<R> primal_w(int c, R f) { return Lin<R>{c, (R)1 - f, f}; }
+template <class R> __device__ inline Lin<R> dual_w(int c, R f) {
+  R v = f - (R)0.5;
+  if (v < (R)0) return Lin<R>{c - 1, (R)0.5 - f, f + (R)0.5};
+  return Lin<R>{c, (R)1 - v, v};
+}
+
+template <class R> __device__ inline R interp2(const R* a, Lin<R> sx, Lin<R> sr) {
+  return sx.a * (sr.a * a[sx.i * LR + sr.i] + sr.b * a[sx.i * LR + sr.i + 1]) +
+         sx.b * (sr.a * a[(sx.i + 1) * LR + sr.i] + sr.b * a[(sx.i + 1) * LR + sr.i + 1]);
+}
+template <class C, class R> __device__ inline C interp2c(const C* a, Lin<R> sx, Lin<R> sr) {
+  C v00 = a[sx.i * LR + sr.i], v01 = a[sx.i * LR + sr.i + 1];
+  C v10 = a[(sx.i + 1) * LR + sr.i], v11 = a[(sx.i + 1) * LR + sr.i + 1];
+  R w00 = sx.a * sr.a, w01 = sx.a * sr.b, w10 = sx.b * sr.a, w11 = sx.b * sr.b;
+  return mk<C>(w00 * v00.x + w01 * v01.x + w10 * v10.x + w11 * v11.x,
+               w00 * v00.y + w01 * v01.y + w10 * v10.y + w11 * v11.y);
+}
+
+__device__ inline int clampi(int v, int lo, int hi, bool& bad) {
+  if (v < lo) { bad = true; return lo; }
+  if (v > hi) { bad = true; return hi; }
+  return v;
+}
+
+__device__ inline void lds_add(float* a, float v) { atomicAdd(a, v); }
+__device__ inline void lds_add(double* a, double v) { atomicAdd(a, v); }
+__device__ inline void lds_addc(float2* a, float2 v) {
+  atomicAdd(&a->x, v.x);
+  atomicAdd(&a->y, v.y);
+}
+__device__ inline void lds_addc(double2* a, double2 v) {
+  atomicAdd(&a->x, v.x);
+  atomicAdd(&a->y, v.y);
+}
+
+__device__ inline void sincos_r(float t, float* s, float* c) { sincosf(t, s, c); }
+__device__ inline void sincos_r(double t, double* s, double* c) { sincos(t, s, c); }
+
+// carry an offset back into [0, 1): cell += floor(off), off -= floor(off)
+template <class R> __device__ inline void carry(int& cell, R& off) {
+  const R c = floor(off);
+  cell += (int)c;
+  off -= c;
+  if (off >= (R)1) {  // rounding of 1 - tiny
+    off = 0;
+    cell += 1;
+  }
+}
+
+// New radius and azimuth after a Cartesian transverse displacement with
+// radial component a and azimuthal component b (lengths) from radius r:
+// r' = |(r + a, b)|, written r' - r = a + (r + a)(sqrt(1 + beta^2) - 1) with
+// beta = b/(r + a) so that small displacements keep full relative precision.
+template <class R> __device__ inline void radial_step(R r, R a, R b, R& dr_out, R& dth) {
+  const R ra = r + a;
+  if (ra > (R)0) {
+    const R beta = b / ra;
+    const R q = sqrt((R)1 + beta * beta);
+    dr_out = a + ra * beta * beta / ((R)1 + q);
+  } else {
+    dr_out = sqrt(ra * ra + b * b) - r;
+  }
+  dth = atan2(b, ra);
+}
+
+template <class R> __device__ inline R wrap_angle(R t) {
+  const R pi = (R)3.14159265358979323846, two_pi = (R)6.28318530717958647692;
+  if (t > pi) t -= two_pi;
+  if (t < -pi) t += two_pi;
+  return t;
+}
+
+// the tile region of a work item: lab column X0 = T TX - HALO, row R0
+struct Region {
+  int T, tcx, tcr;
+  long long X0;
+  int relX0, R0;
+};
+__device__ inline Region region_of(const Geo& g, int key) {
+  Region q;
+  q.tcx = key / g.ntr;
+  q.tcr = key - q.tcx * g.ntr;
+  q.T = lab_tile(g, q.tcx);
+  q.X0 = (long long)q.T * TX - HALO;
+  q.relX0 = (int)(q.X0 - g.shift);
+  q.R0 = q.tcr * TR - HALO;
+  return q;
+}
+
+// ================================================== momentum pass ==
+template <class R, bool M1> struct SmemMom {
+  using C = typename cplx_of<R>::type;
+  R ex[LN], er[LN], bt[LN], phi[LN], chi[LN];
+  C ex1[M1 ? LN : 1], er1[M1 ? LN : 1], et1[M1 ? LN : 1];
+  C bx1[M1 ? LN : 1], br1[M1 ? LN : 1], bt1[M1 ? LN : 1];
+  R ivol[LR];
+  int cnt[9], base[9];
+};
+
+template <class R, bool M1, bool DEFER>
+__global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restrict__ chi_out,
+                                                 Parts<R> src, Parts<R> dst, Layout Ls, Layout Ld,
+                                                 R* __restrict__ gscr, int* err) {
+  using C = typename cplx_of<R>::type;
+  __shared__ SmemMom<R, M1> sm;
+  const int item = blockIdx.x;
+  if (item >= *Ls.n_items) return;
+  const int4 it = Ls.items[item];
+  const int start = it.y, count = it.z;
+  const Region q = region_of(g, it.x);
+  const R inv_dx = (R)(1.0 / g.dx), inv_dr = (R)(1.0 / g.dr);
+  const R hdt = (R)(0.5 * g.dt);
+
+  // ---- stage E, Bbar, Phi (and mode 1) of the region in LDS
+  for (int k = threadIdx.x; k < LN; k += WG) {
+    const int a = k / LR, b = k - (k / LR) * LR;
+    const int rel = q.relX0 + a, j = q.R0 + b;
+    const bool px = rel >= 0 && rel <= g.nx, dxok = rel >= 0 && rel <= g.nx - 1;
+    const size_t o = (px || dxok) ? (size_t)phys_col(g, rel) * g.pitch : 0;
+    const bool pr = j >= 0 && j <= g.nr, drok = j >= 0 && j <= g.nr - 1, ghost = j == -1;
+    sm.ex[k] = (dxok && pr) ? f.ex[o + j] : (R)0;
+    sm.er[k] = px ? (drok ? f.er[o + j] : (ghost ? -f.er[o] : (R)0)) : (R)0;
+    sm.bt[k] = dxok ? (drok ? f.btb[o + j] : (ghost ? -f.btb[o] : (R)0)) : (R)0;
+    R ph = 0;
+    if (px && pr) ph = (R)0.5 * cnorm(f.env[o + j]);
+    sm.phi[k] = ph;
+    sm.chi[k] = 0;
+    if (M1) {
+      const C z = mk<C>((R)0, (R)0);
+      sm.ex1[k] = (dxok && pr) ? f.ex1[o + j] : z;
+      sm.er1[k] = px ? (drok ? f.er1[o + j] : (ghost ? f.er1[o] : z)) : z;
+      sm.et1[k] = (px && pr) ? f.et1[o + j] : z;
+      sm.bx1[k] = px ? (drok ? f.bxb1[o + j] : (ghost ? cscale(f.bxb1[o], (R)-1) : z)) : z;
+      sm.br1[k] = (dxok && pr) ? f.brb1[o + j] : z;
+      sm.bt1[k] = dxok ? (drok ? f.btb1[o + j] : (ghost ? f.btb1[o] : z)) : z;
+    }
+  }
+  for (int k = threadIdx.x; k < LR; k += WG) {
+    const int j = q.R0 + k;
+    sm.ivol[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (R)0;
+  }
+  if (threadIdx.x < 9) sm.cnt[threadIdx.x] = 0;
+  __syncthreads();
+
+  // ---- destination tile (3 x 3 neighbourhood) and rank of each particle
+  int slot_rank[PPT];
+  bool bad = false;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int k = threadIdx.x + u * WG;
+    slot_rank[u] = -1;
+    if (k < count) {
+      const unsigned cw = src.cell[start + k];
+      if (cw != kDead) {
+        const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
+        const int dtr = clampi(cell_jr(cw) / TR - q.tcr, -1, 1, bad);
+        const int slot = (dtx + 1) * 3 + (dtr + 1);
+        slot_rank[u] = (slot << 24) | atomicAdd(&sm.cnt[slot], 1);
+      }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < 9) {
+    const int c = sm.cnt[threadIdx.x];
+    if (c > 0) {
+      int tx2 = q.tcx + threadIdx.x / 3 - 1;
+      if (tx2 < 0) tx2 += g.ntxa;
+      if (tx2 >= g.ntxa) tx2 -= g.ntxa;
+      const int tr2 = q.tcr + threadIdx.x % 3 - 1;
+      sm.base[threadIdx.x] = atomicAdd(&Ld.cursor[tx2 * g.ntr + tr2], c);
+    }
+  }
+  __syncthreads();
+
+  // ---- gather, push, deposit, scatter
+  const R i2dx = (R)0.5 * inv_dx, i2dr = (R)0.5 * inv_dr;
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    if (slot_rank[u] < 0) continue;
+    const int p = start + threadIdx.x + u * WG;
+    const int d = sm.base[slot_rank[u] >> 24] + (slot_rank[u] & 0xFFFFFF);
+    if ((long long)d >= g.cap) {  // the scan has flagged the overflow
+      bad = true;
+      continue;
+    }
+    const unsigned cw = src.cell[p];
+    const R fx = src.fx[p], fr = src.fr[p], th = src.th[p], w = src.w[p];
+    R pv[3] = {src.px[p], src.py[p], src.pz[p]};
+    const int a = clampi((int)((long long)cell_ix(cw) - q.X0), 1, LX - 3, bad);
+    const int b = clampi(cell_jr(cw) - q.R0, 1, LR - 3, bad);
+    const Lin<R> Px = primal_w<R>(a, fx), Dx = dual_w<R>(a, fx);
+    const Lin<R> Pr = primal_w<R>(b, fr), Dr = dual_w<R>(b, fr);
+    R s, c;
+    sincos_r(th, &s, &c);
+    R ex = interp2<R>(sm.ex, Dx, Pr);
+    R er = interp2<R>(sm.er, Px, Dr);
+    R bt = interp2<R>(sm.bt, Dx, Dr);
+    R et = 0, bx = 0, br = 0;
+    const R ph = interp2<R>(sm.phi, Px, Pr);
+    // centred differences of Phi at the four primal nodes, then interpolated
+    R gx = 0, gr = 0;
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        const int na = Px.i + aa, nb = Pr.i + bb;
+        const R wgt = (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a);
+        gx += wgt * (sm.phi[(na + 1) * LR + nb] - sm.phi[(na - 1) * LR + nb]) * i2dx;
+        if (q.R0 + nb != 0) gr += wgt * (sm.phi[na * LR + nb + 1] - sm.phi[na * LR + nb - 1]) * i2dr;
+      }
+    if (M1) {
+      ex += mode1_at<C, R>(interp2c<C, R>(sm.ex1, Dx, Pr), c, s);
+      er += mode1_at<C, R>(interp2c<C, R>(sm.er1, Px, Dr), c, s);
+      et = mode1_at<C, R>(interp2c<C, R>(sm.et1, Px, Pr), c, s);
+      bx = mode1_at<C, R>(interp2c<C, R>(sm.bx1, Px, Dr), c, s);
+      br = mode1_at<C, R>(interp2c<C, R>(sm.br1, Dx, Pr), c, s);
+      bt += mode1_at<C, R>(interp2c<C, R>(sm.bt1, Dx, Dr), c, s);
+    }
+    // (x, r, theta) -> Cartesian, r-hat = (0, c, s), theta-hat = (0, -s, c)
+    const R E[3] = {ex, er * c - et * s, er * s + et * c};
+    const R B[3] = {bx, br * c - bt * s, br * s + bt * c};
+    const R G[3] = {gx, gr * c, gr * s};
+    // ponderomotive Boris: half kick with gbar(p^{n-1/2}), rotation and chi
+    // with gbar of the half-kicked momentum, second half kick
+    const R g0 = sqrt((R)1 + pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2] + ph);
+    const R ig0 = (R)0.5 / g0;
+    R F[3], pm[3];
+#pragma unroll
+    for (int e = 0; e < 3; ++e) {
+      F[e] = -E[e] - G[e] * ig0;
+      pm[e] = pv[e] + hdt * F[e];
+    }
+    const R gb = sqrt((R)1 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2] + ph);
+    const R tf = -hdt / gb;
+    const R t[3] = {tf * B[0], tf * B[1], tf * B[2]};
+    const R sf = (R)2 / ((R)1 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    const R sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
+    const R pp[3] = {pm[0] + pm[1] * t[2] - pm[2] * t[1], pm[1] + pm[2] * t[0] - pm[0] * t[2],
+                     pm[2] + pm[0] * t[1] - pm[1] * t[0]};
+    pv[0] = pm[0] + pp[1] * sv[2] - pp[2] * sv[1] + hdt * F[0];
+    pv[1] = pm[1] + pp[2] * sv[0] - pp[0] * sv[2] + hdt * F[1];
+    pv[2] = pm[2] + pp[0] * sv[1] - pp[1] * sv[0] + hdt * F[2];
+    if (DEFER) {
+      gscr[d] = gb;
+    } else {
+      const R wg = w / gb;
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+          const int nb = Pr.i + bb;
+          lds_add(&sm.chi[(Px.i + aa) * LR + nb], wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivol[nb]);
+        }
+    }
+    dst.cell[d] = cw;
+    dst.fx[d] = fx;
+    dst.fr[d] = fr;
+    dst.th[d] = th;
+    dst.px[d] = pv[0];
+    dst.py[d] = pv[1];
+    dst.pz[d] = pv[2];
+    dst.w[d] = w;
+    dst.id[d] = src.id[p];
+  }
+  if (bad) atomicOr(err, ERR_HALO);
+  if (DEFER) return;
+  __syncthreads();
+  for (int k = threadIdx.x; k < LN; k += WG) {
+    const R v = sm.chi[k];
+    if (v == (R)0) continue;
+    const int a = k / LR, b = k - (k / LR) * LR;
+    const int rel = q.relX0 + a, j = q.R0 + b;
+    if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
+    atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], v);
+  }
+}
+
+// ================================================== position pass ==
+template <class R, bool M1> struct SmemPos {
+  using C = typename cplx_of<R>::type;
+  R phh[LN], jx[LN], jr[LN];
+  C jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
+  R iax[LR], iar[LR], ivn[LR], ivh[LR];
+  int hist[9];
+};
+
+// one particle's move: old and new cells/offsets, transverse displacement
+// (radial a, azimuthal b, lengths) at the old azimuth, new azimuth, velocity
+template <class R> struct Move {
+  int ix0, jr0, ix1, jr1;
+  R fx0, fr0, fx1, fr1;
+  R th0, th1, a, b;
+  bool refl;
+  R vx, vy, vz;
+};
+
+// The push x^{n+1} = x^n + dt v in Cartesian space, expressed on the cell
+// representation; specular reflection at r_max (p updated).
+template <class R>
+__device__ inline void push_position(const Geo& g, unsigned cw, R fx, R fr, R th, R& py, R& pz, R vx, R vy, R vz,
+                                     Move<R>& mv) {
+  const R dt = (R)g.dt, dr = (R)g.dr;
+  mv.ix0 = cell_ix(cw);
+  mv.jr0 = cell_jr(cw);
+  mv.fx0 = fx;
+  mv.fr0 = fr;
+  mv.th0 = th;
+  mv.vx = vx;
+  mv.vy = vy;
+  mv.vz = vz;
+  mv.ix1 = mv.ix0;
+  mv.fx1 = fx + dt * vx * (R)(1.0 / g.dx);
+  carry(mv.ix1, mv.fx1);
+  R s, c;
+  sincos_r(th, &s, &c);
+  const R dy = dt * vy, dz = dt * vz;
+  mv.a = c * dy + s * dz;
+  mv.b = -s * dy + c * dz;
+  const R r = ((R)mv.jr0 + fr) * dr;
+  R drad, dth;
+  radial_step(r, mv.a, mv.b, drad, dth);
+  mv.jr1 = mv.jr0;
+  mv.fr1 = fr + drad / dr;
+  carry(mv.jr1, mv.fr1);
+  if (mv.jr1 < 0) {
+    mv.jr1 = 0;
+    mv.fr1 = 0;
+  }
+  mv.th1 = wrap_angle(th + dth);
+  mv.refl = false;
+  if (mv.jr1 >= g.nr) {
+    // r' = r_max + e with 0 <= e < dr  ->  r_max - e; reverse p_r
+    const R e = (R)(mv.jr1 - g.nr) + mv.fr1;
+    mv.jr1 = g.nr - 1;
+    mv.fr1 = (R)1 - e;
+    if (mv.fr1 < (R)0) mv.fr1 = 0;
+    R s1, c1;
+    sincos_r(mv.th1, &s1, &c1);
+    const R prad = py * c1 + pz * s1;
+    py -= (R)2 * prad * c1;
+    pz -= (R)2 * prad * s1;
+    mv.refl = true;
+  }
+}
+
+// Esirkepov current of one particle between two positions (mode 0) and the
+// direct mid-point current of mode 1, into the LDS accumulators.
+template <class R, bool M1>
+__device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, const Geo& g, const Move<R>& mv, R w,
+                                       bool& bad) {
+  using C = typename cplx_of<R>::type;
+  // the stencil spans min(a0, a1) .. min(a0, a1) + 2 (at most one cell moved)
+  const int a0 = clampi((int)((long long)mv.ix0 - q.X0), 1, LX - 4, bad);
+  const int a1 = clampi((int)((long long)mv.ix1 - q.X0), a0 - 1, a0 + 1, bad);
+  const int b0 = clampi(mv.jr0 - q.R0, 1, LR - 4, bad);
+  const int b1 = clampi(mv.jr1 - q.R0, b0 - 1, b0 + 1, bad);
+  const int amin = min(a0, a1), bmin = min(b0, b1);
+  R S0x[3] = {0, 0, 0}, S1x[3] = {0, 0, 0}, S0r[3] = {0, 0, 0}, S1r[3] = {0, 0, 0};
+  S0x[a0 - amin] += (R)1 - mv.fx0;
+  S0x[a0 - amin + 1] += mv.fx0;
+  S1x[a1 - amin] += (R)1 - mv.fx1;
+  S1x[a1 - amin + 1] += mv.fx1;
+  S0r[b0 - bmin] += (R)1 - mv.fr0;
+  S0r[b0 - bmin + 1] += mv.fr0;
+  S1r[b1 - bmin] += (R)1 - mv.fr1;
+  S1r[b1 - bmin + 1] += mv.fr1;
+  // J_x (i+1/2, j): flux accumulated along x; the third partial sum is zero
+#pragma unroll
+  for (int bb = 0; bb < 3; ++bb) {
+    const R sr = (S0r[bb] + S1r[bb]) * (R)0.5;
+    R acc = 0;
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa) {
+      acc += (S1x[aa] - S0x[aa]) * sr;
+      if (acc != (R)0) lds_add(&sm.jx[(amin + aa) * LR + bmin + bb], w * acc * sm.iax[bmin + bb]);
+    }
+  }
+  // J_r (i, j+1/2): flux accumulated along r
+#pragma unroll
+  for (int aa = 0; aa < 3; ++aa) {
+    const R sx = (S0x[aa] + S1x[aa]) * (R)0.5;
+    R acc = 0;
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb) {
+      acc += (S1r[bb] - S0r[bb]) * sx;
+      if (acc != (R)0) lds_add(&sm.jr[(amin + aa) * LR + bmin + bb], w * acc * sm.iar[bmin + bb]);
+    }
+  }
+  if (M1) {
+    // Cartesian mid-point of the old and new positions
+    const R dr = (R)g.dr;
+    const R r0 = ((R)mv.jr0 + mv.fr0) * dr;
+    int jm = mv.jr0;
+    R frm, thm;
+    if (!mv.refl) {
+      R dm, dthm;
+      radial_step(r0, (R)0.5 * mv.a, (R)0.5 * mv.b, dm, dthm);
+      frm = mv.fr0 + dm / dr;
+      thm = mv.th0 + dthm;
+    } else {
+      R s0, c0, s1, c1;
+      sincos_r(mv.th0, &s0, &c0);
+      sincos_r(mv.th1, &s1, &c1);
+      const R r1 = ((R)mv.jr1 + mv.fr1) * dr;
+      const R ym = (R)0.5 * (r0 * c0 + r1 * c1), zm = (R)0.5 * (r0 * s0 + r1 * s1);
+      jm = 0;
+      frm = sqrt(ym * ym + zm * zm) / dr;
+      thm = atan2(zm, ym);
+    }
+    carry(jm, frm);
+    if (jm < 0) {
+      jm = 0;
+      frm = 0;
+    }
+    if (jm > g.nr - 1) {
+      frm += (R)(jm - (g.nr - 1));
+      jm = g.nr - 1;
+    }
+    R s, c;
+    sincos_r(thm, &s, &c);
+    const R um = (R)0.5 * ((R)a0 + mv.fx0 + (R)a1 + mv.fx1);
+    const int am = (int)floor(um);
+    const R fm = um - (R)am;
+    const int bm = clampi(jm - q.R0, 1, LR - 3, bad);
+    const int amc = clampi(am, 1, LX - 3, bad);
+    const R vr = mv.vy * c + mv.vz * s, vt = -mv.vy * s + mv.vz * c;
+    const R q2 = (R)-2 * w;  // 2 q w, electrons
+    const C e = mk<C>(c, s);
+    const Lin<R> Px = primal_w<R>(amc, fm), Dx = dual_w<R>(amc, fm);
+    const Lin<R> Pr = primal_w<R>(bm, frm), Dr = dual_w<R>(bm, frm);
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        // J_x1 at (i+1/2, j)
+        {
+          const int nb = Pr.i + bb;
+          const R wt = (aa ? Dx.b : Dx.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
+          lds_addc(&sm.jx1[(Dx.i + aa) * LR + nb], cscale(e, q2 * mv.vx * wt));
+        }
+        // J_r1 at (i, j+1/2); row -1/2 folds onto +1/2 (even for mode 1)
+        {
+          int nb = Dr.i + bb;
+          if (q.R0 + nb == -1) nb += 1;
+          const R wt = (aa ? Px.b : Px.a) * (bb ? Dr.b : Dr.a) * sm.ivh[nb];
+          lds_addc(&sm.jr1[(Px.i + aa) * LR + nb], cscale(e, q2 * vr * wt));
+        }
+        // J_t1 at (i, j)
+        {
+          const int nb = Pr.i + bb;
+          const R wt = (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
+          lds_addc(&sm.jt1[(Px.i + aa) * LR + nb], cscale(e, q2 * vt * wt));
+        }
+      }
+  }
+}
+
+template <class R, bool M1>
+__device__ inline void stage_pos_constants(SmemPos<R, M1>& sm, const Region& q, const Geo& g) {
+  const double pi = 3.14159265358979323846;
+  for (int k = threadIdx.x; k < LR; k += WG) {
+    const int j = q.R0 + k;
+    // 1 / (face area * dt): axial face of row j (V_j / dx), radial face at r_{j+1/2}
+    double ax = (j == 0 ? pi * g.dr * g.dr * 0.25 : 2.0 * pi * j * g.dr * g.dr);
+    double ar = 2.0 * pi * (j + 0.5) * g.dr * g.dx;
+    sm.iax[k] = (j >= 0 && j <= g.nr) ? (R)(1.0 / (ax * g.dt)) : (R)0;
+    sm.iar[k] = (j >= 0 && j <= g.nr - 1) ? (R)(1.0 / (ar * g.dt)) : (R)0;
+    sm.ivn[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (R)0;
+    sm.ivh[k] = (j >= 0 && j <= g.nr - 1) ? inv_vol_half<R>(g, j) : (R)0;
+  }
+}
+
+template <class R, bool M1>
+__device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
+  using C = typename cplx_of<R>::type;
+  for (int k = threadIdx.x; k < LN; k += WG) {
+    sm.jx[k] = 0;
+    sm.jr[k] = 0;
+    if (M1) {
+      sm.jx1[k] = mk<C>((R)0, (R)0);
+      sm.jr1[k] = mk<C>((R)0, (R)0);
+      sm.jt1[k] = mk<C>((R)0, (R)0);
+    }
+  }
+  if (threadIdx.x < 9) sm.hist[threadIdx.x] = 0;
+}
+
+template <class R, bool M1>
+__device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const Geo& g, R* jx_out,
+                                     R* jr_out, typename cplx_of<R>::type* jx1_out,
+                                     typename cplx_of<R>::type* jr1_out,
+                                     typename cplx_of<R>::type* jt1_out) {
+  for (int k = threadIdx.x; k < LN; k += WG) {
+    const int a = k / LR, b = k - (k / LR) * LR;
+    const int rel = q.relX0 + a, j = q.R0 + b;
+    if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
+    const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
+    const bool dxok = rel <= g.nx - 1, drok = j <= g.nr - 1;
+    if (dxok && sm.jx[k] != (R)0) atomicAdd(&jx_out[o], sm.jx[k]);
+    if (drok && sm.jr[k] != (R)0) atomicAdd(&jr_out[o], sm.jr[k]);
+    if (M1) {
+      if (dxok && (sm.jx1[k].x != (R)0 || sm.jx1[k].y != (R)0)) {
+        atomicAdd(&jx1_out[o].x, sm.jx1[k].x);
+        atomicAdd(&jx1_out[o].y, sm.jx1[k].y);
+      }
+      if (drok && (sm.jr1[k].x != (R)0 || sm.jr1[k].y != (R)0)) {
+        atomicAdd(&jr1_out[o].x, sm.jr1[k].x);
+        atomicAdd(&jr1_out[o].y, sm.jr1[k].y);
+      }
+      if (sm.jt1[k].x != (R)0 || sm.jt1[k].y != (R)0) {
+        atomicAdd(&jt1_out[o].x, sm.jt1[k].x);
+        atomicAdd(&jt1_out[o].y, sm.jt1[k].y);
+      }
+    }
+  }
+}
+
+__device__ inline void flush_hist(const int* h9, const Region& q, const Geo& g, int* hist) {
+  if (threadIdx.x < 9) {
+    const int c = h9[threadIdx.x];
+    if (c > 0) {
+      int tx2 = q.tcx + threadIdx.x / 3 - 1;
+      if (tx2 < 0) tx2 += g.ntxa;
+      if (tx2 >= g.ntxa) tx2 -= g.ntxa;
+      const int tr2 = q.tcr + threadIdx.x % 3 - 1;
+      atomicAdd(&hist[tx2 * g.ntr + tr2], c);
+    }
+  }
+}
+
+// vacate: 1 when the window moves after this step (particles whose new
+// column is the window's first one are dropped after depositing)
+template <class R, bool M1, bool DEFER>
+__global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restrict__ jx_out,
+                                                 R* __restrict__ jr_out,
+                                                 typename cplx_of<R>::type* __restrict__ jx1_out,
+                                                 typename cplx_of<R>::type* __restrict__ jr1_out,
+                                                 typename cplx_of<R>::type* __restrict__ jt1_out,
+                                                 Parts<R> P, Layout L, int* __restrict__ hist, int vacate,
+                                                 Parts<R> scr, int* err) {
+  __shared__ SmemPos<R, M1> sm;
+  const int item = blockIdx.x;
+  if (item >= *L.n_items) return;
+  const int4 it = L.items[item];
+  const int start = it.y, count = it.z;
+  const Region q = region_of(g, it.x);
+
+  // Phi^{n+1/2} = (|A^{n+1}|^2 + |A^n|^2)/4 on the primal nodes
+  for (int k = threadIdx.x; k < LN; k += WG) {
+    const int a = k / LR, b = k - (k / LR) * LR;
+    const int rel = q.relX0 + a, j = q.R0 + b;
+    R v = 0;
+    if (rel >= 0 && rel <= g.nx && j >= 0 && j <= g.nr) {
+      const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
+      v = (R)0.25 * (cnorm(f.env[o]) + cnorm(f.envp[o]));
+    }
+    sm.phh[k] = v;
+  }
+  stage_pos_constants(sm, q, g);
+  zero_pos_acc(sm);
+  __syncthreads();
+
+  bool bad = false;
+  for (int k = threadIdx.x; k < count; k += WG) {
+    const int p = start + k;
+    const unsigned cw = P.cell[p];
+    if (cw == kDead) continue;
+    const R fx = P.fx[p], fr = P.fr[p], th = P.th[p], w = P.w[p];
+    const R px = P.px[p];
+    R py = P.py[p], pz = P.pz[p];
+    const int a = clampi((int)((long long)cell_ix(cw) - q.X0), 0, LX - 2, bad);
+    const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
+    const R ph = interp2<R>(sm.phh, primal_w<R>(a, fx), primal_w<R>(b, fr));
+    const R gm = sqrt((R)1 + px * px + py * py + pz * pz + ph);
+    const R ig = (R)1 / gm;
+    Move<R> mv;
+    push_position<R>(g, cw, fx, fr, th, py, pz, px * ig, py * ig, pz * ig, mv);
+    if (mv.refl) {
+      P.py[p] = py;
+      P.pz[p] = pz;
+    }
+    const long long reln = (long long)mv.ix1 - g.shift;
+    if (reln < 0 || reln >= g.nx) {
+      P.cell[p] = kDead;  // left the window: removed without deposit
+      continue;
+    }
+    if (DEFER) {
+      scr.cell[p] = cw;
+      scr.fx[p] = fx;
+      scr.fr[p] = fr;
+      scr.th[p] = th;
+      scr.w[p] = mv.refl ? -gm : gm;
+    } else {
+      deposit_current<R, M1>(sm, q, g, mv, w, bad);
+    }
+    P.cell[p] = pack_cell(mv.ix1, mv.jr1);
+    P.fx[p] = mv.fx1;
+    P.fr[p] = mv.fr1;
+    P.th[p] = mv.th1;
+    if (vacate && reln < 1) {
+      if (!DEFER) P.cell[p] = kDead;  // vacated column: dropped after depositing
+      continue;
+    }
+    const int dtx = clampi(mv.ix1 / TX - q.T, -1, 1, bad);
+    const int dtr = clampi(mv.jr1 / TR - q.tcr, -1, 1, bad);
+    atomicAdd(&sm.hist[(dtx + 1) * 3 + (dtr + 1)], 1);
+  }
+  if (bad) atomicOr(err, ERR_HALO);
+  __syncthreads();
+  if (!DEFER) flush_current(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
+  flush_hist(sm.hist, q, g, hist);
+}
+
+// ============================= deferred deposits (stage-by-stage API) ==
+// chi^n from x^n and the gbar^n kept by a deferred momentum pass
+template <class R>
+__global__ __launch_bounds__(WG) void k_deposit_chi(Geo g, R* __restrict__ chi_out, Parts<R> P,
+                                                    Layout L, const R* __restrict__ gscr, int* err) {
+  __shared__ R acc[LN];
+  __shared__ R ivol[LR];
+  const int item = blockIdx.x;
+  if (item >= *L.n_items) return;
+  const int4 it = L.items[item];
+  const Region q = region_of(g, it.x);
+  for (int k = threadIdx.x; k < LN; k += WG) acc[k] = 0;
+  for (int k = threadIdx.x; k < LR; k += WG) {
+    const int j = q.R0 + k;
+    ivol[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (R)0;
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int k = threadIdx.x; k < it.z; k += WG) {
+    const int p = it.y + k;
+    const unsigned cw = P.cell[p];
+    if (cw == kDead) continue;
+    const int a = clampi((int)((long long)cell_ix(cw) - q.X0), 0, LX - 2, bad);
+    const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
+    const Lin<R> Px = primal_w<R>(a, P.fx[p]), Pr = primal_w<R>(b, P.fr[p]);
+    const R wg = P.w[p] / gscr[p];
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb)
+        lds_add(&acc[(Px.i + aa) * LR + Pr.i + bb], wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * ivol[Pr.i + bb]);
+  }
+  if (bad) atomicOr(err, ERR_HALO);
+  __syncthreads();
+  for (int k = threadIdx.x; k < LN; k += WG) {
+    const R v = acc[k];
+    if (v == (R)0) continue;
+    const int a = k / LR, b = k - (k / LR) * LR;
+    const int rel = q.relX0 + a, j = q.R0 + b;
+    if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
+    atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], v);
+  }
+}
+
+// J^{n+1/2} from the old positions and gbar kept by a deferred position pass
+template <class R, bool M1>
+__global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out, R* __restrict__ jr_out,
+                                                  typename cplx_of<R>::type* __restrict__ jx1_out,
+                                                  typename cplx_of<R>::type* __restrict__ jr1_out,
+                                                  typename cplx_of<R>::type* __restrict__ jt1_out,
+                                                  Parts<R> P, Layout L, int vacate, Parts<R> scr, int* err) {
+  __shared__ SmemPos<R, M1> sm;
+  const int item = blockIdx.x;
+  if (item >= *L.n_items) return;
+  const int4 it = L.items[item];
+  const Region q = region_of(g, it.x);
+  stage_pos_constants(sm, q, g);
+  zero_pos_acc(sm);
+  __syncthreads();
+  bool bad = false;
+  for (int k = threadIdx.x; k < it.z; k += WG) {
+    const int p = it.y + k;
+    const unsigned cw = P.cell[p];
+    if (cw == kDead) continue;
+    const R gm = scr.w[p];
+    R py = P.py[p], pz = P.pz[p];
+    if (gm < (R)0) {
+      // undo the specular reflection of p (an involution about r-hat)
+      R s1, c1;
+      sincos_r(P.th[p], &s1, &c1);
+      const R prad = py * c1 + pz * s1;
+      py -= (R)2 * prad * c1;
+      pz -= (R)2 * prad * s1;
+    }
+    const R ig = (R)1 / fabs(gm);
+    // replay the push from the kept old position: the same arithmetic as the
+    // fused position pass, hence the same move
+    Move<R> mv;
+    R py2 = py, pz2 = pz;
+    push_position<R>(g, scr.cell[p], scr.fx[p], scr.fr[p], scr.th[p], py2, pz2, P.px[p] * ig, py * ig, pz * ig, mv);
+    deposit_current<R, M1>(sm, q, g, mv, P.w[p], bad);
+    if (vacate && (long long)cell_ix(cw) - g.shift < 1) P.cell[p] = kDead;
+  }
+  if (bad) atomicOr(err, ERR_HALO);
+  __syncthreads();
+  flush_current(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
+}
+
+// ============================================== loading / injection ==
+// Plasma of lab cell column `col`, radial cell j (one thread per cell):
+// regular in x and r, one SplitMix64 angle per cell with equally spaced
+// angles inside the cell, weights n 2 pi r (dr/N_r)(dx/N_x)/N_theta.
+template <class R>
+__device__ inline int load_cell(const Geo& g, const Plasma& pl, Parts<R> P, int slot, long long col, int j) {
+  const double pi = 3.14159265358979323846;
+  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
+  const double th0 = 2.0 * pi * counter_uniform(pl.seed, STREAM_ANGLE, col, j);
+  int live = 0;
+  int k = 0;
+  for (int a = 0; a < g.ppc_x; ++a)
+    for (int b = 0; b < g.ppc_r; ++b)
+      for (int t = 0; t < g.ppc_t; ++t, ++k) {
+        const double fx = (a + 0.5) / g.ppc_x, fr = (b + 0.5) / g.ppc_r;
+        const double xl = ((double)col + fx) * g.dx;
+        const double r = (j + fr) * g.dr;
+        const double n = plasma_density(pl, xl, col, j);
+        const int s = slot + k;
+        P.px[s] = 0;
+        P.py[s] = 0;
+        P.pz[s] = 0;
+        P.id[s] = (uint32_t)(col * (long long)g.nr * ppc + (long long)j * ppc + (a * g.ppc_r + b) * g.ppc_t + t);
+        if (!(n > 0.0)) {
+          P.cell[s] = kDead;
+          P.fx[s] = 0;
+          P.fr[s] = 0;
+          P.th[s] = 0;
+          P.w[s] = 0;
+          continue;
+        }
+        double th = th0 + 2.0 * pi * t / g.ppc_t;
+        th = atan2(sin(th), cos(th));
+        P.cell[s] = pack_cell((int)col, j);
+        P.fx[s] = (R)fx;
+        P.fr[s] = (R)fr;
+        P.th[s] = (R)th;
+        P.w[s] = (R)(n * 2.0 * pi * r * (g.dr / g.ppc_r) * (g.dx / g.ppc_x) / g.ppc_t);
+        ++live;
+      }
+  return live;
+}
+
+// initial loading of window cells in tile-major order (offsets per tile
+// from the host, cells of a tile column-major inside the tile)
+template <class R>
+__global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __restrict__ offsets) {
+  const long long cell = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (cell >= (long long)g.nx * g.nr) return;
+  const int col = (int)(cell / g.nr), j = (int)(cell - (long long)col * g.nr);
+  const int T = col / TX, tcr = j / TR;
+  const int trt = min(TR, g.nr - tcr * TR);
+  const int key = tile_key(g, col, j);
+  const int local = (col - T * TX) * trt + (j - tcr * TR);
+  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
+  load_cell<R>(g, pl, P, offsets[key] + local * ppc, col, j);
+}
+
+// injection of the cell column entering the window after a shift (g holds
+// the new shift); particles are appended after the live range of P and get
+// one work item per tile row (one work group: the item count is updated
+// after all reads of it)
+template <class R>
+__global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict__ hist, long long capacity,
+                         int max_items, int* err) {
+  const long long col = g.shift + g.nx - 1;
+  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
+  const int total = L.offsets[g.ntiles];
+  const int base_items = *L.n_items;
+  if ((long long)total + (long long)g.nr * ppc > capacity || base_items + g.ntr > max_items || col > COL_MAX) {
+    if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+    return;
+  }
+  for (int j = threadIdx.x; j < g.nr; j += blockDim.x) {
+    const int live = load_cell<R>(g, pl, P, total + j * ppc, col, j);
+    if (live) atomicAdd(&hist[tile_key(g, col, j)], live);
+  }
+  for (int t = threadIdx.x; t < g.ntr; t += blockDim.x) {
+    const int trt = min(TR, g.nr - t * TR);
+    L.items[base_items + t] = make_int4(tile_key(g, col, t * TR), total + t * TR * ppc, trt * ppc, 0);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) *L.n_items = base_items + g.ntr;
+}
+
+// counts of live particles per tile of their current position
+template <class R>
+__global__ void k_hist(Geo g, Parts<R> P, Layout L, int* __restrict__ hist) {
+  const int item = blockIdx.x;
+  if (item >= *L.n_items) return;
+  const int4 it = L.items[item];
+  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
+    const unsigned cw = P.cell[it.y + k];
+    if (cw == kDead) continue;
+    atomicAdd(&hist[tile_key(g, cell_ix(cw), cell_jr(cw))], 1);
+  }
+}
+
+// ============================================================ launchers ==
+template <class R>
+void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
+                     const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool defer,
+                     hipStream_t st) {
+  if (grid <= 0) return;
+  if (g.modes >= 2) {
+    if (defer)
+      hipLaunchKernelGGL((k_momentum<R, true, true>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+    else
+      hipLaunchKernelGGL((k_momentum<R, true, false>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+  } else {
+    if (defer)
+      hipLaunchKernelGGL((k_momentum<R, false, true>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+    else
+      hipLaunchKernelGGL((k_momentum<R, false, false>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+  }
+}
+
+template <class R>
+void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
+                     int* hist, int vacate, const Parts<R>& scr, int* err, int grid, bool defer, hipStream_t st) {
+  if (grid <= 0) return;
+  if (g.modes >= 2) {
+    if (defer)
+      hipLaunchKernelGGL((k_position<R, true, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+    else
+      hipLaunchKernelGGL((k_position<R, true, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+  } else {
+    if (defer)
+      hipLaunchKernelGGL((k_position<R, false, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+    else
+      hipLaunchKernelGGL((k_position<R, false, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+  }
+}
+
+template <class R>
+void launch_deposit_chi(const Geo& g, R* chi, const Parts<R>& P, const Layout& L, const R* gscr, int* err, int grid,
+                        hipStream_t st) {
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((k_deposit_chi<R>), dim3(grid), dim3(WG), 0, st, g, chi, P, L, gscr, err);
+}
+
+template <class R>
+void launch_deposit_J(const Geo& g, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L, int vacate,
+                      const Parts<R>& scr, int* err, int grid, hipStream_t st) {
+  if (grid <= 0) return;
+  if (g.modes >= 2)
+    hipLaunchKernelGGL((k_deposit_J<R, true>), dim3(grid), dim3(WG), 0, st, g, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, vacate, scr, err);
+  else
+    hipLaunchKernelGGL((k_deposit_J<R, false>), dim3(grid), dim3(WG), 0, st, g, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, vacate, scr, err);
+}
+
+template <class R>
+void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, const int* offsets, hipStream_t st) {
+  const long long cells = (long long)g.nx * g.nr;
+  const int grid = (int)((cells + 255) / 256);
+  hipLaunchKernelGGL((k_init_particles<R>), dim3(grid), dim3(256), 0, st, g, pl, P, offsets);
+}
+
+template <class R>
+void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* hist, long long capacity,
+                   int max_items, int* err, hipStream_t st) {
+  hipLaunchKernelGGL((k_inject<R>), dim3(1), dim3(1024), 0, st, g, pl, P, L, hist, capacity, max_items, err);
+}
+
+template <class R>
+void launch_hist(const Geo& g, const Parts<R>& P, const Layout& L, int* hist, int grid, hipStream_t st) {
+  if (grid <= 0) return;
+  hipLaunchKernelGGL((k_hist<R>), dim3(grid), dim3(256), 0, st, g, P, L, hist);
+}
+
+#define ENVPIC_INST(R)                                                                                          \
+  template void launch_momentum<R>(const Geo&, const Grids<R>&, R*, const Parts<R>&, const Parts<R>&,           \
+                                   const Layout&, const Layout&, R*, int*, int, bool, hipStream_t);             \
+  template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
+                                   const Layout&, int*, int, const Parts<R>&, int*, int, bool, hipStream_t);    \
+  template void launch_deposit_chi<R>(const Geo&, R*, const Parts<R>&, const Layout&, const R*, int*, int,      \
+                                      hipStream_t);                                                             \
+  template void launch_deposit_J<R>(const Geo&, const DepositBufs<R>&, const Parts<R>&, const Layout&, int,     \
+                                    const Parts<R>&, int*, int, hipStream_t);                                   \
+  template void launch_init_particles<R>(const Geo&, const Plasma&, const Parts<R>&, const int*, hipStream_t);  \
+  template void launch_inject<R>(const Geo&, const Plasma&, const Parts<R>&, const Layout&, int*, long long,    \
+                                 int, int*, hipStream_t);                                                       \
+  template void launch_hist<R>(const Geo&, const Parts<R>&, const Layout&, int*, int, hipStream_t);
+ENVPIC_INST(float)
+ENVPIC_INST(double)
+#undef ENVPIC_INST
+
+}  // namespace envpic
