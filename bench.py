@@ -1,0 +1,188 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the HIP cylindrical envelope PIC step (one GPU).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c5]
+
+Prints one JSON line.  A step is one full PIC step (momentum pass with chi,
+envelope update, position pass with J, fields, moving window with injection,
+tile sort) of the whole workload, all inputs resident in HBM.  `value` is
+particle pushes per second of the FP32-bulk path; the FP64 path, the
+per-kernel HBM roofline and the CPU oracle baseline are reported beside it.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+for _p in (ROOT, os.path.join(ROOT, "tests"), os.path.join(ROOT, "oracle")):
+    if _p not in sys.path:
+        sys.path.insert(0, _p)
+
+METRIC = "particle-pushes/s FP32 vs FP64 path at oracle tol; scan-job p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(cfg, n_particles, prec_bytes=4):
+    """Bytes the method must move per launch of the two particle kernels
+    (each array read or written once; no sort, halo or re-read traffic).
+    Per particle: momentum pass reads cell, offsets, azimuth, p, w (8 words)
+    and writes p (3 words); position pass reads the same 8 words and writes
+    cell, offsets, azimuth (4 words).  Per cell: the gathered grids and the
+    deposited grids of each pass (mode 1 adds six complex gathers and three
+    complex currents)."""
+    w = prec_bytes
+    cells = cfg["nx"] * cfg["nr"]
+    m1 = cfg.get("n_modes", 1) >= 2
+    mom_p = 4 + 7 * w + 3 * w                 # read 8 words, write p
+    pos_p = 4 + 7 * w + 4 + 3 * w             # read 8 words, write cell + 3 offsets
+    mom_c = 3 * w + 2 * w + w + (12 * w if m1 else 0)   # E_x, E_r, Bbar_t, A; chi; mode-1 gathers
+    pos_c = 4 * w + 2 * w + (6 * w if m1 else 0)        # A^n, A^{n+1}; J_x, J_r; mode-1 J
+    return {"k_momentum": mom_p * n_particles + mom_c * cells,
+            "k_position": pos_p * n_particles + pos_c * cells,
+            "per_particle": {"k_momentum": mom_p, "k_position": pos_p},
+            "per_cell": {"k_momentum": mom_c, "k_position": pos_c}}
+
+
+def traffic_record(kernel, workload):
+    """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
+    by a copy-kernel calibration) from profiles/, valid only while the kernel
+    source is unchanged."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1912_04674_amd", "csrc", "particles.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    if rec.get("source_sha256_16") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True):
+    stream = torch.cuda.current_stream()
+    sim = E.Sim(cfg, prec, stream=stream)
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    n0 = sim.state()[2]
+    evs = []
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    t_start.record(stream)
+    for _ in range(steps):
+        if per_kernel:
+            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+            e[0].record(stream)
+            sim.momentum()
+            e[1].record(stream)
+            sim.envelope_step()
+            e[2].record(stream)
+            sim.position()
+            e[3].record(stream)
+            sim.field_step()
+            evs.append(e)
+        else:
+            sim.step(1)
+    t_end.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    n1 = sim.state()[2]
+    gpu_ms = t_start.elapsed_time(t_end)
+    out = {"wall_s": wall, "gpu_ms": gpu_ms, "particles": 0.5 * (n0 + n1), "n0": n0, "n1": n1}
+    if per_kernel:
+        out["k_momentum_ms"] = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
+        out["k_position_ms"] = sum(e[2].elapsed_time(e[3]) for e in evs) / steps
+    del sim
+    torch.cuda.empty_cache()
+    return out
+
+
+def cpu_baseline(cfg, cols=256, steps=20):
+    """The FP64 oracle (single thread) on a slab of the same workload: the
+    last `cols` cell columns (where the pulse is), full radius, same loading."""
+    import pyoracle
+    from inputs import scaled
+    pyoracle.build()
+    start = cfg["nx"] - cols
+    sub = scaled(cfg, nx=cols, start_col=start)
+    sim = pyoracle.OracleSim(sub)
+    n0 = sim.n_particles
+    t0 = time.perf_counter()
+    sim.step(steps)
+    dt = time.perf_counter() - t0
+    n1 = sim.n_particles
+    return {"value": 0.5 * (n0 + n1) * steps / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
+            "sample": f"{cfg['name']} columns [{start}, {cfg['nx']}) x {cfg['nr']} rows, "
+                      f"{int(0.5 * (n0 + n1))} particles, {steps} steps, FP64, 1 thread ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU x-slab "
+                                   "decomposition is not built (see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import torch
+    import paper_1912_04674_amd as E
+    from inputs import C2, C3, C5
+    cfg = {"c2": C2, "c3": C3, "c5": C5}[args.workload]
+    E.lib()
+    torch.cuda.set_device(0)
+
+    r32 = run_gpu(E, torch, cfg, E.FP32_BULK, args.steps, args.warmup)
+    pushes = r32["particles"] * args.steps
+    value = pushes / r32["wall_s"]
+    cells = cfg["nx"] * cfg["nr"]
+    ab = algorithmic_bytes(cfg, r32["particles"], 4)
+    kernels = {}
+    for k in ("k_momentum", "k_position"):
+        ms = r32[k + "_ms"]
+        kernels[k] = {"avg_ms": ms, "alg_bytes": ab[k], "GBps": ab[k] / (ms * 1e-3) / 1e9}
+    dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
+    achieved = kernels[dom]["GBps"]
+    tr = traffic_record(dom, cfg["name"])
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": tr,
+                "alg_bytes_per_particle": ab["per_particle"][dom], "alg_bytes_per_cell": ab["per_cell"][dom],
+                "kernels": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
+                            for k, v in kernels.items()}}
+    extra = {"cell_updates_per_s": cells * args.steps / r32["wall_s"],
+             "gpu_event_ms_per_step": r32["gpu_ms"] / args.steps,
+             "particles_start_end": [r32["n0"], r32["n1"]]}
+    if not args.no_fp64:
+        s64 = max(10, args.steps // 5)
+        r64 = run_gpu(E, torch, cfg, E.FP64, s64, min(args.warmup, 5), per_kernel=False)
+        extra["fp64_pushes_per_s"] = r64["particles"] * s64 / r64["wall_s"]
+        extra["fp64_steps"] = s64
+        extra["fp32_over_fp64"] = value / extra["fp64_pushes_per_s"]
+    line = {
+        "metric": METRIC, "value": value, "unit": "particle-pushes/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": 1e3 * r32["wall_s"] / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": cfg["name"], "grid": [cfg["nx"], cfg["nr"]], "modes": cfg["n_modes"],
+                   "ppc": list(cfg["ppc"]), "particles": int(r32["particles"]),
+                   "moving_window": bool(cfg["moving_window"]), "precision": "fp32-bulk (fp64 axis rows)"},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(cfg)
+    line["extra"] = extra
+    print(json.dumps(line))
+
+
+if __name__ == "__main__":
+    main()

@@ -101,6 +101,21 @@ template <class R> __device__ inline R wrap_angle(R t) {
   return t;
 }
 
+// Loading order inside a tile: the R particles of a tile, enumerated cell
+// by cell, fill a K-column matrix row by row (K = ceil(R/64)) and are stored
+// column by column.  The 64 lanes of a wavefront then hold particles K apart
+// in the enumeration, i.e. from cells at least four rows apart, so their
+// deposit stencils do not share LDS addresses.  The per-step scatter keeps
+// the relative order of the particles it moves, so the interleaving made at
+// loading persists while every pass reads and writes contiguously.
+__device__ inline int transpose_rank(int r, int R) {
+  const int K = (R + 63) / 64;
+  const int rows = (R + K - 1) / K;
+  const int L = R - (rows - 1) * K;  // columns holding `rows` entries
+  const int m = r % K, q = r / K;
+  return m * rows - max(0, m - L) + q;
+}
+
 // the tile region of a work item: lab column X0 = T TX - HALO, row R0
 struct Region {
   int T, tcx, tcr;
@@ -119,9 +134,13 @@ __device__ inline Region region_of(const Geo& g, int key) {
 }
 
 // ================================================== momentum pass ==
+// Deposits accumulate in FP64 LDS words for both precisions: ds_add_f64 runs
+// at a much higher rate than ds_add_f32 on gfx950 (measured), and the
+// accumulated sums are rounded once, at the flush.
 template <class R, bool M1> struct SmemMom {
   using C = typename cplx_of<R>::type;
-  R ex[LN], er[LN], bt[LN], phi[LN], chi[LN];
+  R ex[LN], er[LN], bt[LN], phi[LN];
+  double chi[LN];
   C ex1[M1 ? LN : 1], er1[M1 ? LN : 1], et1[M1 ? LN : 1];
   C bx1[M1 ? LN : 1], br1[M1 ? LN : 1], bt1[M1 ? LN : 1];
   R ivol[LR];
@@ -155,7 +174,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     R ph = 0;
     if (px && pr) ph = (R)0.5 * cnorm(f.env[o + j]);
     sm.phi[k] = ph;
-    sm.chi[k] = 0;
+    sm.chi[k] = 0.0;
     if (M1) {
       const C z = mk<C>((R)0, (R)0);
       sm.ex1[k] = (dxok && pr) ? f.ex1[o + j] : z;
@@ -280,7 +299,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb) {
           const int nb = Pr.i + bb;
-          lds_add(&sm.chi[(Px.i + aa) * LR + nb], wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivol[nb]);
+          lds_add(&sm.chi[(Px.i + aa) * LR + nb], (double)(wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivol[nb]));
         }
     }
     dst.cell[d] = cw;
@@ -297,7 +316,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   if (DEFER) return;
   __syncthreads();
   for (int k = threadIdx.x; k < LN; k += WG) {
-    const R v = sm.chi[k];
+    const R v = (R)sm.chi[k];
     if (v == (R)0) continue;
     const int a = k / LR, b = k - (k / LR) * LR;
     const int rel = q.relX0 + a, j = q.R0 + b;
@@ -309,8 +328,9 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
 // ================================================== position pass ==
 template <class R, bool M1> struct SmemPos {
   using C = typename cplx_of<R>::type;
-  R phh[LN], jx[LN], jr[LN];
-  C jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
+  R phh[LN];
+  double jx[LN], jr[LN];
+  double2 jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
   R iax[LR], iar[LR], ivn[LR], ivh[LR];
   int hist[9];
 };
@@ -403,7 +423,7 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
 #pragma unroll
     for (int aa = 0; aa < 2; ++aa) {
       acc += (S1x[aa] - S0x[aa]) * sr;
-      if (acc != (R)0) lds_add(&sm.jx[(amin + aa) * LR + bmin + bb], w * acc * sm.iax[bmin + bb]);
+      if (acc != (R)0) lds_add(&sm.jx[(amin + aa) * LR + bmin + bb], (double)(w * acc * sm.iax[bmin + bb]));
     }
   }
   // J_r (i, j+1/2): flux accumulated along r
@@ -414,7 +434,7 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb) {
       acc += (S1r[bb] - S0r[bb]) * sx;
-      if (acc != (R)0) lds_add(&sm.jr[(amin + aa) * LR + bmin + bb], w * acc * sm.iar[bmin + bb]);
+      if (acc != (R)0) lds_add(&sm.jr[(amin + aa) * LR + bmin + bb], (double)(w * acc * sm.iar[bmin + bb]));
     }
   }
   if (M1) {
@@ -456,7 +476,6 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
     const int amc = clampi(am, 1, LX - 3, bad);
     const R vr = mv.vy * c + mv.vz * s, vt = -mv.vy * s + mv.vz * c;
     const R q2 = (R)-2 * w;  // 2 q w, electrons
-    const C e = mk<C>(c, s);
     const Lin<R> Px = primal_w<R>(amc, fm), Dx = dual_w<R>(amc, fm);
     const Lin<R> Pr = primal_w<R>(bm, frm), Dr = dual_w<R>(bm, frm);
 #pragma unroll
@@ -467,20 +486,23 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
         {
           const int nb = Pr.i + bb;
           const R wt = (aa ? Dx.b : Dx.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
-          lds_addc(&sm.jx1[(Dx.i + aa) * LR + nb], cscale(e, q2 * mv.vx * wt));
+          const R v = q2 * mv.vx * wt;
+          lds_addc(&sm.jx1[(Dx.i + aa) * LR + nb], make_double2((double)(v * c), (double)(v * s)));
         }
         // J_r1 at (i, j+1/2); row -1/2 folds onto +1/2 (even for mode 1)
         {
           int nb = Dr.i + bb;
           if (q.R0 + nb == -1) nb += 1;
           const R wt = (aa ? Px.b : Px.a) * (bb ? Dr.b : Dr.a) * sm.ivh[nb];
-          lds_addc(&sm.jr1[(Px.i + aa) * LR + nb], cscale(e, q2 * vr * wt));
+          const R v = q2 * vr * wt;
+          lds_addc(&sm.jr1[(Px.i + aa) * LR + nb], make_double2((double)(v * c), (double)(v * s)));
         }
         // J_t1 at (i, j)
         {
           const int nb = Pr.i + bb;
           const R wt = (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
-          lds_addc(&sm.jt1[(Px.i + aa) * LR + nb], cscale(e, q2 * vt * wt));
+          const R v = q2 * vt * wt;
+          lds_addc(&sm.jt1[(Px.i + aa) * LR + nb], make_double2((double)(v * c), (double)(v * s)));
         }
       }
   }
@@ -503,14 +525,13 @@ __device__ inline void stage_pos_constants(SmemPos<R, M1>& sm, const Region& q, 
 
 template <class R, bool M1>
 __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
-  using C = typename cplx_of<R>::type;
   for (int k = threadIdx.x; k < LN; k += WG) {
-    sm.jx[k] = 0;
-    sm.jr[k] = 0;
+    sm.jx[k] = 0.0;
+    sm.jr[k] = 0.0;
     if (M1) {
-      sm.jx1[k] = mk<C>((R)0, (R)0);
-      sm.jr1[k] = mk<C>((R)0, (R)0);
-      sm.jt1[k] = mk<C>((R)0, (R)0);
+      sm.jx1[k] = make_double2(0.0, 0.0);
+      sm.jr1[k] = make_double2(0.0, 0.0);
+      sm.jt1[k] = make_double2(0.0, 0.0);
     }
   }
   if (threadIdx.x < 9) sm.hist[threadIdx.x] = 0;
@@ -527,20 +548,20 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
     const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
     const bool dxok = rel <= g.nx - 1, drok = j <= g.nr - 1;
-    if (dxok && sm.jx[k] != (R)0) atomicAdd(&jx_out[o], sm.jx[k]);
-    if (drok && sm.jr[k] != (R)0) atomicAdd(&jr_out[o], sm.jr[k]);
+    if (dxok && sm.jx[k] != 0.0) atomicAdd(&jx_out[o], (R)sm.jx[k]);
+    if (drok && sm.jr[k] != 0.0) atomicAdd(&jr_out[o], (R)sm.jr[k]);
     if (M1) {
-      if (dxok && (sm.jx1[k].x != (R)0 || sm.jx1[k].y != (R)0)) {
-        atomicAdd(&jx1_out[o].x, sm.jx1[k].x);
-        atomicAdd(&jx1_out[o].y, sm.jx1[k].y);
+      if (dxok && (sm.jx1[k].x != 0.0 || sm.jx1[k].y != 0.0)) {
+        atomicAdd(&jx1_out[o].x, (R)sm.jx1[k].x);
+        atomicAdd(&jx1_out[o].y, (R)sm.jx1[k].y);
       }
-      if (drok && (sm.jr1[k].x != (R)0 || sm.jr1[k].y != (R)0)) {
-        atomicAdd(&jr1_out[o].x, sm.jr1[k].x);
-        atomicAdd(&jr1_out[o].y, sm.jr1[k].y);
+      if (drok && (sm.jr1[k].x != 0.0 || sm.jr1[k].y != 0.0)) {
+        atomicAdd(&jr1_out[o].x, (R)sm.jr1[k].x);
+        atomicAdd(&jr1_out[o].y, (R)sm.jr1[k].y);
       }
-      if (sm.jt1[k].x != (R)0 || sm.jt1[k].y != (R)0) {
-        atomicAdd(&jt1_out[o].x, sm.jt1[k].x);
-        atomicAdd(&jt1_out[o].y, sm.jt1[k].y);
+      if (sm.jt1[k].x != 0.0 || sm.jt1[k].y != 0.0) {
+        atomicAdd(&jt1_out[o].x, (R)sm.jt1[k].x);
+        atomicAdd(&jt1_out[o].y, (R)sm.jt1[k].y);
       }
     }
   }
@@ -647,7 +668,7 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
 template <class R>
 __global__ __launch_bounds__(WG) void k_deposit_chi(Geo g, R* __restrict__ chi_out, Parts<R> P,
                                                     Layout L, const R* __restrict__ gscr, int* err) {
-  __shared__ R acc[LN];
+  __shared__ double acc[LN];
   __shared__ R ivol[LR];
   const int item = blockIdx.x;
   if (item >= *L.n_items) return;
@@ -672,12 +693,12 @@ __global__ __launch_bounds__(WG) void k_deposit_chi(Geo g, R* __restrict__ chi_o
     for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb)
-        lds_add(&acc[(Px.i + aa) * LR + Pr.i + bb], wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * ivol[Pr.i + bb]);
+        lds_add(&acc[(Px.i + aa) * LR + Pr.i + bb], (double)(wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * ivol[Pr.i + bb]));
   }
   if (bad) atomicOr(err, ERR_HALO);
   __syncthreads();
   for (int k = threadIdx.x; k < LN; k += WG) {
-    const R v = acc[k];
+    const R v = (R)acc[k];
     if (v == (R)0) continue;
     const int a = k / LR, b = k - (k / LR) * LR;
     const int rel = q.relX0 + a, j = q.R0 + b;
@@ -734,8 +755,10 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
 // Plasma of lab cell column `col`, radial cell j (one thread per cell):
 // regular in x and r, one SplitMix64 angle per cell with equally spaced
 // angles inside the cell, weights n 2 pi r (dr/N_r)(dx/N_x)/N_theta.
+// particle k of the cell is stored at base + transpose_rank(r0 + k, n_range)
 template <class R>
-__device__ inline int load_cell(const Geo& g, const Plasma& pl, Parts<R> P, int slot, long long col, int j) {
+__device__ inline int load_cell(const Geo& g, const Plasma& pl, Parts<R> P, int base, int r0, int n_range,
+                                long long col, int j) {
   const double pi = 3.14159265358979323846;
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
   const double th0 = 2.0 * pi * counter_uniform(pl.seed, STREAM_ANGLE, col, j);
@@ -748,7 +771,7 @@ __device__ inline int load_cell(const Geo& g, const Plasma& pl, Parts<R> P, int 
         const double xl = ((double)col + fx) * g.dx;
         const double r = (j + fr) * g.dr;
         const double n = plasma_density(pl, xl, col, j);
-        const int s = slot + k;
+        const int s = base + transpose_rank(r0 + k, n_range);
         P.px[s] = 0;
         P.py[s] = 0;
         P.pz[s] = 0;
@@ -782,10 +805,11 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
   const int col = (int)(cell / g.nr), j = (int)(cell - (long long)col * g.nr);
   const int T = col / TX, tcr = j / TR;
   const int trt = min(TR, g.nr - tcr * TR);
+  const int tct = min(TX, g.nx - T * TX);
   const int key = tile_key(g, col, j);
   const int local = (col - T * TX) * trt + (j - tcr * TR);
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
-  load_cell<R>(g, pl, P, offsets[key] + local * ppc, col, j);
+  load_cell<R>(g, pl, P, offsets[key], local * ppc, tct * trt * ppc, col, j);
 }
 
 // injection of the cell column entering the window after a shift (g holds
@@ -804,7 +828,8 @@ __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict
     return;
   }
   for (int j = threadIdx.x; j < g.nr; j += blockDim.x) {
-    const int live = load_cell<R>(g, pl, P, total + j * ppc, col, j);
+    const int t = j / TR, trt = min(TR, g.nr - t * TR);
+    const int live = load_cell<R>(g, pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j);
     if (live) atomicAdd(&hist[tile_key(g, col, j)], live);
   }
   for (int t = threadIdx.x; t < g.ntr; t += blockDim.x) {
