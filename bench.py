@@ -62,31 +62,22 @@ def traffic_record(kernel, workload):
 
 
 def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True):
+    """Warm up, then time `steps` steps issued by the library's own loop
+    (envpic_step_n) on the simulation's stream.  With `per_kernel`, the
+    library records HIP events around each stage's kernels on that same
+    stream over the timed region."""
     stream = torch.cuda.current_stream()
     sim = E.Sim(cfg, prec, stream=stream)
     sim.step(warmup)
     torch.cuda.synchronize()
     n0 = sim.state()[2]
-    evs = []
+    sim.set_timing(per_kernel)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t_start.record(stream)
-    for _ in range(steps):
-        if per_kernel:
-            e = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
-            e[0].record(stream)
-            sim.momentum()
-            e[1].record(stream)
-            sim.envelope_step()
-            e[2].record(stream)
-            sim.position()
-            e[3].record(stream)
-            sim.field_step()
-            evs.append(e)
-        else:
-            sim.step(1)
+    sim.step(steps)
     t_end.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
@@ -94,8 +85,12 @@ def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True):
     gpu_ms = t_start.elapsed_time(t_end)
     out = {"wall_s": wall, "gpu_ms": gpu_ms, "particles": 0.5 * (n0 + n1), "n0": n0, "n1": n1}
     if per_kernel:
-        out["k_momentum_ms"] = sum(e[0].elapsed_time(e[1]) for e in evs) / steps
-        out["k_position_ms"] = sum(e[2].elapsed_time(e[3]) for e in evs) / steps
+        t = sim.timing()
+        out["k_momentum_ms"] = t["momentum"][0]
+        out["k_position_ms"] = t["position"][0]
+        out["stage_ms"] = {k: round(v[0], 5) for k, v in t.items()}
+        assert t["momentum"][1] == steps and t["position"][1] == steps
+    sim.close()
     del sim
     torch.cuda.empty_cache()
     return out
@@ -128,7 +123,24 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
+                    help="only run a plain device copy of this many MiB, 10 times (reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        n = args.copy_calibration * 2**20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(10):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / 10
+        print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "seconds": dt,
+                          "GBps_read_plus_write": 2 * n / dt / 1e9}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU x-slab "
                                    "decomposition is not built (see DESIGN.md)", "n_gpus": args.gpus}))
@@ -161,6 +173,7 @@ def main():
                             for k, v in kernels.items()}}
     extra = {"cell_updates_per_s": cells * args.steps / r32["wall_s"],
              "gpu_event_ms_per_step": r32["gpu_ms"] / args.steps,
+             "stage_avg_ms": r32["stage_ms"],
              "particles_start_end": [r32["n0"], r32["n1"]]}
     if not args.no_fp64:
         s64 = max(10, args.steps // 5)

@@ -113,6 +113,7 @@ template <class R> struct State {
   Layout lay[2];
   int* hist;
   int* err;
+  int* pending;  // work items appended by the last injection, not yet counted
   double* diag_scratch;
   double* diag_out;
 };
@@ -182,6 +183,7 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   }
   S.hist = cv.take<int>((size_t)s.ntiles);
   S.err = cv.take<int>(1);
+  S.pending = cv.take<int>(1);
   Geo g{};
   g.nx = p.nx;
   g.nr = p.nr;
@@ -210,7 +212,66 @@ struct envpic_sim {
   int cur = 0;       // particle buffer holding the current state
   bool deferred = false, deposit_done = true;
   int chi_last = 0;  // deposit buffer of the last momentum stage
-  virtual ~envpic_sim() {}
+  // stage timing (events on the simulation's stream)
+  struct Tick {
+    int stage;
+    hipEvent_t a, b;
+  };
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  std::vector<Tick> ticks;
+  hipEvent_t ev_open = nullptr;
+  double t_ms[4] = {0, 0, 0, 0};
+  int64_t t_n[4] = {0, 0, 0, 0};
+
+  hipEvent_t take_event() {
+    if (!ev_pool.empty()) {
+      hipEvent_t e = ev_pool.back();
+      ev_pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  void tick_begin() {
+    if (!timing) return;
+    ev_open = take_event();
+    if (ev_open) (void)hipEventRecord(ev_open, stream);
+  }
+  void tick_end(int stage) {
+    if (!timing || !ev_open) return;
+    hipEvent_t e = take_event();
+    if (!e) return;
+    (void)hipEventRecord(e, stream);
+    ticks.push_back(Tick{stage, ev_open, e});
+    ev_open = nullptr;
+    if (ticks.size() >= 4096) resolve_ticks();
+  }
+  int resolve_ticks() {
+    if (ticks.empty()) return ENVPIC_OK;
+    if (hipEventSynchronize(ticks.back().b) != hipSuccess) return ENVPIC_EDEVICE;
+    for (const Tick& t : ticks) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, t.a, t.b) == hipSuccess) {
+        t_ms[t.stage] += ms;
+        t_n[t.stage] += 1;
+      }
+      ev_pool.push_back(t.a);
+      ev_pool.push_back(t.b);
+    }
+    ticks.clear();
+    return ENVPIC_OK;
+  }
+  virtual ~envpic_sim() {
+    if (!ticks.empty()) (void)hipEventSynchronize(ticks.back().b);
+    for (const Tick& t : ticks) {
+      (void)hipEventDestroy(t.a);
+      (void)hipEventDestroy(t.b);
+    }
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+    if (ev_open) (void)hipEventDestroy(ev_open);
+  }
   virtual int init() = 0;
   virtual int momentum(bool defer) = 0;
   virtual int project(int what) = 0;
@@ -314,7 +375,8 @@ template <class R> struct SimT : envpic_sim {
   int rebuild_next_layout() {
     const Geo g = geo();
     launch_hist<R>(g, S.parts[cur], S.lay[cur], S.hist, sz.max_items, stream);
-    launch_scan(g, S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.err, stream);
+    launch_scan(g, S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items, S.pending,
+                S.err, stream);
     return launched("hist/scan");
   }
 
@@ -371,8 +433,10 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 0) return fail(ENVPIC_EORDER, "momentum stage out of order");
     const Geo g = geo();
     const int d = (int)(n & 1);
+    tick_begin();
     launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.scr.w,
                        S.err, sz.max_items, defer, stream);
+    tick_end(0);
     cur = 1 - cur;
     chi_last = d;
     stage = 1;
@@ -400,7 +464,9 @@ template <class R> struct SimT : envpic_sim {
   int envelope() override {
     if (stage != 1 || !deposit_done) return fail(ENVPIC_EORDER, "envelope stage out of order");
     const Geo g = geo();
+    tick_begin();
     launch_envelope<R>(g, S.grids, S.dep[n & 1].chi, fp64_rows ? 1 : 0, stream);
+    tick_end(1);
     std::swap(S.grids.env, S.grids.envp);
     std::swap(S.grids.ax, S.grids.axp);
     stage = 2;
@@ -410,8 +476,10 @@ template <class R> struct SimT : envpic_sim {
   int position(bool defer) override {
     if (stage != 2) return fail(ENVPIC_EORDER, "position stage out of order");
     const Geo g = geo();
+    tick_begin();
     launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.hist, shift_due() ? 1 : 0, S.scr, S.err,
                        sz.max_items, defer, stream);
+    tick_end(2);
     stage = 3;
     deferred = defer;
     deposit_done = !defer;
@@ -420,15 +488,19 @@ template <class R> struct SimT : envpic_sim {
 
   int field() override {
     if (stage != 3 || !deposit_done) return fail(ENVPIC_EORDER, "field stage out of order");
+    tick_begin();
     launch_maxwell<R>(geo(), S.grids, S.dep[n & 1], S.dep[(n + 1) & 1], stream);
     if (shift_due()) {
       shift += 1;
       const Geo g = geo();
       launch_window<R>(g, S.grids, S.dep[0], S.dep[1], fp64_rows ? 1 : 0, stream);
       if (p.profile != ENVPIC_PROFILE_NONE)
-        launch_inject<R>(g, plasma(), S.parts[cur], S.lay[cur], S.hist, sz.capacity, sz.max_items, S.err, stream);
+        launch_inject<R>(g, plasma(), S.parts[cur], S.lay[cur], S.hist, sz.capacity, sz.max_items, S.pending, S.err,
+                         stream);
     }
-    launch_scan(geo(), S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.err, stream);
+    launch_scan(geo(), S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items,
+                S.pending, S.err, stream);
+    tick_end(3);
     n += 1;
     stage = 0;
     return launched("field stage");
@@ -866,6 +938,29 @@ int envpic_set_particles(envpic_sim* s, int64_t n, const double* x, const double
   if (n > 0 && (!x || !y || !z || !px || !py || !pz || !w || !id)) return fail(ENVPIC_EINVAL, "NULL particle array");
   const double* cols[7] = {x, y, z, px, py, pz, w};
   return s->set_particles(n, cols, id);
+}
+
+int envpic_set_timing(envpic_sim* s, int enable) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  int rc = s->resolve_ticks();
+  if (rc) return fail(rc, "timing events failed");
+  for (int k = 0; k < 4; ++k) {
+    s->t_ms[k] = 0.0;
+    s->t_n[k] = 0;
+  }
+  s->timing = enable != 0;
+  return ENVPIC_OK;
+}
+
+int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  int rc = s->resolve_ticks();
+  if (rc) return fail(rc, "timing events failed");
+  for (int k = 0; k < 4; ++k) {
+    if (out_ms) out_ms[k] = s->t_n[k] ? s->t_ms[k] / (double)s->t_n[k] : 0.0;
+    if (counts) counts[k] = s->t_n[k];
+  }
+  return ENVPIC_OK;
 }
 
 int envpic_diagnostics(const envpic_sim* s, double* out) {

@@ -22,7 +22,6 @@ constexpr int LR = TR + 2 * HALO + 1;
 constexpr int LN = LX * LR; // nodes of an LDS tile region
 constexpr int WG = 256;     // work-group size of the particle kernels
 constexpr int CHUNK = 4096; // max particles per work item
-constexpr int PPT = CHUNK / WG;
 // A particle's cell is one 32-bit word: lab column << 12 | radial row.  The
 // position inside the cell is kept as FP32 (or FP64) offsets along x and r,
 // so neither a long moving-window run nor a large radius erodes the

@@ -29,7 +29,7 @@ template <class R>
 void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, const int* offsets, hipStream_t st);
 template <class R>
 void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* hist, long long capacity,
-                   int max_items, int* err, hipStream_t st);
+                   int max_items, int* pending, int* err, hipStream_t st);
 template <class R>
 void launch_hist(const Geo& g, const Parts<R>& P, const Layout& L, int* hist, int grid, hipStream_t st);
 
@@ -44,8 +44,9 @@ void launch_window(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d0, co
 template <class R>
 void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st);
 
+// `pending` items appended by an injection are added to *bump_items first
 void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* err, hipStream_t st);
+                 int* bump_items, int* pending, int* err, hipStream_t st);
 
 int diag_scratch_doubles(int max_items, const Geo& g);
 template <class R>

@@ -16,6 +16,8 @@
 // new radius is obtained from the radial and azimuthal components of the
 // displacement without cancellation, so the offsets keep their resolution at
 // any radius.
+#include <algorithm>
+
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
@@ -64,8 +66,32 @@ __device__ inline void lds_addc(double2* a, double2 v) {
   atomicAdd(&a->y, v.y);
 }
 
-__device__ inline void sincos_r(float t, float* s, float* c) { sincosf(t, s, c); }
+// Elementary functions.  The FP32 path uses the hardware reciprocal and
+// sine/cosine (direction cosines of the azimuth, relative error ~1e-6, far
+// inside the FP32 path's tolerance); the FP64 path uses the libm calls.
+__device__ inline float rsqrt_r(float x) { return rsqrtf(x); }
+__device__ inline double rsqrt_r(double x) { return rsqrt(x); }
+__device__ inline float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ inline double rcp_r(double x) { return 1.0 / x; }
+__device__ inline void sincos_r(float t, float* s, float* c) {
+  *s = __sinf(t);
+  *c = __cosf(t);
+}
 __device__ inline void sincos_r(double t, double* s, double* c) { sincos(t, s, c); }
+// azimuth increment atan2(b, ra); in FP32, for ra > 0 and |b/ra| < 0.05 the
+// odd series beta - beta^3/3 + beta^5/5 (truncation below beta^7/7 < 1.2e-10,
+// under the FP32 resolution of the azimuth)
+__device__ inline float dtheta(float b, float ra) {
+  if (ra > 0.0f) {
+    const float beta = b * rcp_r(ra);
+    if (fabsf(beta) < 0.05f) {
+      const float b2 = beta * beta;
+      return beta * (1.0f - b2 * (1.0f / 3.0f - b2 * 0.2f));
+    }
+  }
+  return atan2f(b, ra);
+}
+__device__ inline double dtheta(double b, double ra) { return atan2(b, ra); }
 
 // carry an offset back into [0, 1): cell += floor(off), off -= floor(off)
 template <class R> __device__ inline void carry(int& cell, R& off) {
@@ -85,13 +111,13 @@ template <class R> __device__ inline void carry(int& cell, R& off) {
 template <class R> __device__ inline void radial_step(R r, R a, R b, R& dr_out, R& dth) {
   const R ra = r + a;
   if (ra > (R)0) {
-    const R beta = b / ra;
+    const R beta = b * rcp_r(ra);
     const R q = sqrt((R)1 + beta * beta);
-    dr_out = a + ra * beta * beta / ((R)1 + q);
+    dr_out = a + ra * beta * beta * rcp_r((R)1 + q);
   } else {
     dr_out = sqrt(ra * ra + b * b) - r;
   }
-  dth = atan2(b, ra);
+  dth = dtheta(b, ra);
 }
 
 template <class R> __device__ inline R wrap_angle(R t) {
@@ -119,7 +145,7 @@ __device__ inline int transpose_rank(int r, int R) {
 // the tile region of a work item: lab column X0 = T TX - HALO, row R0
 struct Region {
   int T, tcx, tcr;
-  long long X0;
+  int X0;  // lab column (lab columns fit 20 bits)
   int relX0, R0;
 };
 __device__ inline Region region_of(const Geo& g, int key) {
@@ -127,8 +153,8 @@ __device__ inline Region region_of(const Geo& g, int key) {
   q.tcx = key / g.ntr;
   q.tcr = key - q.tcx * g.ntr;
   q.T = lab_tile(g, q.tcx);
-  q.X0 = (long long)q.T * TX - HALO;
-  q.relX0 = (int)(q.X0 - g.shift);
+  q.X0 = q.T * TX - HALO;
+  q.relX0 = (int)((long long)q.X0 - g.shift);
   q.R0 = q.tcr * TR - HALO;
   return q;
 }
@@ -139,13 +165,14 @@ __device__ inline Region region_of(const Geo& g, int key) {
 // accumulated sums are rounded once, at the flush.
 template <class R, bool M1> struct SmemMom {
   using C = typename cplx_of<R>::type;
-  R ex[LN], er[LN], bt[LN], phi[LN];
+  R ex[LN], er[LN], bt[LN], phi[LN], gx[LN], gr[LN];
   double chi[LN];
   C ex1[M1 ? LN : 1], er1[M1 ? LN : 1], et1[M1 ? LN : 1];
   C bx1[M1 ? LN : 1], br1[M1 ? LN : 1], bt1[M1 ? LN : 1];
   R ivol[LR];
   int cnt[9], base[9];
 };
+constexpr int PPT = CHUNK / WG;  // particles per thread of a work item
 
 template <class R, bool M1, bool DEFER>
 __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restrict__ chi_out,
@@ -158,7 +185,6 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   const int4 it = Ls.items[item];
   const int start = it.y, count = it.z;
   const Region q = region_of(g, it.x);
-  const R inv_dx = (R)(1.0 / g.dx), inv_dr = (R)(1.0 / g.dr);
   const R hdt = (R)(0.5 * g.dt);
 
   // ---- stage E, Bbar, Phi (and mode 1) of the region in LDS
@@ -191,8 +217,24 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   }
   if (threadIdx.x < 9) sm.cnt[threadIdx.x] = 0;
   __syncthreads();
+  // grad Phi by centred differences on the primal nodes (zero radial
+  // derivative on the axis); the outermost ring of the region is unused
+  {
+    const R i2dx = (R)(0.5 / g.dx), i2dr = (R)(0.5 / g.dr);
+    for (int k = threadIdx.x; k < LN; k += WG) {
+      const int a = k / LR, b = k - (k / LR) * LR;
+      R vx = 0, vr = 0;
+      if (a >= 1 && a <= LX - 2 && b >= 1 && b <= LR - 2) {
+        vx = (sm.phi[k + LR] - sm.phi[k - LR]) * i2dx;
+        if (q.R0 + b != 0) vr = (sm.phi[k + 1] - sm.phi[k - 1]) * i2dr;
+      }
+      sm.gx[k] = vx;
+      sm.gr[k] = vr;
+    }
+  }
 
-  // ---- destination tile (3 x 3 neighbourhood) and rank of each particle
+  // ---- destination tile (3 x 3 neighbourhood) and rank of each particle,
+  // kept in registers (the loops over a thread's particles are unrolled)
   int slot_rank[PPT];
   bool bad = false;
 #pragma unroll
@@ -223,7 +265,6 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   __syncthreads();
 
   // ---- gather, push, deposit, scatter
-  const R i2dx = (R)0.5 * inv_dx, i2dr = (R)0.5 * inv_dr;
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (slot_rank[u] < 0) continue;
@@ -236,7 +277,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     const unsigned cw = src.cell[p];
     const R fx = src.fx[p], fr = src.fr[p], th = src.th[p], w = src.w[p];
     R pv[3] = {src.px[p], src.py[p], src.pz[p]};
-    const int a = clampi((int)((long long)cell_ix(cw) - q.X0), 1, LX - 3, bad);
+    const int a = clampi(cell_ix(cw) - q.X0, 1, LX - 3, bad);
     const int b = clampi(cell_jr(cw) - q.R0, 1, LR - 3, bad);
     const Lin<R> Px = primal_w<R>(a, fx), Dx = dual_w<R>(a, fx);
     const Lin<R> Pr = primal_w<R>(b, fr), Dr = dual_w<R>(b, fr);
@@ -247,17 +288,8 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     R bt = interp2<R>(sm.bt, Dx, Dr);
     R et = 0, bx = 0, br = 0;
     const R ph = interp2<R>(sm.phi, Px, Pr);
-    // centred differences of Phi at the four primal nodes, then interpolated
-    R gx = 0, gr = 0;
-#pragma unroll
-    for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-      for (int bb = 0; bb < 2; ++bb) {
-        const int na = Px.i + aa, nb = Pr.i + bb;
-        const R wgt = (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a);
-        gx += wgt * (sm.phi[(na + 1) * LR + nb] - sm.phi[(na - 1) * LR + nb]) * i2dx;
-        if (q.R0 + nb != 0) gr += wgt * (sm.phi[na * LR + nb + 1] - sm.phi[na * LR + nb - 1]) * i2dr;
-      }
+    const R gx = interp2<R>(sm.gx, Px, Pr);
+    const R gr = interp2<R>(sm.gr, Px, Pr);
     if (M1) {
       ex += mode1_at<C, R>(interp2c<C, R>(sm.ex1, Dx, Pr), c, s);
       er += mode1_at<C, R>(interp2c<C, R>(sm.er1, Px, Dr), c, s);
@@ -272,16 +304,15 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     const R G[3] = {gx, gr * c, gr * s};
     // ponderomotive Boris: half kick with gbar(p^{n-1/2}), rotation and chi
     // with gbar of the half-kicked momentum, second half kick
-    const R g0 = sqrt((R)1 + pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2] + ph);
-    const R ig0 = (R)0.5 / g0;
+    const R ig0 = (R)0.5 * rsqrt_r((R)1 + pv[0] * pv[0] + pv[1] * pv[1] + pv[2] * pv[2] + ph);
     R F[3], pm[3];
 #pragma unroll
     for (int e = 0; e < 3; ++e) {
       F[e] = -E[e] - G[e] * ig0;
       pm[e] = pv[e] + hdt * F[e];
     }
-    const R gb = sqrt((R)1 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2] + ph);
-    const R tf = -hdt / gb;
+    const R igb = rsqrt_r((R)1 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2] + ph);
+    const R tf = -hdt * igb;
     const R t[3] = {tf * B[0], tf * B[1], tf * B[2]};
     const R sf = (R)2 / ((R)1 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     const R sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
@@ -291,9 +322,9 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     pv[1] = pm[1] + pp[2] * sv[0] - pp[0] * sv[2] + hdt * F[1];
     pv[2] = pm[2] + pp[0] * sv[1] - pp[1] * sv[0] + hdt * F[2];
     if (DEFER) {
-      gscr[d] = gb;
+      gscr[d] = (R)1 / igb;
     } else {
-      const R wg = w / gb;
+      const R wg = w * igb;
 #pragma unroll
       for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
@@ -341,6 +372,7 @@ template <class R> struct Move {
   int ix0, jr0, ix1, jr1;
   R fx0, fr0, fx1, fr1;
   R th0, th1, a, b;
+  R c0, s0;  // cos, sin of the old azimuth
   bool refl;
   R vx, vy, vz;
 };
@@ -364,6 +396,8 @@ __device__ inline void push_position(const Geo& g, unsigned cw, R fx, R fr, R th
   carry(mv.ix1, mv.fx1);
   R s, c;
   sincos_r(th, &s, &c);
+  mv.c0 = c;
+  mv.s0 = s;
   const R dy = dt * vy, dz = dt * vz;
   mv.a = c * dy + s * dz;
   mv.b = -s * dy + c * dz;
@@ -371,7 +405,7 @@ __device__ inline void push_position(const Geo& g, unsigned cw, R fx, R fr, R th
   R drad, dth;
   radial_step(r, mv.a, mv.b, drad, dth);
   mv.jr1 = mv.jr0;
-  mv.fr1 = fr + drad / dr;
+  mv.fr1 = fr + drad * (R)(1.0 / g.dr);
   carry(mv.jr1, mv.fr1);
   if (mv.jr1 < 0) {
     mv.jr1 = 0;
@@ -399,64 +433,73 @@ __device__ inline void push_position(const Geo& g, unsigned cw, R fx, R fr, R th
 template <class R, bool M1>
 __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, const Geo& g, const Move<R>& mv, R w,
                                        bool& bad) {
-  using C = typename cplx_of<R>::type;
   // the stencil spans min(a0, a1) .. min(a0, a1) + 2 (at most one cell moved)
-  const int a0 = clampi((int)((long long)mv.ix0 - q.X0), 1, LX - 4, bad);
-  const int a1 = clampi((int)((long long)mv.ix1 - q.X0), a0 - 1, a0 + 1, bad);
+  const int a0 = clampi(mv.ix0 - q.X0, 1, LX - 4, bad);
+  const int a1 = clampi(mv.ix1 - q.X0, a0 - 1, a0 + 1, bad);
   const int b0 = clampi(mv.jr0 - q.R0, 1, LR - 4, bad);
   const int b1 = clampi(mv.jr1 - q.R0, b0 - 1, b0 + 1, bad);
-  const int amin = min(a0, a1), bmin = min(b0, b1);
-  R S0x[3] = {0, 0, 0}, S1x[3] = {0, 0, 0}, S0r[3] = {0, 0, 0}, S1r[3] = {0, 0, 0};
-  S0x[a0 - amin] += (R)1 - mv.fx0;
-  S0x[a0 - amin + 1] += mv.fx0;
-  S1x[a1 - amin] += (R)1 - mv.fx1;
-  S1x[a1 - amin + 1] += mv.fx1;
-  S0r[b0 - bmin] += (R)1 - mv.fr0;
-  S0r[b0 - bmin + 1] += mv.fr0;
-  S1r[b1 - bmin] += (R)1 - mv.fr1;
-  S1r[b1 - bmin + 1] += mv.fr1;
+  // node weights on the 3-node union of the old and new supports, without
+  // indexing into register arrays: d = a1 - a0 in {-1, 0, 1}
+  const int dxs = a1 - a0, drs = b1 - b0;
+  const int amin = a0 + min(dxs, 0), bmin = b0 + min(drs, 0);
+  const R u0 = (R)1 - mv.fx0, u1 = (R)1 - mv.fx1, v0 = (R)1 - mv.fr0, v1 = (R)1 - mv.fr1;
+  const R S0x[3] = {dxs >= 0 ? u0 : (R)0, dxs >= 0 ? mv.fx0 : u0, dxs >= 0 ? (R)0 : mv.fx0};
+  const R S1x[3] = {dxs <= 0 ? u1 : (R)0, dxs <= 0 ? mv.fx1 : u1, dxs <= 0 ? (R)0 : mv.fx1};
+  const R S0r[3] = {drs >= 0 ? v0 : (R)0, drs >= 0 ? mv.fr0 : v0, drs >= 0 ? (R)0 : mv.fr0};
+  const R S1r[3] = {drs <= 0 ? v1 : (R)0, drs <= 0 ? mv.fr1 : v1, drs <= 0 ? (R)0 : mv.fr1};
   // J_x (i+1/2, j): flux accumulated along x; the third partial sum is zero
+  const R cx0 = S1x[0] - S0x[0], cx1 = cx0 + S1x[1] - S0x[1];
+  const R cr0 = S1r[0] - S0r[0], cr1 = cr0 + S1r[1] - S0r[1];
+  double* jx = &sm.jx[amin * LR + bmin];
+  double* jr = &sm.jr[amin * LR + bmin];
 #pragma unroll
   for (int bb = 0; bb < 3; ++bb) {
-    const R sr = (S0r[bb] + S1r[bb]) * (R)0.5;
-    R acc = 0;
-#pragma unroll
-    for (int aa = 0; aa < 2; ++aa) {
-      acc += (S1x[aa] - S0x[aa]) * sr;
-      if (acc != (R)0) lds_add(&sm.jx[(amin + aa) * LR + bmin + bb], (double)(w * acc * sm.iax[bmin + bb]));
-    }
+    const R sr = (S0r[bb] + S1r[bb]) * (R)0.5 * w * sm.iax[bmin + bb];
+    if (cx0 != (R)0) lds_add(&jx[bb], (double)(cx0 * sr));
+    if (cx1 != (R)0) lds_add(&jx[LR + bb], (double)(cx1 * sr));
   }
   // J_r (i, j+1/2): flux accumulated along r
 #pragma unroll
   for (int aa = 0; aa < 3; ++aa) {
-    const R sx = (S0x[aa] + S1x[aa]) * (R)0.5;
-    R acc = 0;
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb) {
-      acc += (S1r[bb] - S0r[bb]) * sx;
-      if (acc != (R)0) lds_add(&sm.jr[(amin + aa) * LR + bmin + bb], (double)(w * acc * sm.iar[bmin + bb]));
-    }
+    const R sx = (S0x[aa] + S1x[aa]) * (R)0.5 * w;
+    if (cr0 != (R)0) lds_add(&jr[aa * LR], (double)(cr0 * sx * sm.iar[bmin]));
+    if (cr1 != (R)0) lds_add(&jr[aa * LR + 1], (double)(cr1 * sx * sm.iar[bmin + 1]));
   }
   if (M1) {
-    // Cartesian mid-point of the old and new positions
+    // Cartesian mid-point of the old and new positions: in the frame of the
+    // old azimuth it sits at (r0 + a/2, b/2); its radius and direction follow
+    // without trigonometric calls
     const R dr = (R)g.dr;
     const R r0 = ((R)mv.jr0 + mv.fr0) * dr;
     int jm = mv.jr0;
-    R frm, thm;
+    R frm, c, s;
     if (!mv.refl) {
-      R dm, dthm;
-      radial_step(r0, (R)0.5 * mv.a, (R)0.5 * mv.b, dm, dthm);
-      frm = mv.fr0 + dm / dr;
-      thm = mv.th0 + dthm;
+      const R u = r0 + (R)0.5 * mv.a, v = (R)0.5 * mv.b;
+      R cd, sd;
+      if (u > (R)0) {
+        const R beta = v * rcp_r(u);
+        const R qq = sqrt((R)1 + beta * beta);
+        frm = mv.fr0 + ((R)0.5 * mv.a + u * beta * beta * rcp_r((R)1 + qq)) * (R)(1.0 / g.dr);
+        cd = rcp_r(qq);
+        sd = beta * cd;
+      } else {
+        const R rm = sqrt(u * u + v * v);
+        frm = mv.fr0 + (rm - r0) / dr;
+        cd = rm > (R)0 ? u / rm : (R)1;
+        sd = rm > (R)0 ? v / rm : (R)0;
+      }
+      c = mv.c0 * cd - mv.s0 * sd;
+      s = mv.s0 * cd + mv.c0 * sd;
     } else {
-      R s0, c0, s1, c1;
-      sincos_r(mv.th0, &s0, &c0);
+      R s1, c1;
       sincos_r(mv.th1, &s1, &c1);
       const R r1 = ((R)mv.jr1 + mv.fr1) * dr;
-      const R ym = (R)0.5 * (r0 * c0 + r1 * c1), zm = (R)0.5 * (r0 * s0 + r1 * s1);
+      const R ym = (R)0.5 * (r0 * mv.c0 + r1 * c1), zm = (R)0.5 * (r0 * mv.s0 + r1 * s1);
+      const R rm = sqrt(ym * ym + zm * zm);
       jm = 0;
-      frm = sqrt(ym * ym + zm * zm) / dr;
-      thm = atan2(zm, ym);
+      frm = rm / dr;
+      c = rm > (R)0 ? ym / rm : (R)1;
+      s = rm > (R)0 ? zm / rm : (R)0;
     }
     carry(jm, frm);
     if (jm < 0) {
@@ -467,8 +510,6 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
       frm += (R)(jm - (g.nr - 1));
       jm = g.nr - 1;
     }
-    R s, c;
-    sincos_r(thm, &s, &c);
     const R um = (R)0.5 * ((R)a0 + mv.fx0 + (R)a1 + mv.fx1);
     const int am = (int)floor(um);
     const R fm = um - (R)am;
@@ -620,11 +661,10 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
     const R fx = P.fx[p], fr = P.fr[p], th = P.th[p], w = P.w[p];
     const R px = P.px[p];
     R py = P.py[p], pz = P.pz[p];
-    const int a = clampi((int)((long long)cell_ix(cw) - q.X0), 0, LX - 2, bad);
+    const int a = clampi(cell_ix(cw) - q.X0, 0, LX - 2, bad);
     const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
     const R ph = interp2<R>(sm.phh, primal_w<R>(a, fx), primal_w<R>(b, fr));
-    const R gm = sqrt((R)1 + px * px + py * py + pz * pz + ph);
-    const R ig = (R)1 / gm;
+    const R ig = rsqrt_r((R)1 + px * px + py * py + pz * pz + ph);
     Move<R> mv;
     push_position<R>(g, cw, fx, fr, th, py, pz, px * ig, py * ig, pz * ig, mv);
     if (mv.refl) {
@@ -641,7 +681,7 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
       scr.fx[p] = fx;
       scr.fr[p] = fr;
       scr.th[p] = th;
-      scr.w[p] = mv.refl ? -gm : gm;
+      scr.w[p] = mv.refl ? -ig : ig;
     } else {
       deposit_current<R, M1>(sm, q, g, mv, w, bad);
     }
@@ -685,7 +725,7 @@ __global__ __launch_bounds__(WG) void k_deposit_chi(Geo g, R* __restrict__ chi_o
     const int p = it.y + k;
     const unsigned cw = P.cell[p];
     if (cw == kDead) continue;
-    const int a = clampi((int)((long long)cell_ix(cw) - q.X0), 0, LX - 2, bad);
+    const int a = clampi(cell_ix(cw) - q.X0, 0, LX - 2, bad);
     const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
     const Lin<R> Px = primal_w<R>(a, P.fx[p]), Pr = primal_w<R>(b, P.fr[p]);
     const R wg = P.w[p] / gscr[p];
@@ -737,7 +777,7 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
       py -= (R)2 * prad * c1;
       pz -= (R)2 * prad * s1;
     }
-    const R ig = (R)1 / fabs(gm);
+    const R ig = fabs(gm);
     // replay the push from the kept old position: the same arithmetic as the
     // fused position pass, hence the same move
     Move<R> mv;
@@ -752,48 +792,43 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
 }
 
 // ============================================== loading / injection ==
-// Plasma of lab cell column `col`, radial cell j (one thread per cell):
-// regular in x and r, one SplitMix64 angle per cell with equally spaced
-// angles inside the cell, weights n 2 pi r (dr/N_r)(dx/N_x)/N_theta.
-// particle k of the cell is stored at base + transpose_rank(r0 + k, n_range)
+// Plasma of lab cell column `col`, radial cell j: regular in x and r, one
+// SplitMix64 angle per cell with equally spaced angles inside the cell,
+// weights n 2 pi r (dr/N_r)(dx/N_x)/N_theta.  Particle k of the cell is
+// stored at base + transpose_rank(r0 + k, n_range).  Returns 1 if live.
 template <class R>
-__device__ inline int load_cell(const Geo& g, const Plasma& pl, Parts<R> P, int base, int r0, int n_range,
-                                long long col, int j) {
+__device__ inline int load_particle(const Geo& g, const Plasma& pl, Parts<R> P, int base, int r0, int n_range,
+                                    long long col, int j, int k) {
   const double pi = 3.14159265358979323846;
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
+  const int t = k % g.ppc_t, b = (k / g.ppc_t) % g.ppc_r, a = k / (g.ppc_t * g.ppc_r);
+  const double fx = (a + 0.5) / g.ppc_x, fr = (b + 0.5) / g.ppc_r;
+  const double xl = ((double)col + fx) * g.dx;
+  const double r = (j + fr) * g.dr;
+  const double n = plasma_density(pl, xl, col, j);
+  const int s = base + transpose_rank(r0 + k, n_range);
+  P.px[s] = 0;
+  P.py[s] = 0;
+  P.pz[s] = 0;
+  P.id[s] = (uint32_t)(col * (long long)g.nr * ppc + (long long)j * ppc + k);
+  if (!(n > 0.0)) {
+    P.cell[s] = kDead;
+    P.fx[s] = 0;
+    P.fr[s] = 0;
+    P.th[s] = 0;
+    P.w[s] = 0;
+    return 0;
+  }
   const double th0 = 2.0 * pi * counter_uniform(pl.seed, STREAM_ANGLE, col, j);
-  int live = 0;
-  int k = 0;
-  for (int a = 0; a < g.ppc_x; ++a)
-    for (int b = 0; b < g.ppc_r; ++b)
-      for (int t = 0; t < g.ppc_t; ++t, ++k) {
-        const double fx = (a + 0.5) / g.ppc_x, fr = (b + 0.5) / g.ppc_r;
-        const double xl = ((double)col + fx) * g.dx;
-        const double r = (j + fr) * g.dr;
-        const double n = plasma_density(pl, xl, col, j);
-        const int s = base + transpose_rank(r0 + k, n_range);
-        P.px[s] = 0;
-        P.py[s] = 0;
-        P.pz[s] = 0;
-        P.id[s] = (uint32_t)(col * (long long)g.nr * ppc + (long long)j * ppc + (a * g.ppc_r + b) * g.ppc_t + t);
-        if (!(n > 0.0)) {
-          P.cell[s] = kDead;
-          P.fx[s] = 0;
-          P.fr[s] = 0;
-          P.th[s] = 0;
-          P.w[s] = 0;
-          continue;
-        }
-        double th = th0 + 2.0 * pi * t / g.ppc_t;
-        th = atan2(sin(th), cos(th));
-        P.cell[s] = pack_cell((int)col, j);
-        P.fx[s] = (R)fx;
-        P.fr[s] = (R)fr;
-        P.th[s] = (R)th;
-        P.w[s] = (R)(n * 2.0 * pi * r * (g.dr / g.ppc_r) * (g.dx / g.ppc_x) / g.ppc_t);
-        ++live;
-      }
-  return live;
+  double th = th0 + 2.0 * pi * t / g.ppc_t;  // in [0, 4 pi): fold into (-pi, pi]
+  if (th > pi) th -= 2.0 * pi;
+  if (th > pi) th -= 2.0 * pi;
+  P.cell[s] = pack_cell((int)col, j);
+  P.fx[s] = (R)fx;
+  P.fr[s] = (R)fr;
+  P.th[s] = (R)th;
+  P.w[s] = (R)(n * 2.0 * pi * r * (g.dr / g.ppc_r) * (g.dx / g.ppc_x) / g.ppc_t);
+  return 1;
 }
 
 // initial loading of window cells in tile-major order (offsets per tile
@@ -809,35 +844,46 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
   const int key = tile_key(g, col, j);
   const int local = (col - T * TX) * trt + (j - tcr * TR);
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
-  load_cell<R>(g, pl, P, offsets[key], local * ppc, tct * trt * ppc, col, j);
+  for (int k = 0; k < ppc; ++k) load_particle<R>(g, pl, P, offsets[key], local * ppc, tct * trt * ppc, col, j, k);
 }
 
 // injection of the cell column entering the window after a shift (g holds
-// the new shift); particles are appended after the live range of P and get
-// one work item per tile row (one work group: the item count is updated
-// after all reads of it)
+// the new shift), one thread per particle; particles are appended after the
+// live range of P and get one work item per tile row.  The item count of L
+// is raised by the scan that follows (via *pending), after every block has
+// read it here.
 template <class R>
 __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict__ hist, long long capacity,
-                         int max_items, int* err) {
+                         int max_items, int* __restrict__ pending, int* err) {
   const long long col = g.shift + g.nx - 1;
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
   const int total = L.offsets[g.ntiles];
   const int base_items = *L.n_items;
   if ((long long)total + (long long)g.nr * ppc > capacity || base_items + g.ntr > max_items || col > COL_MAX) {
-    if (threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
     return;
   }
-  for (int j = threadIdx.x; j < g.nr; j += blockDim.x) {
+  // live particles per tile row, counted in LDS first (a block spans at most
+  // blockDim / ppc + 1 rows, i.e. a few tile rows)
+  __shared__ int s_cnt[64];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j_first = (blockIdx.x * blockDim.x) / ppc;
+  for (int k = threadIdx.x; k < 64; k += blockDim.x) s_cnt[k] = 0;
+  __syncthreads();
+  if (idx < g.nr * ppc) {
+    const int j = idx / ppc, k = idx - (idx / ppc) * ppc;
     const int t = j / TR, trt = min(TR, g.nr - t * TR);
-    const int live = load_cell<R>(g, pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j);
-    if (live) atomicAdd(&hist[tile_key(g, col, j)], live);
-  }
-  for (int t = threadIdx.x; t < g.ntr; t += blockDim.x) {
-    const int trt = min(TR, g.nr - t * TR);
-    L.items[base_items + t] = make_int4(tile_key(g, col, t * TR), total + t * TR * ppc, trt * ppc, 0);
+    if (load_particle<R>(g, pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j, k))
+      atomicAdd(&s_cnt[min(63, t - j_first / TR)], 1);
   }
   __syncthreads();
-  if (threadIdx.x == 0) *L.n_items = base_items + g.ntr;
+  if (threadIdx.x < 64 && s_cnt[threadIdx.x] > 0)
+    atomicAdd(&hist[tile_key(g, col, (j_first / TR + threadIdx.x) * TR)], s_cnt[threadIdx.x]);
+  if (idx < g.ntr) {
+    const int trt = min(TR, g.nr - idx * TR);
+    L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), total + idx * TR * ppc, trt * ppc, 0);
+  }
+  if (idx == 0) *pending = g.ntr;
 }
 
 // counts of live particles per tile of their current position
@@ -915,8 +961,10 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
 
 template <class R>
 void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* hist, long long capacity,
-                   int max_items, int* err, hipStream_t st) {
-  hipLaunchKernelGGL((k_inject<R>), dim3(1), dim3(1024), 0, st, g, pl, P, L, hist, capacity, max_items, err);
+                   int max_items, int* pending, int* err, hipStream_t st) {
+  const int n = std::max(g.nr * g.ppc_x * g.ppc_r * g.ppc_t, g.ntr);
+  hipLaunchKernelGGL((k_inject<R>), dim3((n + 255) / 256), dim3(256), 0, st, g, pl, P, L, hist, capacity, max_items,
+                     pending, err);
 }
 
 template <class R>
@@ -936,7 +984,7 @@ void launch_hist(const Geo& g, const Parts<R>& P, const Layout& L, int* hist, in
                                     const Parts<R>&, int*, int, hipStream_t);                                   \
   template void launch_init_particles<R>(const Geo&, const Plasma&, const Parts<R>&, const int*, hipStream_t);  \
   template void launch_inject<R>(const Geo&, const Plasma&, const Parts<R>&, const Layout&, int*, long long,    \
-                                 int, int*, hipStream_t);                                                       \
+                                 int, int*, int*, hipStream_t);                                                 \
   template void launch_hist<R>(const Geo&, const Parts<R>&, const Layout&, int*, int, hipStream_t);
 ENVPIC_INST(float)
 ENVPIC_INST(double)

@@ -15,10 +15,15 @@ namespace envpic {
 constexpr int SCAN_T = 1024;
 
 __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, Layout out, long long capacity,
-                                                 int inj_max, int max_items, int* err) {
+                                                 int inj_max, int max_items, int* bump_items, int* pending,
+                                                 int* err) {
   __shared__ int s_c[SCAN_T], s_m[SCAN_T];
   const int nt = g.ntiles;
   const int tid = threadIdx.x;
+  if (tid == 0 && pending != nullptr && *pending != 0) {
+    *bump_items += *pending;  // items of the column injected before this scan
+    *pending = 0;
+  }
   const int per = (nt + SCAN_T - 1) / SCAN_T;
   const int t0 = min(nt, tid * per), t1 = min(nt, t0 + per);
   int c = 0, m = 0;
@@ -65,8 +70,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
 }
 
 void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* err, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, st, g, hist, out, capacity, inj_max, max_items, err);
+                 int* bump_items, int* pending, int* err, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, st, g, hist, out, capacity, inj_max, max_items, bump_items,
+                     pending, err);
 }
 
 // ---------------------------------------------------------- diagnostics --

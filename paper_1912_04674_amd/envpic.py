@@ -62,6 +62,7 @@ EXPORTS = [
     "envpic_batch_step", "envpic_get_field", "envpic_set_field", "envpic_state",
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
+    "envpic_set_timing", "envpic_get_timing",
 ]
 
 
@@ -93,6 +94,8 @@ def lib():
     L.envpic_get_particles.argtypes = [vp] + [dp] * 7 + [up]
     L.envpic_set_particles.argtypes = [vp, ctypes.c_int64] + [dp] * 7 + [up]
     L.envpic_diagnostics.argtypes = [vp, dp]
+    L.envpic_set_timing.argtypes = [vp, ctypes.c_int]
+    L.envpic_get_timing.argtypes = [vp, dp, i64p]
     L.envpic_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
     L.envpic_load.argtypes = [vp, vp, ctypes.c_size_t]
     L.envpic_debug_poison.argtypes = [vp, ctypes.c_int]
@@ -248,6 +251,18 @@ class Sim:
         ids = np.ascontiguousarray(parts["id"], dtype=np.uint32)
         _check(lib().envpic_set_particles(self._h, n, *(_dptr(a) for a in arrs),
                                           ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+
+    def set_timing(self, enable=True):
+        _check(lib().envpic_set_timing(self._h, int(bool(enable))))
+
+    def timing(self):
+        """Average ms per launch and launch counts of the momentum, envelope,
+        position and field stages since timing was enabled."""
+        ms = np.zeros(4)
+        cnt = np.zeros(4, dtype=np.int64)
+        _check(lib().envpic_get_timing(self._h, _dptr(ms), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))))
+        names = ("momentum", "envelope", "position", "field")
+        return {n: (float(ms[k]), int(cnt[k])) for k, n in enumerate(names)}
 
     def diagnostics(self):
         out = np.zeros(len(DIAG_NAMES))

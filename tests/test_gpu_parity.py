@@ -268,6 +268,24 @@ def test_checkpoint_resume(E, prec):
                       1e-10 if prec == "fp64" else 1e-3)
 
 
+def test_stage_timing_does_not_change_results(E):
+    """Stage timing records one launch per stage per step and leaves the
+    result unchanged up to the deposit-order rounding of atomics."""
+    say("stage timing")
+    a = E.Sim(C2_SMALL, E.FP64)
+    b = E.Sim(C2_SMALL, E.FP64)
+    a.set_timing(True)
+    a.step(7)
+    t = a.timing()
+    assert all(n == 7 for _, n in t.values()), t
+    assert all(ms > 0 for ms, _ in t.values()), t
+    b.step(7)
+    compare_fields(a, b, 1e-12, names=("env", "chi", "ex", "er", "bt"), modes=1)
+    a.set_timing(False)
+    a.step(1)
+    assert all(n == 0 for _, n in a.timing().values())
+
+
 def test_nonfinite_detected(E):
     g = E.Sim(scaled(C1, nx=32, nr=8, x_c=12.8, x_f=12.8), E.FP32_BULK)
     assert g.diagnostics()["nonfinite"] == 0
