@@ -306,6 +306,21 @@ template <class R> struct SimT : envpic_sim {
   State<R> S;
   bool fp64_rows;
   char* arena;
+  double wmax = 0.0;  // bound of |w| over every particle loaded, injected or set
+
+  // largest weight the loading rule gives: n_max 2 pi r (dr/ppc_r)(dx/ppc_x)/ppc_t at r <= r_max
+  double loading_weight_bound() const {
+    double nmax = 0.0;
+    switch (p.profile) {
+      case ENVPIC_PROFILE_UNIFORM:
+      case ENVPIC_PROFILE_RAMP: nmax = std::fabs(p.n0); break;
+      case ENVPIC_PROFILE_PERTURB: nmax = std::fabs(p.n0) * (1.0 + std::fabs(p.perturb)); break;
+      case ENVPIC_PROFILE_BUMP: nmax = 2.0 * std::fabs(p.n0); break;
+      default: nmax = 0.0;
+    }
+    const double pi = 3.14159265358979323846;
+    return nmax * 2.0 * pi * (p.nr * p.dr) * (p.dr / p.ppc_r) * (p.dx / p.ppc_x) / p.ppc_t;
+  }
 
   Geo geo() const {
     Geo g{};
@@ -328,6 +343,12 @@ template <class R> struct SimT : envpic_sim {
     g.dx = p.dx;
     g.dr = p.dr;
     g.dt = p.dt;
+    // fixed-point scale of the mode-1 current sums: 2^49 over the largest
+    // |2 q w v S / V| = 2 w_max / V_0, V_0 = pi dr^2 dx / 4
+    const double cmax = 2.0 * wmax * 4.0 / (3.14159265358979323846 * p.dr * p.dr * p.dx);
+    const double fix = cmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 49) / cmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
+    g.fix = (float)fix;
+    g.unfix = 1.0 / (double)g.fix;
     return g;
   }
   Plasma plasma() const {
@@ -359,7 +380,11 @@ template <class R> struct SimT : envpic_sim {
     std::vector<int4> items;
     for (int t = 0; t < sz.ntiles; ++t) {
       off[t + 1] = off[t] + counts[t];
-      for (int k = 0; k < counts[t]; k += CHUNK) items.push_back(make_int4(t, off[t] + k, std::min(CHUNK, counts[t] - k), 0));
+      const int nm = (counts[t] + CHUNK - 1) / CHUNK;  // equal shares, as in the device scan
+      for (int k = 0; k < nm; ++k) {
+        const int lo = (int)((long long)k * counts[t] / nm), hi = (int)((long long)(k + 1) * counts[t] / nm);
+        items.push_back(make_int4(t, off[t] + lo, hi - lo, 0));
+      }
     }
     if ((int)items.size() > sz.max_items - sz.ntr) return fail(ENVPIC_ENOMEM, "work-item list overflow");
     const int ni = (int)items.size();
@@ -382,6 +407,7 @@ template <class R> struct SimT : envpic_sim {
 
   int init() override {
     int rc;
+    wmax = loading_weight_bound();
     if ((rc = hip_check(hipMemsetAsync(arena, 0, footprint_bytes(p, prec), stream), "arena clear"))) return rc;
     const Geo g = geo();
     // initial layout: window cells in tile-major order, ppc slots per cell
@@ -714,6 +740,7 @@ template <class R> struct SimT : envpic_sim {
       h[2][d] = (R)thv[k];
       for (int c = 3; c < 7; ++c) h[c][d] = (R)in[c][k];
       hid[d] = id[k];
+      wmax = std::max(wmax, std::fabs((double)h[6][d]));
     }
     int rc;
     if ((rc = upload_layout(cur, counts))) return rc;

@@ -20,7 +20,7 @@ constexpr int HALO = 2;     // LDS region margin around a tile (cells)
 constexpr int LX = TX + 2 * HALO + 1;
 constexpr int LR = TR + 2 * HALO + 1;
 constexpr int LN = LX * LR; // nodes of an LDS tile region
-constexpr int WG = 256;     // work-group size of the particle kernels
+constexpr int WG = 512;     // work-group size of the particle kernels
 constexpr int CHUNK = 4096; // max particles per work item
 // A particle's cell is one 32-bit word: lab column << 12 | radial row.  The
 // position inside the cell is kept as FP32 (or FP64) offsets along x and r,
@@ -56,6 +56,8 @@ struct Geo {
   long long shift;   // lab column of the window's left edge
   long long cap;     // particle slots per buffer
   double dx, dr, dt;
+  float fix;         // fixed-point scale of the FP32 path's mode-1 current sums
+  double unfix;      // 1 / fix
 };
 
 template <class R> struct Parts {

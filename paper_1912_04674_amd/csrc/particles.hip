@@ -57,14 +57,44 @@ __device__ inline int clampi(int v, int lo, int hi, bool& bad) {
 
 __device__ inline void lds_add(float* a, float v) { atomicAdd(a, v); }
 __device__ inline void lds_add(double* a, double v) { atomicAdd(a, v); }
-__device__ inline void lds_addc(float2* a, float2 v) {
-  atomicAdd(&a->x, v.x);
-  atomicAdd(&a->y, v.y);
+
+// Mode-1 current accumulators.  The FP64 path sums in FP64 LDS words.  The
+// FP32 path sums 64-bit fixed-point integers: on gfx950 integer LDS atomics
+// issue faster than FP64 ones (and FP32 LDS atomics are far slower than
+// either, measured), and an integer sum is exact and independent of the
+// order in which the lanes land.  Each contribution is scaled by g.fix =
+// 2^49 / (2 w_max / V_0), the bound of any |2 q w v S / V| (|v| < 1, S <= 1,
+// V_0 the smallest node volume), so one contribution is at most 2^49 in
+// magnitude and the <= 2 CHUNK contributions of a work item to one node stay
+// below 2^63.  The float -> int64 conversion adds 1.5 2^52 in FP64 and reads
+// the mantissa bits (round to nearest, exact for |x| < 2^51).
+template <class R> struct Acc1;
+template <> struct Acc1<double> {
+  using T = double2;
+  __device__ static T zero() { return make_double2(0.0, 0.0); }
+  __device__ static void add(T* a, double re, double im, const Geo&) {
+    atomicAdd(&a->x, re);
+    atomicAdd(&a->y, im);
+  }
+  __device__ static bool nonzero(const T& v) { return v.x != 0.0 || v.y != 0.0; }
+  __device__ static double re(const T& v, const Geo&) { return v.x; }
+  __device__ static double im(const T& v, const Geo&) { return v.y; }
+};
+__device__ inline long long to_fixed(float x) {
+  const double m = 6755399441055744.0;  // 1.5 * 2^52
+  return __double_as_longlong((double)x + m) - __double_as_longlong(m);
 }
-__device__ inline void lds_addc(double2* a, double2 v) {
-  atomicAdd(&a->x, v.x);
-  atomicAdd(&a->y, v.y);
-}
+template <> struct Acc1<float> {
+  using T = longlong2;
+  __device__ static T zero() { return make_longlong2(0, 0); }
+  __device__ static void add(T* a, float re, float im, const Geo& g) {
+    atomicAdd((unsigned long long*)&a->x, (unsigned long long)to_fixed(re * g.fix));
+    atomicAdd((unsigned long long*)&a->y, (unsigned long long)to_fixed(im * g.fix));
+  }
+  __device__ static bool nonzero(const T& v) { return v.x != 0 || v.y != 0; }
+  __device__ static float re(const T& v, const Geo& g) { return (float)((double)v.x * g.unfix); }
+  __device__ static float im(const T& v, const Geo& g) { return (float)((double)v.y * g.unfix); }
+};
 
 // Elementary functions.  The FP32 path uses the hardware reciprocal and
 // sine/cosine (direction cosines of the azimuth, relative error ~1e-6, far
@@ -187,28 +217,38 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   const Region q = region_of(g, it.x);
   const R hdt = (R)(0.5 * g.dt);
 
-  // ---- stage E, Bbar, Phi (and mode 1) of the region in LDS
+  // ---- stage E, Bbar, Phi (and mode 1) of the region in LDS.  Every load
+  // reads a valid address (the index falls back to the column start) and the
+  // value is selected afterwards; outside the grid the value is zero, and on
+  // the ghost row j = -1 the radial-staggered values mirror row 1/2 with the
+  // parity of the component (odd for mode-0 E_r and Bbar_t and mode-1 B_x).
   for (int k = threadIdx.x; k < LN; k += WG) {
     const int a = k / LR, b = k - (k / LR) * LR;
     const int rel = q.relX0 + a, j = q.R0 + b;
     const bool px = rel >= 0 && rel <= g.nx, dxok = rel >= 0 && rel <= g.nx - 1;
     const size_t o = (px || dxok) ? (size_t)phys_col(g, rel) * g.pitch : 0;
     const bool pr = j >= 0 && j <= g.nr, drok = j >= 0 && j <= g.nr - 1, ghost = j == -1;
-    sm.ex[k] = (dxok && pr) ? f.ex[o + j] : (R)0;
-    sm.er[k] = px ? (drok ? f.er[o + j] : (ghost ? -f.er[o] : (R)0)) : (R)0;
-    sm.bt[k] = dxok ? (drok ? f.btb[o + j] : (ghost ? -f.btb[o] : (R)0)) : (R)0;
-    R ph = 0;
-    if (px && pr) ph = (R)0.5 * cnorm(f.env[o + j]);
-    sm.phi[k] = ph;
+    const size_t in = pr ? o + j : o;                  // primal row (clamped)
+    const size_t ih = drok ? o + j : o;                // half row, ghost -> row 1/2
+    const R hs = drok ? (R)1 : (ghost ? (R)-1 : (R)0); // odd parity on the ghost row
+    const R hp = drok ? (R)1 : (ghost ? (R)1 : (R)0);  // even parity on the ghost row
+    const R vex = f.ex[in], ver = f.er[ih], vbt = f.btb[ih];
+    const C venv = f.env[in];
+    sm.ex[k] = (dxok && pr) ? vex : (R)0;
+    sm.er[k] = px ? hs * ver : (R)0;
+    sm.bt[k] = dxok ? hs * vbt : (R)0;
+    sm.phi[k] = (px && pr) ? (R)0.5 * cnorm(venv) : (R)0;
     sm.chi[k] = 0.0;
     if (M1) {
       const C z = mk<C>((R)0, (R)0);
-      sm.ex1[k] = (dxok && pr) ? f.ex1[o + j] : z;
-      sm.er1[k] = px ? (drok ? f.er1[o + j] : (ghost ? f.er1[o] : z)) : z;
-      sm.et1[k] = (px && pr) ? f.et1[o + j] : z;
-      sm.bx1[k] = px ? (drok ? f.bxb1[o + j] : (ghost ? cscale(f.bxb1[o], (R)-1) : z)) : z;
-      sm.br1[k] = (dxok && pr) ? f.brb1[o + j] : z;
-      sm.bt1[k] = dxok ? (drok ? f.btb1[o + j] : (ghost ? f.btb1[o] : z)) : z;
+      const C e1 = f.ex1[in], r1 = f.er1[ih], t1 = f.et1[in];
+      const C bx = f.bxb1[ih], br = f.brb1[in], bt = f.btb1[ih];
+      sm.ex1[k] = (dxok && pr) ? e1 : z;
+      sm.er1[k] = px ? cscale(r1, hp) : z;
+      sm.et1[k] = (px && pr) ? t1 : z;
+      sm.bx1[k] = px ? cscale(bx, hs) : z;
+      sm.br1[k] = (dxok && pr) ? br : z;
+      sm.bt1[k] = dxok ? cscale(bt, hp) : z;
     }
   }
   for (int k = threadIdx.x; k < LR; k += WG) {
@@ -361,7 +401,7 @@ template <class R, bool M1> struct SmemPos {
   using C = typename cplx_of<R>::type;
   R phh[LN];
   double jx[LN], jr[LN];
-  double2 jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
+  typename Acc1<R>::T jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
   R iax[LR], iar[LR], ivn[LR], ivh[LR];
   int hist[9];
 };
@@ -528,7 +568,7 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
           const int nb = Pr.i + bb;
           const R wt = (aa ? Dx.b : Dx.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
           const R v = q2 * mv.vx * wt;
-          lds_addc(&sm.jx1[(Dx.i + aa) * LR + nb], make_double2((double)(v * c), (double)(v * s)));
+          Acc1<R>::add(&sm.jx1[(Dx.i + aa) * LR + nb], v * c, v * s, g);
         }
         // J_r1 at (i, j+1/2); row -1/2 folds onto +1/2 (even for mode 1)
         {
@@ -536,14 +576,14 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
           if (q.R0 + nb == -1) nb += 1;
           const R wt = (aa ? Px.b : Px.a) * (bb ? Dr.b : Dr.a) * sm.ivh[nb];
           const R v = q2 * vr * wt;
-          lds_addc(&sm.jr1[(Px.i + aa) * LR + nb], make_double2((double)(v * c), (double)(v * s)));
+          Acc1<R>::add(&sm.jr1[(Px.i + aa) * LR + nb], v * c, v * s, g);
         }
         // J_t1 at (i, j)
         {
           const int nb = Pr.i + bb;
           const R wt = (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
           const R v = q2 * vt * wt;
-          lds_addc(&sm.jt1[(Px.i + aa) * LR + nb], make_double2((double)(v * c), (double)(v * s)));
+          Acc1<R>::add(&sm.jt1[(Px.i + aa) * LR + nb], v * c, v * s, g);
         }
       }
   }
@@ -570,9 +610,9 @@ __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
     sm.jx[k] = 0.0;
     sm.jr[k] = 0.0;
     if (M1) {
-      sm.jx1[k] = make_double2(0.0, 0.0);
-      sm.jr1[k] = make_double2(0.0, 0.0);
-      sm.jt1[k] = make_double2(0.0, 0.0);
+      sm.jx1[k] = Acc1<R>::zero();
+      sm.jr1[k] = Acc1<R>::zero();
+      sm.jt1[k] = Acc1<R>::zero();
     }
   }
   if (threadIdx.x < 9) sm.hist[threadIdx.x] = 0;
@@ -592,17 +632,18 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
     if (dxok && sm.jx[k] != 0.0) atomicAdd(&jx_out[o], (R)sm.jx[k]);
     if (drok && sm.jr[k] != 0.0) atomicAdd(&jr_out[o], (R)sm.jr[k]);
     if (M1) {
-      if (dxok && (sm.jx1[k].x != 0.0 || sm.jx1[k].y != 0.0)) {
-        atomicAdd(&jx1_out[o].x, (R)sm.jx1[k].x);
-        atomicAdd(&jx1_out[o].y, (R)sm.jx1[k].y);
+      using A = Acc1<R>;
+      if (dxok && A::nonzero(sm.jx1[k])) {
+        atomicAdd(&jx1_out[o].x, (R)A::re(sm.jx1[k], g));
+        atomicAdd(&jx1_out[o].y, (R)A::im(sm.jx1[k], g));
       }
-      if (drok && (sm.jr1[k].x != 0.0 || sm.jr1[k].y != 0.0)) {
-        atomicAdd(&jr1_out[o].x, (R)sm.jr1[k].x);
-        atomicAdd(&jr1_out[o].y, (R)sm.jr1[k].y);
+      if (drok && A::nonzero(sm.jr1[k])) {
+        atomicAdd(&jr1_out[o].x, (R)A::re(sm.jr1[k], g));
+        atomicAdd(&jr1_out[o].y, (R)A::im(sm.jr1[k], g));
       }
-      if (sm.jt1[k].x != 0.0 || sm.jt1[k].y != 0.0) {
-        atomicAdd(&jt1_out[o].x, (R)sm.jt1[k].x);
-        atomicAdd(&jt1_out[o].y, (R)sm.jt1[k].y);
+      if (A::nonzero(sm.jt1[k])) {
+        atomicAdd(&jt1_out[o].x, (R)A::re(sm.jt1[k], g));
+        atomicAdd(&jt1_out[o].y, (R)A::im(sm.jt1[k], g));
       }
     }
   }

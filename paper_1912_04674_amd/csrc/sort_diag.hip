@@ -9,9 +9,10 @@ namespace envpic {
 
 // ----------------------------------------------------------------- scan --
 // One work group of 1024 threads: exclusive scan of the tile counts into
-// offsets (and the scatter cursors), work items of <= CHUNK particles per
-// tile, and a reset of the histogram for the next step.  Flags when the
-// particles plus one injected column would not fit.
+// offsets (and the scatter cursors), work items (a tile of v particles gives
+// ceil(v / CHUNK) items of equal size), and a reset of the histogram for the
+// next step.  Flags when the particles plus one injected column would not
+// fit.
 constexpr int SCAN_T = 1024;
 
 __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, Layout out, long long capacity,
@@ -52,7 +53,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
     out.cursor[t] = ec;
     const int nm = (v + CHUNK - 1) / CHUNK;
     for (int k = 0; k < nm; ++k) {
-      const int st = ec + k * CHUNK, cn = min(CHUNK, v - k * CHUNK);
+      // the nm items of a tile share its particles evenly
+      const int lo = (int)((long long)k * v / nm), hi = (int)((long long)(k + 1) * v / nm);
+      const int st = ec + lo, cn = hi - lo;
       // items never reach past the buffer (an overflow is flagged below)
       out.items[em + k] = (em + k < item_cap && (long long)st + cn <= capacity) ? make_int4(t, st, cn, 0)
                                                                                 : make_int4(t, 0, 0, 0);
