@@ -46,17 +46,26 @@ def algorithmic_bytes(cfg, n_particles, prec_bytes=4):
             "per_cell": {"k_momentum": mom_c, "k_position": pos_c}}
 
 
+def source_digest():
+    """sha256 (first 16 hex digits) of the HIP sources, in name order."""
+    d = os.path.join(ROOT, "paper_1912_04674_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        if name.endswith((".hip", ".hpp")):
+            h.update(name.encode())
+            h.update(open(os.path.join(d, name), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_record(kernel, workload):
     """Measured HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, scaled
     by a copy-kernel calibration) from profiles/, valid only while the kernel
-    source is unchanged."""
+    sources are unchanged."""
     path = os.path.join(ROOT, "profiles", f"traffic_{kernel}_{workload}.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
-    src = os.path.join(ROOT, "paper_1912_04674_amd", "csrc", "particles.hip")
-    h = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
-    if rec.get("source_sha256_16") != h:
+    if rec.get("source_sha256_16") != source_digest():
         return None
     return rec.get("bytes_per_launch")
 

@@ -72,7 +72,8 @@ template <class R> struct Acc1;
 template <> struct Acc1<double> {
   using T = double2;
   __device__ static T zero() { return make_double2(0.0, 0.0); }
-  __device__ static void add(T* a, double re, double im, const Geo&) {
+  __device__ static double scale(const Geo&) { return 1.0; }
+  __device__ static void add(T* a, double re, double im) {
     atomicAdd(&a->x, re);
     atomicAdd(&a->y, im);
   }
@@ -87,20 +88,24 @@ __device__ inline long long to_fixed(float x) {
 template <> struct Acc1<float> {
   using T = longlong2;
   __device__ static T zero() { return make_longlong2(0, 0); }
-  __device__ static void add(T* a, float re, float im, const Geo& g) {
-    atomicAdd((unsigned long long*)&a->x, (unsigned long long)to_fixed(re * g.fix));
-    atomicAdd((unsigned long long*)&a->y, (unsigned long long)to_fixed(im * g.fix));
+  __device__ static float scale(const Geo& g) { return g.fix; }
+  __device__ static void add(T* a, float re, float im) {  // re, im already scaled
+    atomicAdd((unsigned long long*)&a->x, (unsigned long long)to_fixed(re));
+    atomicAdd((unsigned long long*)&a->y, (unsigned long long)to_fixed(im));
   }
   __device__ static bool nonzero(const T& v) { return v.x != 0 || v.y != 0; }
   __device__ static float re(const T& v, const Geo& g) { return (float)((double)v.x * g.unfix); }
   __device__ static float im(const T& v, const Geo& g) { return (float)((double)v.y * g.unfix); }
 };
 
-// Elementary functions.  The FP32 path uses the hardware reciprocal and
-// sine/cosine (direction cosines of the azimuth, relative error ~1e-6, far
-// inside the FP32 path's tolerance); the FP64 path uses the libm calls.
-__device__ inline float rsqrt_r(float x) { return rsqrtf(x); }
+// Elementary functions.  The FP32 path uses the hardware reciprocal, square
+// root, reciprocal square root and sine/cosine (about 1 ulp, or ~1e-6 for
+// the direction cosines of the azimuth, far inside the FP32 path's
+// tolerance); the FP64 path uses the libm calls.
+__device__ inline float rsqrt_r(float x) { return __builtin_amdgcn_rsqf(x); }  // x >= 1 here
 __device__ inline double rsqrt_r(double x) { return rsqrt(x); }
+__device__ inline float sqrt_r(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ inline double sqrt_r(double x) { return sqrt(x); }
 __device__ inline float rcp_r(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ inline double rcp_r(double x) { return 1.0 / x; }
 __device__ inline void sincos_r(float t, float* s, float* c) {
@@ -142,10 +147,10 @@ template <class R> __device__ inline void radial_step(R r, R a, R b, R& dr_out, 
   const R ra = r + a;
   if (ra > (R)0) {
     const R beta = b * rcp_r(ra);
-    const R q = sqrt((R)1 + beta * beta);
+    const R q = sqrt_r((R)1 + beta * beta);
     dr_out = a + ra * beta * beta * rcp_r((R)1 + q);
   } else {
-    dr_out = sqrt(ra * ra + b * b) - r;
+    dr_out = sqrt_r(ra * ra + b * b) - r;
   }
   dth = dtheta(b, ra);
 }
@@ -518,12 +523,12 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
       R cd, sd;
       if (u > (R)0) {
         const R beta = v * rcp_r(u);
-        const R qq = sqrt((R)1 + beta * beta);
+        const R qq = sqrt_r((R)1 + beta * beta);
         frm = mv.fr0 + ((R)0.5 * mv.a + u * beta * beta * rcp_r((R)1 + qq)) * (R)(1.0 / g.dr);
         cd = rcp_r(qq);
         sd = beta * cd;
       } else {
-        const R rm = sqrt(u * u + v * v);
+        const R rm = sqrt_r(u * u + v * v);
         frm = mv.fr0 + (rm - r0) / dr;
         cd = rm > (R)0 ? u / rm : (R)1;
         sd = rm > (R)0 ? v / rm : (R)0;
@@ -535,7 +540,7 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
       sincos_r(mv.th1, &s1, &c1);
       const R r1 = ((R)mv.jr1 + mv.fr1) * dr;
       const R ym = (R)0.5 * (r0 * mv.c0 + r1 * c1), zm = (R)0.5 * (r0 * mv.s0 + r1 * s1);
-      const R rm = sqrt(ym * ym + zm * zm);
+      const R rm = sqrt_r(ym * ym + zm * zm);
       jm = 0;
       frm = rm / dr;
       c = rm > (R)0 ? ym / rm : (R)1;
@@ -555,37 +560,29 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
     const R fm = um - (R)am;
     const int bm = clampi(jm - q.R0, 1, LR - 3, bad);
     const int amc = clampi(am, 1, LX - 3, bad);
-    const R vr = mv.vy * c + mv.vz * s, vt = -mv.vy * s + mv.vz * c;
-    const R q2 = (R)-2 * w;  // 2 q w, electrons
     const Lin<R> Px = primal_w<R>(amc, fm), Dx = dual_w<R>(amc, fm);
     const Lin<R> Pr = primal_w<R>(bm, frm), Dr = dual_w<R>(bm, frm);
+    // 2 q w v e^{i theta} per component (electrons, q = -1), with the
+    // accumulator scale folded in; radial weights times inverse volumes
+    const R q2 = (R)-2 * w * Acc1<R>::scale(g);
+    const R vx = q2 * mv.vx, vr = q2 * (mv.vy * c + mv.vz * s), vt = q2 * (mv.vz * c - mv.vy * s);
+    const R xc = vx * c, xs = vx * s, rc = vr * c, rs = vr * s, tc = vt * c, ts = vt * s;
+    const R pv[2] = {Pr.a * sm.ivn[Pr.i], Pr.b * sm.ivn[Pr.i + 1]};
+    // J_r1 rows; row -1/2 folds onto +1/2 (even for mode 1)
+    const int dn0 = (q.R0 + Dr.i == -1) ? Dr.i + 1 : Dr.i, dn1 = Dr.i + 1;
+    const R dv[2] = {Dr.a * sm.ivh[dn0], Dr.b * sm.ivh[dn1]};
+    const int dn[2] = {dn0, dn1};
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa)
+    for (int aa = 0; aa < 2; ++aa) {
+      const R wdx = aa ? Dx.b : Dx.a, wpx = aa ? Px.b : Px.a;
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb) {
-        // J_x1 at (i+1/2, j)
-        {
-          const int nb = Pr.i + bb;
-          const R wt = (aa ? Dx.b : Dx.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
-          const R v = q2 * mv.vx * wt;
-          Acc1<R>::add(&sm.jx1[(Dx.i + aa) * LR + nb], v * c, v * s, g);
-        }
-        // J_r1 at (i, j+1/2); row -1/2 folds onto +1/2 (even for mode 1)
-        {
-          int nb = Dr.i + bb;
-          if (q.R0 + nb == -1) nb += 1;
-          const R wt = (aa ? Px.b : Px.a) * (bb ? Dr.b : Dr.a) * sm.ivh[nb];
-          const R v = q2 * vr * wt;
-          Acc1<R>::add(&sm.jr1[(Px.i + aa) * LR + nb], v * c, v * s, g);
-        }
-        // J_t1 at (i, j)
-        {
-          const int nb = Pr.i + bb;
-          const R wt = (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivn[nb];
-          const R v = q2 * vt * wt;
-          Acc1<R>::add(&sm.jt1[(Px.i + aa) * LR + nb], v * c, v * s, g);
-        }
+        const R ux = wdx * pv[bb], ur = wpx * dv[bb], ut = wpx * pv[bb];
+        Acc1<R>::add(&sm.jx1[(Dx.i + aa) * LR + Pr.i + bb], ux * xc, ux * xs);  // (i+1/2, j)
+        Acc1<R>::add(&sm.jr1[(Px.i + aa) * LR + dn[bb]], ur * rc, ur * rs);     // (i, j+1/2)
+        Acc1<R>::add(&sm.jt1[(Px.i + aa) * LR + Pr.i + bb], ut * tc, ut * ts);  // (i, j)
       }
+    }
   }
 }
 
