@@ -105,6 +105,33 @@ def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True):
     return out
 
 
+def run_serving(E, prec, budget_bytes, steps=300):
+    """The scan-serving trace: 64 jobs arriving as a Poisson process (mean
+    4 jobs/s), grids from {512x64, 1024x128, 2048x256}, 300 steps each,
+    served by continuous batching inside one arena of `budget_bytes`."""
+    from inputs import c4_trace
+    from paper_1912_04674_amd.serve import DONE, GpuBackend, ScanServer, latency_stats
+    cfgs, arrivals = c4_trace()
+    be = GpuBackend(budget_bytes, precision=prec, lineout=True)
+    # load the kernels' code objects before the trace starts
+    warm = ScanServer(be, chunk=5)
+    warm.run_trace([dict(cfgs[0], nx=64, nr=16, x_c=20.0, x_f=20.0)], [0.0], steps=3)
+    srv = ScanServer(be, max_slots=32, chunk=25, depth=2)
+    jobs = srv.run_trace(cfgs, arrivals, steps=steps, timeout=600)
+    ok = [j for j in jobs if j.status == DONE]
+    makespan = max(j.finish for j in jobs) - min(j.arrival for j in jobs)
+    pushes = sum(j.result["diag"]["count"] * j.steps for j in ok)
+    st = latency_stats(jobs)
+    by_grid = {}
+    for j in ok:
+        by_grid.setdefault(f"{j.cfg['nx']}x{j.cfg['nr']}", []).append(j.latency)
+    del be, srv, warm
+    return {"jobs": len(jobs), "done": len(ok), "p50_s": st["p50"], "p99_s": st["p99"], "mean_s": st["mean"],
+            "makespan_s": makespan, "aggregate_pushes_per_s": pushes / makespan,
+            "median_latency_s_by_grid": {k: float(sorted(v)[(len(v) - 1) // 2]) for k, v in sorted(by_grid.items())},
+            "budget_bytes": budget_bytes}
+
+
 def cpu_baseline(cfg, cols=256, steps=20):
     """The FP64 oracle (single thread) on a slab of the same workload: the
     last `cols` cell columns (where the pulse is), full radius, same loading."""
@@ -132,6 +159,8 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c5"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-serving", action="store_true", help="skip the scan-serving trace")
+    ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB, 10 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -200,6 +229,13 @@ def main():
                    "moving_window": bool(cfg["moving_window"]), "precision": "fp32-bulk (fp64 axis rows)"},
         "roofline": roofline,
     }
+    if not args.no_serving:
+        budget = int(args.serving_budget_gib * 2**30)
+        line["serving"] = {"trace": "64 jobs, Poisson 4 jobs/s, grids {512x64, 1024x128, 2048x256}, m=0, "
+                                    "2x2x2 ppc, 300 steps, window on",
+                           "fp32": run_serving(E, E.FP32_BULK, budget)}
+        if not args.no_fp64:
+            line["serving"]["fp64"] = run_serving(E, E.FP64, budget)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
     line["extra"] = extra

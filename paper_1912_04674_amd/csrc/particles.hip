@@ -927,14 +927,26 @@ __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict
 // counts of live particles per tile of their current position
 template <class R>
 __global__ void k_hist(Geo g, Parts<R> P, Layout L, int* __restrict__ hist) {
+  // the particles of an item sit in its tile: count in LDS, one global add
+  __shared__ int cnt;
   const int item = blockIdx.x;
   if (item >= *L.n_items) return;
   const int4 it = L.items[item];
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  int mine = 0;
   for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
     const unsigned cw = P.cell[it.y + k];
     if (cw == kDead) continue;
-    atomicAdd(&hist[tile_key(g, cell_ix(cw), cell_jr(cw))], 1);
+    const int key = tile_key(g, cell_ix(cw), cell_jr(cw));
+    if (key == it.x)
+      ++mine;
+    else
+      atomicAdd(&hist[key], 1);
   }
+  if (mine) atomicAdd(&cnt, mine);
+  __syncthreads();
+  if (threadIdx.x == 0 && cnt) atomicAdd(&hist[it.x], cnt);
 }
 
 // ============================================================ launchers ==

@@ -176,21 +176,29 @@ __global__ __launch_bounds__(DG) void k_diag_grid(Geo g, Grids<R> f, const R* __
 // fixed-order final sums (one thread per quantity)
 __global__ void k_diag_final(const double* __restrict__ pp, int np_blocks, const double* __restrict__ pg,
                              int ng_blocks, double* __restrict__ out) {
-  const int q = threadIdx.x;
+  // wavefront q sums quantity q: lane l takes blocks l, l + 64, ..., then a
+  // fixed-order tree over the lanes (the result does not depend on timing)
+  __shared__ double lanes[NPD + NGD][64];
+  const int q = threadIdx.x / 64, l = threadIdx.x % 64;
   double s = 0.0;
   if (q < NPD) {
-    for (int b = 0; b < np_blocks; ++b) s += pp[(size_t)b * NPD + q];
+    for (int b = l; b < np_blocks; b += 64) s += pp[(size_t)b * NPD + q];
   } else if (q < NPD + NGD) {
-    for (int b = 0; b < ng_blocks; ++b) s += pg[(size_t)b * NGD + (q - NPD)];
+    for (int b = l; b < ng_blocks; b += 64) s += pg[(size_t)b * NGD + (q - NPD)];
   }
+  if (q < NPD + NGD) lanes[q][l] = s;
   __syncthreads();
+  for (int h = 32; h > 0; h >>= 1) {
+    if (q < NPD + NGD && l < h) lanes[q][l] += lanes[q][l + h];
+    __syncthreads();
+  }
   // map onto the public diagnostics vector
   // pp: 0 count, 1 charge, 2 kin, 3 lx, 4 px, 5 nonfinite
   // pg: 0 chi V, 1 |A|^2 V, 2 u0, 3 u1, 4 nonfinite
   __shared__ double t[NPD + NGD];
-  if (q < NPD + NGD) t[q] = s;
+  if (l == 0 && q < NPD + NGD) t[q] = lanes[q][0];
   __syncthreads();
-  if (q == 0) {
+  if (threadIdx.x == 0) {
     out[0] = t[0];
     out[1] = t[1];
     out[2] = t[NPD + 0];
@@ -216,7 +224,7 @@ void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, int max_items
   double* pg = scratch + (size_t)max_items * NPD;
   hipLaunchKernelGGL((k_diag_particles<R>), dim3(max_items), dim3(DG), 0, st, g, P, L, pp);
   hipLaunchKernelGGL((k_diag_grid<R>), dim3(nb), dim3(DG), 0, st, g, f, chi, fp64_rows, pg);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64), 0, st, pp, max_items, pg, nb, out);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * (NPD + NGD)), 0, st, pp, max_items, pg, nb, out);
 }
 
 template void launch_diag<float>(const Geo&, const Parts<float>&, const Layout&, int, const Grids<float>&,
