@@ -19,6 +19,34 @@
  *   - particles are exchanged as separate FP64 arrays in lab-frame Cartesian
  *     coordinates plus a uint32 identifier.
  *   - every call returns 0 on success or a negative code.
+ *
+ * What pins each part (tests/test_oracle_*.py; none compares the oracle
+ * with itself):
+ *   envelope bulk          discrete dispersion relation of the scheme (exact)
+ *   envelope axis, radial  closed-form Laplacian of a Gaussian, 2nd order
+ *   envelope in vacuum     paraxial waist / amplitude / Gouy phase, and the
+ *                          paper's own diffraction set-up (Sec. 4, tests/golden)
+ *   chi deposit            chi = n0 exactly for uniform loading at rest; sum
+ *                          rule sum chi V = sum w / gbar
+ *   Boris core             pure-E and pure-B closed forms (gbar with Phi)
+ *   ponderomotive force    kick direction and factor; luminal invariant
+ *                          gbar - p_x = 1 at the scheme's first order
+ *   Cartesian signs        L_x conserved exactly in mode-0 fields
+ *   full push on a grid    brute-force ODE integration of one particle
+ *   mode-0 J, Maxwell      discrete continuity and Gauss law, exactly
+ *   full loop              linear wake of the paper's second benchmark
+ *                          against quasi-static theory (tests/golden)
+ *   moving window          equals a static run in a longer box, bitwise
+ *   loading RNG            SplitMix64 published output
+ *   mode-1 Maxwell/deposit vacuum energy bounded (and unstable beyond the
+ *                          limit), uniform transverse field static, a
+ *                          theta-symmetric ring deposits zero, deposit phase
+ *                          of one particle.  Beyond these the mode-1 fields
+ *                          and currents are PARITY UNPINNED (derived
+ *                          equations only, no closed form for a general state).
+ *   step order, gbar and   documented choices with no value printed in the
+ *   Phi centring (R6-R8)   paper: PARITY UNPINNED beyond the convergence
+ *                          order the luminal test fixes.
  */
 #ifndef ENVPIC_ORACLE_H
 #define ENVPIC_ORACLE_H

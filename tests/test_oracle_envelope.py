@@ -3,9 +3,14 @@
 Envelope equation: Sec. 2, Eq. envelope_equation; scheme: Sec. 3,
 Eq. envelope_solver with the cylindrical Laplacian printed after it.
 """
+import json
+import os
+
 import numpy as np
 import pytest
 from scipy.optimize import brentq
+
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sec4_benchmarks.json")))
 
 
 def _vac(nx, nr, dx=0.8, dr=1.5, dt=0.6, **kw):
@@ -124,3 +129,37 @@ def test_envelope_boundaries_stay_zero(oracle_mod):
     A = s.get_field("env")
     assert np.all(A[0] == 0) and np.all(A[-1] == 0) and np.all(A[:, -1] == 0)
     assert np.abs(A).max() > 0.1
+
+
+@pytest.mark.slow
+def test_paper_vacuum_diffraction_setup(oracle_mod):
+    """The paper's first benchmark at its own parameters (w0 = 90, intensity
+    FWHM 49.5, dx = 0.7, dr = 5, dt = 0.8 dx; values in tests/golden): the
+    waist at the pulse peak after 1000 c/w0 of propagation from focus follows
+    w/w0 = sqrt(1 + (x/Z_R)^2), Z_R = w0^2/2 = 4050, i.e. 1.0301."""
+    b = GOLDEN["vacuum_diffraction"]
+    dx, dr, w0 = b["dx"], b["dr"], b["w0"]
+    dt = b["dt_over_dx"] * dx
+    tau = b["tau_fwhm_intensity"] * np.sqrt(2.0)  # FWHM of |A| (reading of the duration)
+    nx, nr = 400, 72
+    x_c = nx * dx - 140.0
+    cfg = _vac(nx, nr, dx=dx, dr=dr, dt=dt, a0=1.0, w0=w0, tau=tau, x_c=x_c, x_f=x_c, moving_window=1)
+    s = oracle_mod.OracleSim(cfg)
+    r = np.arange(nr + 1) * dr
+
+    def waist():
+        n, shift, _ = s.state()
+        xpk = x_c + n * dt - shift * dx
+        col = s.get_field("env")[int(round(xpk / dx))]
+        i2 = np.abs(col) ** 2
+        return np.sqrt(2 * np.trapezoid(i2 * r**3, r) / np.trapezoid(i2 * r, r)), n * dt
+
+    wa, _ = waist()
+    s.step(int(round(1000.0 / dt)))
+    wb, X = waist()
+    zr = w0**2 / 2
+    expect = np.sqrt(1 + (X / zr) ** 2)
+    assert X == pytest.approx(1000.0, abs=dt)
+    assert wb / wa == pytest.approx(expect, abs=3e-4)
+    # the printed law (x^2/(w0^2/2)) would give a far wider beam
+    assert abs(wb / wa - np.sqrt(1 + X**2 / (w0**2 / 2))) > 1.0

@@ -11,16 +11,23 @@ ponderomotive source |A|^2/4, (d2/dxi2 + kp^2) phi = kp^2 |A|^2/4, E_x =
 pulse its amplitude is kp^2 (a0^2/4) sigma sqrt(pi/2) exp(-kp^2 sigma^2/8) =
 1.54e-6 on the axis).
 """
+import json
+import os
+
 import numpy as np
 import pytest
 from scipy.integrate import quad
 
+GOLDEN = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "sec4_benchmarks.json")))["linear_wake"]
+
 
 @pytest.mark.slow
 def test_linear_wake_matches_quasistatic_theory(oracle_mod):
-    dx, dr, dt = 0.7, 5.0, 0.56
+    dx, dr = GOLDEN["dx"], GOLDEN["dr"]
+    dt = GOLDEN["dt_over_dx"] * dx
     nx, nr = 700, 20
-    a0, w0, tau, n0 = 0.01, 90.0, 70.0, 0.0017
+    a0, w0, tau, n0 = GOLDEN["a0"], GOLDEN["w0"], GOLDEN["tau_fwhm_field"], GOLDEN["n0"]
+    assert GOLDEN["particles_per_cell"] == 2 * 3 * 1
     sig = tau / (2 * np.sqrt(np.log(2)))
     x_c = nx * dx - 130.0
     cfg = dict(nx=nx, nr=nr, dx=dx, dr=dr, dt=dt, profile="uniform", n0=n0, ppc=(2, 3, 1),
