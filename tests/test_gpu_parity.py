@@ -11,7 +11,7 @@ import sys
 import numpy as np
 import pytest
 
-from inputs import C1, C3, random_grid, random_particles, scaled
+from inputs import C1, C3, C5, random_grid, random_particles, scaled
 
 pytestmark = pytest.mark.gpu
 
@@ -312,35 +312,63 @@ def test_batch_equals_alone(E):
 
 
 # ------------------------------------------------ full-size sampled check --
-def test_c3_full_size_slab(E, oracle_mod):
-    """The 4096 x 512, modes 0-1, 33.5 M-particle workload in the benchmark's
-    launch configuration, 20 steps, against an oracle replica of a 96-column
-    slab around the pulse (same lab positions, angles and ids): particles and
-    grids outside the slab boundary's domain of dependence must agree."""
-    say("C3 full size slab")
-    steps = 20
-    g = E.Sim(C3, E.FP32_BULK)
+def _full_size_slab(E, oracle_mod, cfg, c0, w, steps):
+    """Run the whole workload on the GPU in the benchmark's launch
+    configuration and an oracle replica of columns [c0, c0 + w) (same lab
+    positions, angles, ids and window timing); compare grids and particles
+    outside the slab boundary's domain of dependence (every stencil reaches
+    one cell per step)."""
+    g = E.Sim(cfg, E.FP32_BULK)
     g.step(steps)
-    # every stencil reaches one cell per step, so columns more than `steps`
-    # cells inside the slab cannot see its boundaries
-    c0, w = 2048 - 48, 96
-    r = oracle_mod.OracleSim(scaled(C3, nx=w, start_col=c0))
+    r = oracle_mod.OracleSim(scaled(cfg, nx=w, start_col=c0))
     r.step(steps)
+    (gn, gs, _), (rn, rs, _) = g.state(), r.state()
+    assert gn == rn and rs == c0 + gs  # the oracle's shift counts lab columns from its slab start
     lo, hi = steps + 4, w - steps - 4
-    for n in ("env", "chi", "ex", "er", "bt", "jx", "jr"):
+    if c0 + w == cfg["nx"]:
+        hi = w  # the slab shares the window's leading edge (same boundary, same injection)
+    for n in ("env", "chi", "ex", "er", "bt", "jx", "jr") + (("ex1", "er1", "bt1", "jx1") if cfg["n_modes"] > 1 else ()):
         a = g.get_field(n)[c0 + lo:c0 + hi]
         b = r.get_field(n)[lo:hi]
-        e = ferr(a, b)
+        scale = None
+        if n.endswith("1"):
+            scale = np.abs(r.get_field({"ex1": "ex", "er1": "er", "bt1": "bt", "jx1": "jx"}[n])[lo:hi]).max()
+        e = ferr(a, b, scale)
         say("slab field", n, e)
         assert e <= 1e-4, (n, e)
     pg = g.get_particles()
     pr = r.get_particles()
-    dx = C3["dx"]
-    sel_r = (pr["x"] >= (c0 + lo + 1) * dx) & (pr["x"] < (c0 + hi - 1) * dx)
+    dx = cfg["dx"]
+    x_lo = (rs + lo + 1) * dx  # lab x of the oracle window's column lo + 1
+    x_hi = (rs + hi - 1) * dx if hi < w else np.inf
+    sel_r = (pr["x"] >= x_lo) & (pr["x"] < x_hi)
     ids = np.sort(pr["id"][sel_r])
     kg = np.searchsorted(pg["id"], ids)
-    assert np.array_equal(pg["id"][kg], ids)
+    assert np.array_equal(pg["id"][np.minimum(kg, len(pg["id"]) - 1)], ids)
     sub_g = {k: v[kg] for k, v in pg.items()}
     sub_r = by_id({k: v[sel_r] for k, v in pr.items()})
     say("sampled particles", len(ids))
     compare_particles(sub_g, sub_r, 1e-3, 1e-3)
+    return g
+
+
+def test_c3_full_size_slab(E, oracle_mod):
+    """The 4096 x 512, modes 0-1, 33.5 M-particle workload, 20 steps, against
+    an oracle replica of a 96-column slab around the pulse."""
+    say("C3 full size slab")
+    _full_size_slab(E, oracle_mod, C3, 2048 - 48, 96, 20)
+
+
+def test_c5_full_size_window_slab(E, oracle_mod):
+    """The 8192 x 768, modes 0-1, 151 M-particle workload with the moving
+    window and injection at the leading edge, 20 steps (15 window shifts),
+    against an oracle replica of the 64 leading columns; the particle count
+    stays that of the full window (each shift drops one column and injects
+    one)."""
+    say("C5 full size window slab")
+    g = _full_size_slab(E, oracle_mod, C5, C5["nx"] - 64, 64, 20)
+    n, shift, count = g.state()
+    assert shift == 15
+    ppc = int(np.prod(C5["ppc"]))
+    assert count == C5["nx"] * C5["nr"] * ppc
+    assert g.diagnostics()["nonfinite"] == 0
