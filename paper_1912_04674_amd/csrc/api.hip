@@ -50,8 +50,9 @@ Sizes sizes_of(const envpic_params& p) {
   s.ntiles = s.ntxa * s.ntr;
   s.ppc = p.ppc_x * p.ppc_r * p.ppc_t;
   const long long window = (long long)p.nx * p.nr * s.ppc;
-  s.capacity = p.capacity > 0 ? p.capacity : window + 2LL * p.nr * s.ppc + 1024;
-  s.max_items = (int)(s.ntiles + s.capacity / CHUNK + s.ntr + 16);
+  // one window of particles plus the columns injected between two sorts
+  s.capacity = p.capacity > 0 ? p.capacity : window + (SORT_EVERY + 1LL) * p.nr * s.ppc + 1024;
+  s.max_items = (int)(s.ntiles + s.capacity / CHUNK + SORT_EVERY * s.ntr + 16);
   s.ngrid = (size_t)s.nxa * s.pitch;
   return s;
 }
@@ -88,8 +89,8 @@ int validate(const envpic_params* p) {
   if (p->a0 < 0 || (p->a0 > 0 && !(p->w0 > 0 && p->tau > 0))) return fail(ENVPIC_EINVAL, "bad laser parameters");
   const Sizes s = sizes_of(*p);
   if (s.capacity >= (1LL << 31) - 1) return fail(ENVPIC_EINVAL, "too many particles for int32 slots");
-  if (s.capacity < (long long)p->nx * p->nr * s.ppc + (long long)p->nr * s.ppc)
-    return fail(ENVPIC_EINVAL, "capacity below one window of particles plus one column");
+  if (s.capacity < (long long)p->nx * p->nr * s.ppc + (long long)SORT_EVERY * p->nr * s.ppc)
+    return fail(ENVPIC_EINVAL, "capacity below one window of particles plus the columns injected between sorts");
   return ENVPIC_OK;
 }
 
@@ -113,7 +114,7 @@ template <class R> struct State {
   Layout lay[2];
   int* hist;
   int* err;
-  int* pending;  // work items appended by the last injection, not yet counted
+  int* pending;  // [items, slots] appended by the last injection, not yet counted
   double* diag_scratch;
   double* diag_out;
 };
@@ -180,10 +181,11 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
     L.cursor = cv.take<int>((size_t)s.ntiles);
     L.items = cv.take<int4>((size_t)s.max_items);
     L.n_items = cv.take<int>(1);
+    L.fill = cv.take<int>(1);
   }
   S.hist = cv.take<int>((size_t)s.ntiles);
   S.err = cv.take<int>(1);
-  S.pending = cv.take<int>(1);
+  S.pending = cv.take<int>(2);
   Geo g{};
   g.nx = p.nx;
   g.nr = p.nr;
@@ -210,6 +212,7 @@ struct envpic_sim {
   int64_t n = 0, shift = 0;
   int stage = 0;     // next expected stage: 0 momentum, 1 envelope, 2 position, 3 field
   int cur = 0;       // particle buffer holding the current state
+  int64_t sorted_at = 0;  // step whose positions the layout of P[cur] is sorted by
   bool deferred = false, deposit_done = true;
   int chi_last = 0;  // deposit buffer of the last momentum stage
   // stage timing (events on the simulation's stream)
@@ -393,6 +396,7 @@ template <class R> struct SimT : envpic_sim {
     if ((rc = hip_check(hipMemcpyAsync(S.lay[b].cursor, off.data(), (size_t)sz.ntiles * sizeof(int), hipMemcpyHostToDevice, stream), "upload cursor"))) return rc;
     if (ni && (rc = hip_check(hipMemcpyAsync(S.lay[b].items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, stream), "upload items"))) return rc;
     if ((rc = hip_check(hipMemcpyAsync(S.lay[b].n_items, &ni, sizeof(int), hipMemcpyHostToDevice, stream), "upload n_items"))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(S.lay[b].fill, &off[sz.ntiles], sizeof(int), hipMemcpyHostToDevice, stream), "upload fill"))) return rc;
     return hip_check(hipStreamSynchronize(stream), "layout upload");
   }
 
@@ -400,8 +404,9 @@ template <class R> struct SimT : envpic_sim {
   int rebuild_next_layout() {
     const Geo g = geo();
     launch_hist<R>(g, S.parts[cur], S.lay[cur], S.hist, sz.max_items, stream);
-    launch_scan(g, S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items, S.pending,
-                S.err, stream);
+    launch_scan(g, S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items,
+                S.lay[cur].fill, S.pending, S.err, stream);
+    sorted_at = n;  // the particles of P[cur] sit in their tiles
     return launched("hist/scan");
   }
 
@@ -459,11 +464,17 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 0) return fail(ENVPIC_EORDER, "momentum stage out of order");
     const Geo g = geo();
     const int d = (int)(n & 1);
+    // re-sort when the particles have had SORT_EVERY steps to drift from
+    // their tiles; in between, p is updated in place
+    const bool scatter = n - sorted_at >= SORT_EVERY;
     tick_begin();
     launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.scr.w,
-                       S.err, sz.max_items, defer, stream);
+                       S.err, sz.max_items, defer, scatter, stream);
     tick_end(0);
-    cur = 1 - cur;
+    if (scatter) {
+      cur = 1 - cur;
+      sorted_at = n;
+    }
     chi_last = d;
     stage = 1;
     deferred = defer;
@@ -525,7 +536,7 @@ template <class R> struct SimT : envpic_sim {
                          stream);
     }
     launch_scan(geo(), S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items,
-                S.pending, S.err, stream);
+                S.lay[cur].fill, S.pending, S.err, stream);
     tick_end(3);
     n += 1;
     stage = 0;

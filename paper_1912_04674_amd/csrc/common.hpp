@@ -2,11 +2,13 @@
 //
 // Method: arXiv:1912.04674 (cylindrical envelope PIC).  Data layout in HBM:
 //   * grids: one array per field, [column][row] with the radius contiguous
-//     (pitch >= nr + 2), columns kept in a ring of `nxa` entries indexed by
-//     lab column mod nxa, so a moving-window shift moves no data;
-//   * particles: structure of arrays, lab cell column (int32) + offset in
-//     the cell (R), Cartesian y, z, momenta, weight (R), id (uint32); two
-//     buffers ping-pong through the per-step counting sort by tile;
+//     (pitch >= nr + 1, a multiple of 16), columns kept in a ring of `nxa`
+//     entries indexed by lab column mod nxa, so a moving-window shift moves
+//     no data;
+//   * particles: structure of arrays, cell word (lab column, radial row),
+//     offsets in the cell along x and r, azimuth, momenta, weight (R), id
+//     (uint32); two buffers ping-pong through the counting sort by tile,
+//     which runs every second step;
 //   * the envelope rows j = 0, 1 additionally in FP64 (FP32 mode).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -16,7 +18,12 @@ namespace envpic {
 
 constexpr int TX = 16;      // tile width along x (cells)
 constexpr int TR = 16;      // tile height along r (cells)
-constexpr int HALO = 2;     // LDS region margin around a tile (cells)
+// Particles move at most one cell per step and are re-sorted by tile every
+// SORT_EVERY steps, so a particle is at most SORT_EVERY cells outside its
+// tile at a gather (SORT_EVERY + 1 at the end of a push); one more cell of
+// margin holds the linear and half-cell-staggered stencils.
+constexpr int SORT_EVERY = 2;
+constexpr int HALO = SORT_EVERY + 1;  // LDS region margin around a tile (cells)
 constexpr int LX = TX + 2 * HALO + 1;
 constexpr int LR = TR + 2 * HALO + 1;
 constexpr int LN = LX * LR; // nodes of an LDS tile region
@@ -85,6 +92,7 @@ struct Layout {
   int* cursor;   // [ntiles]
   int4* items;   // {key, start, count, 0}
   int* n_items;  // scalar
+  int* fill;     // scalar: end of the used slots (injected columns are appended here)
 };
 
 struct Plasma {

@@ -15,7 +15,8 @@ template <class R> struct DepositBufs {
 
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                     const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool defer, hipStream_t st);
+                     const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool defer, bool scatter,
+                     hipStream_t st);
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
                      int* hist, int vacate, const Parts<R>& scr, int* err, int grid, bool defer, hipStream_t st);
@@ -44,9 +45,10 @@ void launch_window(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d0, co
 template <class R>
 void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st);
 
-// `pending` items appended by an injection are added to *bump_items first
+// the items (pending[0]) and slots (pending[1]) appended by an injection
+// are first added to *bump_items and *bump_fill of the layout in use
 void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* bump_items, int* pending, int* err, hipStream_t st);
+                 int* bump_items, int* bump_fill, int* pending, int* err, hipStream_t st);
 
 int diag_scratch_doubles(int max_items, const Geo& g);
 template <class R>

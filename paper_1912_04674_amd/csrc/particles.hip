@@ -209,7 +209,9 @@ template <class R, bool M1> struct SmemMom {
 };
 constexpr int PPT = CHUNK / WG;  // particles per thread of a work item
 
-template <class R, bool M1, bool DEFER>
+// SCATTER: move every particle into the next layout (tile order of x^n);
+// otherwise p is updated in place and the layout is kept.
+template <class R, bool M1, bool DEFER, bool SCATTER>
 __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restrict__ chi_out,
                                                  Parts<R> src, Parts<R> dst, Layout Ls, Layout Ld,
                                                  R* __restrict__ gscr, int* err) {
@@ -279,7 +281,8 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   }
 
   // ---- destination tile (3 x 3 neighbourhood) and rank of each particle,
-  // kept in registers (the loops over a thread's particles are unrolled)
+  // kept in registers (the loops over a thread's particles are unrolled).
+  // Without the scatter only the live flag is kept.
   int slot_rank[PPT];
   bool bad = false;
 #pragma unroll
@@ -289,15 +292,19 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     if (k < count) {
       const unsigned cw = src.cell[start + k];
       if (cw != kDead) {
-        const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
-        const int dtr = clampi(cell_jr(cw) / TR - q.tcr, -1, 1, bad);
-        const int slot = (dtx + 1) * 3 + (dtr + 1);
-        slot_rank[u] = (slot << 24) | atomicAdd(&sm.cnt[slot], 1);
+        if (SCATTER) {
+          const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
+          const int dtr = clampi(cell_jr(cw) / TR - q.tcr, -1, 1, bad);
+          const int slot = (dtx + 1) * 3 + (dtr + 1);
+          slot_rank[u] = (slot << 24) | atomicAdd(&sm.cnt[slot], 1);
+        } else {
+          slot_rank[u] = 0;
+        }
       }
     }
   }
   __syncthreads();
-  if (threadIdx.x < 9) {
+  if (SCATTER && threadIdx.x < 9) {
     const int c = sm.cnt[threadIdx.x];
     if (c > 0) {
       int tx2 = q.tcx + threadIdx.x / 3 - 1;
@@ -307,17 +314,20 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
       sm.base[threadIdx.x] = atomicAdd(&Ld.cursor[tx2 * g.ntr + tr2], c);
     }
   }
-  __syncthreads();
+  if (SCATTER) __syncthreads();
 
   // ---- gather, push, deposit, scatter
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (slot_rank[u] < 0) continue;
     const int p = start + threadIdx.x + u * WG;
-    const int d = sm.base[slot_rank[u] >> 24] + (slot_rank[u] & 0xFFFFFF);
-    if ((long long)d >= g.cap) {  // the scan has flagged the overflow
-      bad = true;
-      continue;
+    int d = p;
+    if (SCATTER) {
+      d = sm.base[slot_rank[u] >> 24] + (slot_rank[u] & 0xFFFFFF);
+      if ((long long)d >= g.cap) {  // the scan has flagged the overflow
+        bad = true;
+        continue;
+      }
     }
     const unsigned cw = src.cell[p];
     const R fx = src.fx[p], fr = src.fr[p], th = src.th[p], w = src.w[p];
@@ -378,15 +388,21 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
           lds_add(&sm.chi[(Px.i + aa) * LR + nb], (double)(wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivol[nb]));
         }
     }
-    dst.cell[d] = cw;
-    dst.fx[d] = fx;
-    dst.fr[d] = fr;
-    dst.th[d] = th;
-    dst.px[d] = pv[0];
-    dst.py[d] = pv[1];
-    dst.pz[d] = pv[2];
-    dst.w[d] = w;
-    dst.id[d] = src.id[p];
+    if (SCATTER) {
+      dst.cell[d] = cw;
+      dst.fx[d] = fx;
+      dst.fr[d] = fr;
+      dst.th[d] = th;
+      dst.px[d] = pv[0];
+      dst.py[d] = pv[1];
+      dst.pz[d] = pv[2];
+      dst.w[d] = w;
+      dst.id[d] = src.id[p];
+    } else {
+      src.px[p] = pv[0];
+      src.py[p] = pv[1];
+      src.pz[p] = pv[2];
+    }
   }
   if (bad) atomicOr(err, ERR_HALO);
   if (DEFER) return;
@@ -895,7 +911,7 @@ __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict
                          int max_items, int* __restrict__ pending, int* err) {
   const long long col = g.shift + g.nx - 1;
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
-  const int total = L.offsets[g.ntiles];
+  const int total = *L.fill;  // end of the used slots
   const int base_items = *L.n_items;
   if ((long long)total + (long long)g.nr * ppc > capacity || base_items + g.ntr > max_items || col > COL_MAX) {
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
@@ -921,7 +937,10 @@ __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict
     const int trt = min(TR, g.nr - idx * TR);
     L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), total + idx * TR * ppc, trt * ppc, 0);
   }
-  if (idx == 0) *pending = g.ntr;
+  if (idx == 0) {
+    pending[0] = g.ntr;           // items appended
+    pending[1] = g.nr * ppc;      // slots appended
+  }
 }
 
 // counts of live particles per tile of their current position
@@ -950,21 +969,31 @@ __global__ void k_hist(Geo g, Parts<R> P, Layout L, int* __restrict__ hist) {
 }
 
 // ============================================================ launchers ==
+template <class R, bool M1, bool DEFER>
+static void launch_momentum_sc(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
+                               const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool scatter,
+                               hipStream_t st) {
+  if (scatter)
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, true>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+  else
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, false>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+}
+
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                     const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool defer,
+                     const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool defer, bool scatter,
                      hipStream_t st) {
   if (grid <= 0) return;
   if (g.modes >= 2) {
     if (defer)
-      hipLaunchKernelGGL((k_momentum<R, true, true>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+      launch_momentum_sc<R, true, true>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
     else
-      hipLaunchKernelGGL((k_momentum<R, true, false>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+      launch_momentum_sc<R, true, false>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
   } else {
     if (defer)
-      hipLaunchKernelGGL((k_momentum<R, false, true>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+      launch_momentum_sc<R, false, true>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
     else
-      hipLaunchKernelGGL((k_momentum<R, false, false>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+      launch_momentum_sc<R, false, false>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
   }
 }
 
@@ -1025,7 +1054,7 @@ void launch_hist(const Geo& g, const Parts<R>& P, const Layout& L, int* hist, in
 
 #define ENVPIC_INST(R)                                                                                          \
   template void launch_momentum<R>(const Geo&, const Grids<R>&, R*, const Parts<R>&, const Parts<R>&,           \
-                                   const Layout&, const Layout&, R*, int*, int, bool, hipStream_t);             \
+                                   const Layout&, const Layout&, R*, int*, int, bool, bool, hipStream_t);       \
   template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
                                    const Layout&, int*, int, const Parts<R>&, int*, int, bool, hipStream_t);    \
   template void launch_deposit_chi<R>(const Geo&, R*, const Parts<R>&, const Layout&, const R*, int*, int,      \

@@ -16,14 +16,16 @@ namespace envpic {
 constexpr int SCAN_T = 1024;
 
 __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, Layout out, long long capacity,
-                                                 int inj_max, int max_items, int* bump_items, int* pending,
-                                                 int* err) {
+                                                 int inj_max, int max_items, int* bump_items, int* bump_fill,
+                                                 int* pending, int* err) {
   __shared__ int s_c[SCAN_T], s_m[SCAN_T];
   const int nt = g.ntiles;
   const int tid = threadIdx.x;
-  if (tid == 0 && pending != nullptr && *pending != 0) {
-    *bump_items += *pending;  // items of the column injected before this scan
-    *pending = 0;
+  if (tid == 0 && pending != nullptr && pending[0] != 0) {
+    *bump_items += pending[0];  // items and slots of the column injected before this scan
+    *bump_fill += pending[1];
+    pending[0] = 0;
+    pending[1] = 0;
   }
   const int per = (nt + SCAN_T - 1) / SCAN_T;
   const int t0 = min(nt, tid * per), t1 = min(nt, t0 + per);
@@ -46,7 +48,8 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
   }
   int ec = s_c[tid] - c, em = s_m[tid] - m;
   const int total = s_c[SCAN_T - 1], n_items = s_m[SCAN_T - 1];
-  const int item_cap = max_items - g.ntr;  // room kept for one injected column
+  // room kept for the columns injected before the next sort (one per step)
+  const int item_cap = max_items - SORT_EVERY * g.ntr;
   for (int t = t0; t < t1; ++t) {
     const int v = hist[t];
     out.offsets[t] = ec;
@@ -66,16 +69,17 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
   }
   if (tid == SCAN_T - 1) {
     out.offsets[nt] = total;
+    *out.fill = total;
     *out.n_items = min(n_items, item_cap);
     if (n_items > item_cap) atomicOr(err, ERR_ITEMS);
-    if ((long long)total + inj_max > capacity) atomicOr(err, ERR_CAPACITY);
+    if ((long long)total + (long long)SORT_EVERY * inj_max > capacity) atomicOr(err, ERR_CAPACITY);
   }
 }
 
 void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* bump_items, int* pending, int* err, hipStream_t st) {
+                 int* bump_items, int* bump_fill, int* pending, int* err, hipStream_t st) {
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, st, g, hist, out, capacity, inj_max, max_items, bump_items,
-                     pending, err);
+                     bump_fill, pending, err);
 }
 
 // ---------------------------------------------------------- diagnostics --
