@@ -215,6 +215,106 @@ def test_window_modes01_parity(E, oracle_mod, prec, tf, tp):
 
 
 # ------------------------------------------------------------ API paths --
+# ------------------------------------------------------------ edge cases --
+RAGGED = dict(name="ragged", nx=101, nr=21, dx=0.8, dr=1.5, dt=0.6, n_modes=2, ppc=(2, 3, 3),
+              profile="perturb", n0=0.003, perturb=0.2, a0=1.5, w0=12.0, tau=12.0,
+              x_c=101 * 0.8 - 30.0, x_f=101 * 0.8 - 30.0, moving_window=1, seed=191204677)
+
+
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_ragged_grid_parity(E, oracle_mod, prec, tf, tp):
+    """Grid sizes that fill no tile exactly (101 x 21), odd particles per cell
+    (2 x 3 x 3), per-cell density noise, moving window and modes 0-1."""
+    say("ragged", prec)
+    g = E.Sim(RAGGED, _prec(E, prec))
+    r = oracle_mod.OracleSim(RAGGED)
+    g.step(60)
+    r.step(60)
+    assert g.state() == r.state()
+    compare_fields(g, r, tf, modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_vacuum_run_has_no_particles(E, oracle_mod, prec):
+    """No plasma: zero particles through every stage; the envelope and the
+    (zero) fields match the oracle."""
+    cfg = scaled(C2_SMALL, profile="none", name="vacuum")
+    g = E.Sim(cfg, _prec(E, prec))
+    r = oracle_mod.OracleSim(cfg)
+    g.step(30)
+    r.step(30)
+    assert g.state()[2] == r.state()[2] == 0
+    compare_fields(g, r, 1e-9 if prec == "fp64" else 1e-4, names=("env", "env_prev", "chi", "ex", "jx"))
+    d = g.diagnostics()
+    assert d["count"] == 0 and d["kin"] == 0 and d["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_plasma_without_laser_stays_at_rest(E, prec):
+    """a0 = 0: a neutral plasma at rest is an exact equilibrium of the
+    discrete loop (no force, no current): momenta and fields stay zero and
+    chi = n0 at interior nodes."""
+    cfg = scaled(C1, a0=0.0, name="rest")
+    g = E.Sim(cfg, _prec(E, prec))
+    g.step(20)
+    P = g.get_particles()
+    assert max(np.abs(P[k]).max() for k in ("px", "py", "pz")) == 0.0
+    for n in ("ex", "er", "bt", "jx", "jr", "env"):
+        assert np.abs(g.get_field(n)).max() == 0.0, n
+    chi = g.get_field("chi")[1:-1, 1:-1]
+    assert np.abs(chi - cfg["n0"]).max() <= (1e-12 if prec == "fp64" else 2e-6) * cfg["n0"]
+
+
+@pytest.mark.parametrize("n", [0, 1, 7])
+def test_tiny_particle_sets(E, oracle_mod, n):
+    """Empty and near-empty particle sets through a full step (FP64)."""
+    cfg = dict(nx=48, nr=16, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=0.5, w0=6.0, tau=8.0,
+               x_c=20.0, x_f=20.0, ppc=(1, 1, 1))
+    g = E.Sim(cfg, E.FP64)
+    r = oracle_mod.OracleSim(cfg)
+    parts = random_particles(cfg, n, seed=31 + n, margin=4, pmax=0.3)
+    g.set_particles(parts)
+    r.set_particles(parts)
+    g.step(10)
+    r.step(10)
+    assert g.state()[2] == r.state()[2] == n
+    compare_fields(g, r, 1e-9, names=("env", "chi", "ex", "er", "bt", "jx", "jr"), modes=2 if n else 1)
+    if n:
+        compare_particles(g.get_particles(), r.get_particles(), 1e-9, 1e-9)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_axis_crossing_and_wall_reflection(E, oracle_mod, prec):
+    """Particles aimed through the axis and at r_max: crossings of r = 0
+    and specular reflection at the wall follow the oracle."""
+    cfg = dict(nx=48, nr=12, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=0.0, ppc=(1, 1, 1))
+    rng = np.random.default_rng(41)
+    n = 400
+    x = rng.uniform(8.0, 30.0, n)
+    th = rng.uniform(-np.pi, np.pi, n)
+    near = np.arange(n) < n // 2
+    r = np.where(near, rng.uniform(0.05, 2.0, n), rng.uniform(16.0, 17.9, n))
+    y, z = r * np.cos(th), r * np.sin(th)
+    # inward through the axis for the first half, outward to the wall for the rest
+    sgn = np.where(near, -1.0, 1.0)
+    pr = sgn * rng.uniform(0.5, 3.0, n)
+    pt = rng.uniform(-0.3, 0.3, n)
+    parts = dict(x=x, y=y, z=z, px=rng.uniform(-0.2, 0.2, n), py=pr * np.cos(th) - pt * np.sin(th),
+                 pz=pr * np.sin(th) + pt * np.cos(th), w=rng.uniform(0.5, 1.5, n) * 1e-3,
+                 id=np.arange(n, dtype=np.uint32))
+    g = E.Sim(cfg, _prec(E, prec))
+    o = oracle_mod.OracleSim(cfg)
+    g.set_particles(parts)
+    o.set_particles(parts)
+    g.step(12)
+    o.step(12)
+    tol = 1e-9 if prec == "fp64" else 1e-4
+    compare_fields(g, o, tol, names=("chi", "ex", "er", "bt", "jx", "jr"), modes=2)
+    compare_particles(g.get_particles(), o.get_particles(), 1e-9 if prec == "fp64" else 1e-3,
+                      1e-9 if prec == "fp64" else 1e-3)
+
+
 def test_deferred_deposits_match_fused(E):
     say("deferred deposits")
     a = E.Sim(C2_SMALL, E.FP64)
