@@ -36,7 +36,7 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // ------------------------------------------------------------ geometry --
 struct Sizes {
-  int nxa, pitch, ntxa, ntr, ntiles, ppc, max_items;
+  int nxa, pitch, ntxa, ntr, ntiles, ppc, max_items, chunk;
   long long capacity;
   size_t ngrid;  // elements per grid
 };
@@ -52,7 +52,11 @@ Sizes sizes_of(const envpic_params& p) {
   const long long window = (long long)p.nx * p.nr * s.ppc;
   // one window of particles plus the columns injected between two sorts
   s.capacity = p.capacity > 0 ? p.capacity : window + (SORT_EVERY + 1LL) * p.nr * s.ppc + 1024;
-  s.max_items = (int)(s.ntiles + s.capacity / CHUNK + SORT_EVERY * s.ntr + 16);
+  // work-item size: about four items per compute unit (256 of them) so that
+  // small runs fill the device, at most CHUNK, a multiple of WG
+  const long long per = window / (4LL * 256);
+  s.chunk = (int)std::max<long long>(WG, std::min<long long>(CHUNK, per / WG * WG));
+  s.max_items = (int)(s.ntiles + s.capacity / s.chunk + SORT_EVERY * s.ntr + 16);
   s.ngrid = (size_t)s.nxa * s.pitch;
   return s;
 }
@@ -162,6 +166,15 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   f.bxb1 = cv.take<C>(n1);
   f.brb1 = cv.take<C>(n1);
   f.btb1 = cv.take<C>(n1);
+  f.ex_n = cv.take<R>(ng);
+  f.er_n = cv.take<R>(ng);
+  f.bt_n = cv.take<R>(ng);
+  f.ex1_n = cv.take<C>(n1);
+  f.er1_n = cv.take<C>(n1);
+  f.et1_n = cv.take<C>(n1);
+  f.bx1_n = cv.take<C>(n1);
+  f.br1_n = cv.take<C>(n1);
+  f.bt1_n = cv.take<C>(n1);
   for (int b = 0; b < 2; ++b) {
     DepositBufs<R>& d = S.dep[b];
     d.chi = cv.take<R>(ng);
@@ -346,6 +359,7 @@ template <class R> struct SimT : envpic_sim {
     g.dx = p.dx;
     g.dr = p.dr;
     g.dt = p.dt;
+    g.chunk = sz.chunk;
     // fixed-point scale of the mode-1 current sums: 2^49 over the largest
     // |2 q w v S / V| = 2 w_max / V_0, V_0 = pi dr^2 dx / 4
     const double cmax = 2.0 * wmax * 4.0 / (3.14159265358979323846 * p.dr * p.dr * p.dx);
@@ -377,13 +391,13 @@ template <class R> struct SimT : envpic_sim {
   int launched(const char* what) { return hip_check(hipGetLastError(), what); }
 
   // host-built layout of a particle set sorted by tile key: offsets per key
-  // and work items of <= CHUNK particles
+  // and work items of <= chunk particles
   int upload_layout(int b, const std::vector<int>& counts) {
     std::vector<int> off(sz.ntiles + 1, 0);
     std::vector<int4> items;
     for (int t = 0; t < sz.ntiles; ++t) {
       off[t + 1] = off[t] + counts[t];
-      const int nm = (counts[t] + CHUNK - 1) / CHUNK;  // equal shares, as in the device scan
+      const int nm = (counts[t] + sz.chunk - 1) / sz.chunk;  // equal shares, as in the device scan
       for (int k = 0; k < nm; ++k) {
         const int lo = (int)((long long)k * counts[t] / nm), hi = (int)((long long)(k + 1) * counts[t] / nm);
         items.push_back(make_int4(t, off[t] + lo, hi - lo, 0));
@@ -527,6 +541,18 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 3 || !deposit_done) return fail(ENVPIC_EORDER, "field stage out of order");
     tick_begin();
     launch_maxwell<R>(geo(), S.grids, S.dep[n & 1], S.dep[(n + 1) & 1], stream);
+    {
+      Grids<R>& G = S.grids;  // the new E, B become the current ones
+      std::swap(G.ex, G.ex_n);
+      std::swap(G.er, G.er_n);
+      std::swap(G.bt, G.bt_n);
+      std::swap(G.ex1, G.ex1_n);
+      std::swap(G.er1, G.er1_n);
+      std::swap(G.et1, G.et1_n);
+      std::swap(G.bx1, G.bx1_n);
+      std::swap(G.br1, G.br1_n);
+      std::swap(G.bt1, G.bt1_n);
+    }
     if (shift_due()) {
       shift += 1;
       const Geo g = geo();

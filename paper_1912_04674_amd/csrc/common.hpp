@@ -28,7 +28,7 @@ constexpr int LX = TX + 2 * HALO + 1;
 constexpr int LR = TR + 2 * HALO + 1;
 constexpr int LN = LX * LR; // nodes of an LDS tile region
 constexpr int WG = 512;     // work-group size of the particle kernels
-constexpr int CHUNK = 4096; // max particles per work item
+constexpr int CHUNK = 4096; // largest work item (particles); small runs use smaller items
 // A particle's cell is one 32-bit word: lab column << 12 | radial row.  The
 // position inside the cell is kept as FP32 (or FP64) offsets along x and r,
 // so neither a long moving-window run nor a large radius erodes the
@@ -65,6 +65,7 @@ struct Geo {
   double dx, dr, dt;
   float fix;         // fixed-point scale of the FP32 path's mode-1 current sums
   double unfix;      // 1 / fix
+  int chunk;         // particles per work item at most (<= CHUNK, a multiple of WG)
 };
 
 template <class R> struct Parts {
@@ -85,6 +86,10 @@ template <class R> struct Grids {
   C *env, *envp;
   double2 *ax, *axp;  // FP64 envelope rows 0, 1 of A^n and A^{n-1}: [phys col][2]
   C *ex1, *er1, *et1, *bx1, *br1, *bt1, *bxb1, *brb1, *btb1, *jx1, *jr1, *jt1;
+  // second copies of E and B: the field update writes E^{n+1}, B^{n+3/2}
+  // here and the host swaps them with the current ones
+  R *ex_n, *er_n, *bt_n;
+  C *ex1_n, *er1_n, *et1_n, *bx1_n, *br1_n, *bt1_n;
 };
 
 struct Layout {

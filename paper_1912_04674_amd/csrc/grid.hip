@@ -90,69 +90,141 @@ __global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp6
   f.envp[o] = mk<C>((R)pre_r * br - (R)pre_i * bi, (R)pre_r * bi + (R)pre_i * br);
 }
 
-// ----------------------------------------------------- Ampere: E^{n+1} --
-// E_r(i, j+1/2) -= dt [(B_t(i+1/2) - B_t(i-1/2))/dx + J_r];   E_r = 0 at x ends
-// E_x(i+1/2, j) += dt [(r_{j+1/2} B_t(j+1/2) - r_{j-1/2} B_t(j-1/2))/(r_j dr) - J_x]
-//   axis: (1/r) d(r B_t)/dr -> 4 B_t(1/2)/dr (flux through the disc r < dr/2);
-//   E_x = 0 at r_max (perfect conductor).
-// Mode 1: d/dtheta -> -i (F = Re[F_1 e^{-i theta}]); axial components vanish
-// on the axis, E_t there from the odd ghost B_x(-1/2) = -B_x(1/2).
-// The deposits for the next step (chi, J) are cleared here.
-template <class R, bool M1>
-__global__ void k_maxwell_E(Geo g, Grids<R> f, DepositBufs<R> din, DepositBufs<R> dnext) {
+// ----------------------------------------------- Ampere and Faraday --
+// Ampere: E^{n+1} from E^n, B^{n+1/2}, J^{n+1/2}
+//   E_r(i, j+1/2) -= dt [(B_t(i+1/2) - B_t(i-1/2))/dx + J_r];   E_r = 0 at x ends
+//   E_x(i+1/2, j) += dt [(r_{j+1/2} B_t(j+1/2) - r_{j-1/2} B_t(j-1/2))/(r_j dr) - J_x]
+//     axis: (1/r) d(r B_t)/dr -> 4 B_t(1/2)/dr (flux through the disc r < dr/2);
+//     E_x = 0 at r_max (perfect conductor).
+//   Mode 1: d/dtheta -> -i (F = Re[F_1 e^{-i theta}]); axial components
+//   vanish on the axis, E_t there from the odd ghost B_x(-1/2) = -B_x(1/2).
+// Faraday: B^{n+3/2} from B^{n+1/2} and E^{n+1}, and Bbar^{n+1} = (B^{n+1/2} + B^{n+3/2})/2
+//   B_t(i+1/2, j+1/2) += dt [(E_x(j+1) - E_x(j))/dr - (E_r(i+1) - E_r(i))/dx]
+//   B_x(i, j+1/2) -= dt [((j+1) E_t(j+1) - j E_t(j))/((j+1/2) dr) + (i/r_{j+1/2}) E_r]
+//   B_r(i+1/2, j) += dt [(i/r) E_x + (E_t(i+1) - E_t(i))/dx]; on the axis E_x/r -> E_x(1)/dr
+// One kernel: a work group computes E^{n+1} on its tile of nodes plus one
+// column and one row beyond (recomputed by the neighbour that owns them,
+// with the same arithmetic), keeps it in LDS, then advances B on its tile.
+// E^n and B^{n+1/2} are only read and the new values go to the second
+// copies (ex_n, ..., bt1_n), so no work group sees another's output; Bbar
+// is written in place.  The deposits of the next step (chi, J) are cleared
+// on the way.
+template <class R, bool M1> struct ENew {
   using C = typename cplx_of<R>::type;
-  const int nr1 = g.nr + 1;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)(g.nx + 1) * nr1) return;
-  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
+  R ex, er;
+  C ex1, er1, et1;
+};
+
+template <class R, bool M1>
+__device__ inline ENew<R, M1> ampere(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, int i, int j) {
+  using C = typename cplx_of<R>::type;
+  ENew<R, M1> e;
   const int pc = phys_col(g, i);
   const size_t o = (size_t)pc * g.pitch + j;
   const size_t om = i > 0 ? (size_t)phys_col(g, i - 1) * g.pitch + j : o;
   const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
   const bool xin = i > 0 && i < g.nx;
-  if (j <= g.nr - 1) {
-    f.er[o] = xin ? f.er[o] - dt * ((f.bt[o] - f.bt[om]) * idx_ + din.jr[o]) : (R)0;
-  }
+  e.er = (j <= g.nr - 1 && xin) ? f.er[o] - dt * ((f.bt[o] - f.bt[om]) * idx_ + din.jr[o]) : (R)0;
+  e.ex = 0;
   if (i <= g.nx - 1) {
-    R e;
-    if (j == g.nr) {
-      e = 0;
-    } else if (j == 0) {
-      e = f.ex[o] + dt * ((R)4 * f.bt[o] * idr - din.jx[o]);
-    } else {
-      e = f.ex[o] + dt * (((R)(j + 0.5) * f.bt[o] - (R)(j - 0.5) * f.bt[o - 1]) * ((R)(1.0 / j) * idr) - din.jx[o]);
+    if (j == 0) {
+      e.ex = f.ex[o] + dt * ((R)4 * f.bt[o] * idr - din.jx[o]);
+    } else if (j < g.nr) {
+      e.ex = f.ex[o] + dt * (((R)(j + 0.5) * f.bt[o] - (R)(j - 0.5) * f.bt[o - 1]) * ((R)(1.0 / j) * idr) - din.jx[o]);
     }
-    f.ex[o] = e;
   }
   if (M1) {
     const C z = mk<C>((R)0, (R)0);
-    if (i <= g.nx - 1) {
-      C e = z;
-      if (j >= 1 && j <= g.nr - 1) {
-        const R irj = (R)(1.0 / (j * g.dr));
-        const C curl = cadd(cscale(csub(cscale(f.bt1[o], (R)(j + 0.5)), cscale(f.bt1[o - 1], (R)(j - 0.5))), irj),
-                            cscale(cmuli(f.br1[o]), irj));
-        e = cadd(f.ex1[o], cscale(csub(curl, din.jx1[o]), dt));
-      }
-      f.ex1[o] = e;
+    e.ex1 = z;
+    e.er1 = z;
+    e.et1 = z;
+    if (i <= g.nx - 1 && j >= 1 && j <= g.nr - 1) {
+      const R irj = (R)(1.0 / (j * g.dr));
+      const C curl = cadd(cscale(csub(cscale(f.bt1[o], (R)(j + 0.5)), cscale(f.bt1[o - 1], (R)(j - 0.5))), irj),
+                          cscale(cmuli(f.br1[o]), irj));
+      e.ex1 = cadd(f.ex1[o], cscale(csub(curl, din.jx1[o]), dt));
     }
+    if (j <= g.nr - 1 && xin) {
+      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+      const C curl = csub(cscale(cmuli(f.bx1[o]), -irh), cscale(csub(f.bt1[o], f.bt1[om]), idx_));
+      e.er1 = cadd(f.er1[o], cscale(csub(curl, din.jr1[o]), dt));
+      const C dbr = cscale(csub(f.br1[o], f.br1[om]), idx_);
+      const C dbx = j == 0 ? cscale(f.bx1[o], (R)2 * idr) : cscale(csub(f.bx1[o], f.bx1[o - 1]), idr);
+      e.et1 = cadd(f.et1[o], cscale(csub(csub(dbr, dbx), din.jt1[o]), dt));
+    }
+  }
+  return e;
+}
+
+constexpr int MW_TI = 4, MW_TJ = 64;  // tile of a Maxwell work group: 4 columns x 64 rows
+
+template <class R, bool M1>
+__global__ __launch_bounds__(MW_TI * MW_TJ) void k_maxwell(Geo g, Grids<R> f, DepositBufs<R> din,
+                                                            DepositBufs<R> dnext) {
+  using C = typename cplx_of<R>::type;
+  constexpr int HI = MW_TI + 1, HJ = MW_TJ + 1, HN = HI * HJ;
+  __shared__ R s_ex[HN], s_er[HN];
+  __shared__ C s_ex1[M1 ? HN : 1], s_er1[M1 ? HN : 1], s_et1[M1 ? HN : 1];
+  const int i0 = blockIdx.y * MW_TI, j0 = blockIdx.x * MW_TJ;
+  // ---- E^{n+1} on the tile and its +1 column / +1 row
+  for (int k = threadIdx.x; k < HN; k += MW_TI * MW_TJ) {
+    const int a = k / HJ, b = k - (k / HJ) * HJ;
+    const int i = i0 + a, j = j0 + b;
+    if (i > g.nx || j > g.nr) continue;
+    const ENew<R, M1> e = ampere<R, M1>(g, f, din, i, j);
+    s_ex[k] = e.ex;
+    s_er[k] = e.er;
+    if (M1) {
+      s_ex1[k] = e.ex1;
+      s_er1[k] = e.er1;
+      s_et1[k] = e.et1;
+    }
+  }
+  __syncthreads();
+  const int a = threadIdx.x / MW_TJ, b = threadIdx.x - (threadIdx.x / MW_TJ) * MW_TJ;
+  const int i = i0 + a, j = j0 + b;
+  if (i > g.nx || j > g.nr) return;
+  const int k = a * HJ + b, kp = k + HJ;  // (i, j), (i+1, j)
+  const size_t o = (size_t)phys_col(g, i) * g.pitch + j;
+  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  // the new E of the owned node
+  if (j <= g.nr - 1) f.er_n[o] = s_er[k];
+  if (i <= g.nx - 1) f.ex_n[o] = s_ex[k];
+  if (M1) {
+    if (i <= g.nx - 1) f.ex1_n[o] = s_ex1[k];
+    if (j <= g.nr - 1) f.er1_n[o] = s_er1[k];
+    f.et1_n[o] = s_et1[k];
+  }
+  // ---- B^{n+3/2} and Bbar^{n+1}
+  if (i <= g.nx - 1 && j <= g.nr - 1) {
+    const R b0 = f.bt[o];
+    const R b1 = b0 + dt * ((s_ex[k + 1] - s_ex[k]) * idr - (s_er[kp] - s_er[k]) * idx_);
+    f.bt_n[o] = b1;
+    f.btb[o] = (R)0.5 * (b0 + b1);
+  }
+  if (M1) {
     if (j <= g.nr - 1) {
-      C e = z;
-      if (xin) {
-        const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
-        const C curl = csub(cscale(cmuli(f.bx1[o]), -irh), cscale(csub(f.bt1[o], f.bt1[om]), idx_));
-        e = cadd(f.er1[o], cscale(csub(curl, din.jr1[o]), dt));
-      }
-      f.er1[o] = e;
+      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+      const C b0 = f.bx1[o];
+      const C curl = cadd(cscale(csub(cscale(s_et1[k + 1], (R)(j + 1)), cscale(s_et1[k], (R)j)), irh),
+                          cscale(cmuli(s_er1[k]), irh));
+      const C b1 = csub(b0, cscale(curl, dt));
+      f.bx1_n[o] = b1;
+      f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
     }
-    {
-      C e = z;
-      if (xin && j <= g.nr - 1) {
-        const C dbr = cscale(csub(f.br1[o], f.br1[om]), idx_);
-        const C dbx = j == 0 ? cscale(f.bx1[o], (R)2 * idr) : cscale(csub(f.bx1[o], f.bx1[o - 1]), idr);
-        e = cadd(f.et1[o], cscale(csub(csub(dbr, dbx), din.jt1[o]), dt));
+    if (i <= g.nx - 1) {
+      const C exr = j == 0 ? cscale(s_ex1[k + 1], idr) : cscale(s_ex1[k], (R)(1.0 / (j * g.dr)));
+      const C b0 = f.br1[o];
+      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(s_et1[kp], s_et1[k]), idx_)), dt));
+      f.br1_n[o] = b1;
+      f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
+      if (j <= g.nr - 1) {
+        const C c0 = f.bt1[o];
+        const C c1 = cadd(c0, cscale(csub(cscale(csub(s_ex1[k + 1], s_ex1[k]), idr),
+                                          cscale(csub(s_er1[kp], s_er1[k]), idx_)), dt));
+        f.bt1_n[o] = c1;
+        f.btb1[o] = cscale(cadd(c0, c1), (R)0.5);
       }
-      f.et1[o] = e;
     }
   }
   dnext.chi[o] = 0;
@@ -163,55 +235,6 @@ __global__ void k_maxwell_E(Geo g, Grids<R> f, DepositBufs<R> din, DepositBufs<R
     dnext.jx1[o] = z;
     dnext.jr1[o] = z;
     dnext.jt1[o] = z;
-  }
-}
-
-// ---------------------------------------------- Faraday: B^{n+3/2}, Bbar --
-// B_t(i+1/2, j+1/2) += dt [(E_x(j+1) - E_x(j))/dr - (E_r(i+1) - E_r(i))/dx]
-// Bbar^{n+1} = (B^{n+1/2} + B^{n+3/2}) / 2
-template <class R, bool M1>
-__global__ void k_maxwell_B(Geo g, Grids<R> f) {
-  using C = typename cplx_of<R>::type;
-  const int nr1 = g.nr + 1;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)(g.nx + 1) * nr1) return;
-  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
-  const int pc = phys_col(g, i);
-  const size_t o = (size_t)pc * g.pitch + j;
-  const size_t op = i < g.nx ? (size_t)phys_col(g, i + 1) * g.pitch + j : o;
-  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
-  if (i <= g.nx - 1 && j <= g.nr - 1) {
-    const R b0 = f.bt[o];
-    const R b1 = b0 + dt * ((f.ex[o + 1] - f.ex[o]) * idr - (f.er[op] - f.er[o]) * idx_);
-    f.bt[o] = b1;
-    f.btb[o] = (R)0.5 * (b0 + b1);
-  }
-  if (M1) {
-    if (j <= g.nr - 1) {
-      // B_x(i, j+1/2) -= dt [((j+1) E_t(j+1) - j E_t(j))/((j+1/2) dr) + (i/r_{j+1/2}) E_r]
-      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
-      const C b0 = f.bx1[o];
-      const C curl = cadd(cscale(csub(cscale(f.et1[o + 1], (R)(j + 1)), cscale(f.et1[o], (R)j)), irh),
-                          cscale(cmuli(f.er1[o]), irh));
-      const C b1 = csub(b0, cscale(curl, dt));
-      f.bx1[o] = b1;
-      f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
-    }
-    if (i <= g.nx - 1) {
-      // B_r(i+1/2, j) += dt [(i/r) E_x + (E_t(i+1) - E_t(i))/dx]; on the axis E_x/r -> E_x(1)/dr
-      const C exr = j == 0 ? cscale(f.ex1[o + 1], idr) : cscale(f.ex1[o], (R)(1.0 / (j * g.dr)));
-      const C b0 = f.br1[o];
-      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(f.et1[op], f.et1[o]), idx_)), dt));
-      f.br1[o] = b1;
-      f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
-      if (j <= g.nr - 1) {
-        const C c0 = f.bt1[o];
-        const C c1 = cadd(c0, cscale(csub(cscale(csub(f.ex1[o + 1], f.ex1[o]), idr),
-                                          cscale(csub(f.er1[op], f.er1[o]), idx_)), dt));
-        f.bt1[o] = c1;
-        f.btb1[o] = cscale(cadd(c0, c1), (R)0.5);
-      }
-    }
   }
 }
 
@@ -312,13 +335,11 @@ void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_row
 template <class R>
 void launch_maxwell(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
                     hipStream_t st) {
-  if (g.modes >= 2) {
-    hipLaunchKernelGGL((k_maxwell_E<R, true>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, din, dnext);
-    hipLaunchKernelGGL((k_maxwell_B<R, true>), dim3(node_blocks(g)), dim3(256), 0, st, g, f);
-  } else {
-    hipLaunchKernelGGL((k_maxwell_E<R, false>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, din, dnext);
-    hipLaunchKernelGGL((k_maxwell_B<R, false>), dim3(node_blocks(g)), dim3(256), 0, st, g, f);
-  }
+  const dim3 grid((g.nr + 1 + MW_TJ - 1) / MW_TJ, (g.nx + 1 + MW_TI - 1) / MW_TI);
+  if (g.modes >= 2)
+    hipLaunchKernelGGL((k_maxwell<R, true>), grid, dim3(MW_TI * MW_TJ), 0, st, g, f, din, dnext);
+  else
+    hipLaunchKernelGGL((k_maxwell<R, false>), grid, dim3(MW_TI * MW_TJ), 0, st, g, f, din, dnext);
 }
 
 template <class R>

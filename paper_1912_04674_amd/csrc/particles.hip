@@ -5,11 +5,12 @@
 // current deposit, tile histogram), loading and injection.
 //
 // Work decomposition: particles are counting-sorted by 16 x 16-cell tiles
-// every step; a work item is (tile, contiguous range of <= CHUNK particles).
-// A work group stages the fields of its tile plus a 2-cell halo in LDS,
-// accumulates the deposits of its particles in LDS and flushes them to HBM
-// once (atomic adds, since halos overlap).  Particles drift at most one cell
-// per step (dt < dx, dt < dr), which the halo covers.
+// every SORT_EVERY steps; a work item is (tile, contiguous range of at most
+// g.chunk particles).  A work group stages the fields of its tile plus a
+// HALO-cell margin in LDS, accumulates the deposits of its particles in LDS
+// and flushes them to HBM once (atomic adds, since halos overlap).
+// Particles drift at most one cell per step (dt < dx, dt < dr), so between
+// two sorts they stay inside the margin.
 //
 // Positions: lab cell (column, row) in one word plus offsets in the cell
 // along x and r and the azimuth; the push is Cartesian (Sec. 3), and the

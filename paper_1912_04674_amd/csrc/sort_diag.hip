@@ -10,7 +10,7 @@ namespace envpic {
 // ----------------------------------------------------------------- scan --
 // One work group of 1024 threads: exclusive scan of the tile counts into
 // offsets (and the scatter cursors), work items (a tile of v particles gives
-// ceil(v / CHUNK) items of equal size), and a reset of the histogram for the
+// ceil(v / chunk) items of equal size), and a reset of the histogram for the
 // next step.  Flags when the particles plus one injected column would not
 // fit.
 constexpr int SCAN_T = 1024;
@@ -33,7 +33,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
   for (int t = t0; t < t1; ++t) {
     const int v = hist[t];
     c += v;
-    m += (v + CHUNK - 1) / CHUNK;
+    m += (v + g.chunk - 1) / g.chunk;
   }
   s_c[tid] = c;
   s_m[tid] = m;
@@ -54,7 +54,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
     const int v = hist[t];
     out.offsets[t] = ec;
     out.cursor[t] = ec;
-    const int nm = (v + CHUNK - 1) / CHUNK;
+    const int nm = (v + g.chunk - 1) / g.chunk;
     for (int k = 0; k < nm; ++k) {
       // the nm items of a tile share its particles evenly
       const int lo = (int)((long long)k * v / nm), hi = (int)((long long)(k + 1) * v / nm);
