@@ -709,13 +709,36 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
   __syncthreads();
 
   bool bad = false;
-  for (int k = threadIdx.x; k < count; k += WG) {
+  // the next particle's record is loaded before this one is processed
+  // (the stores below would otherwise keep the loads from moving up)
+  struct Rec {
+    unsigned cw;
+    R fx, fr, th, w, px, py, pz;
+  };
+  auto fetch = [&](int k) {
+    Rec r;
     const int p = start + k;
-    const unsigned cw = P.cell[p];
+    r.cw = P.cell[p];
+    r.fx = P.fx[p];
+    r.fr = P.fr[p];
+    r.th = P.th[p];
+    r.w = P.w[p];
+    r.px = P.px[p];
+    r.py = P.py[p];
+    r.pz = P.pz[p];
+    return r;
+  };
+  Rec nxt;
+  if (threadIdx.x < count) nxt = fetch(threadIdx.x);
+  for (int k = threadIdx.x; k < count; k += WG) {
+    const Rec cur = nxt;
+    if (k + WG < count) nxt = fetch(k + WG);
+    const int p = start + k;
+    const unsigned cw = cur.cw;
     if (cw == kDead) continue;
-    const R fx = P.fx[p], fr = P.fr[p], th = P.th[p], w = P.w[p];
-    const R px = P.px[p];
-    R py = P.py[p], pz = P.pz[p];
+    const R fx = cur.fx, fr = cur.fr, th = cur.th, w = cur.w;
+    const R px = cur.px;
+    R py = cur.py, pz = cur.pz;
     const int a = clampi(cell_ix(cw) - q.X0, 0, LX - 2, bad);
     const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
     const R ph = interp2<R>(sm.phh, primal_w<R>(a, fx), primal_w<R>(b, fr));
