@@ -116,7 +116,9 @@ template <class R> struct State {
   Grids<R> grids;
   DepositBufs<R> dep[2];
   Layout lay[2];
-  int* hist;
+  int* hist;    // particles per tile at the next sort
+  int* ccount;  // particles per cell at the next sort ([phys col][row], as the grids)
+  int* ccur;    // per-cell scatter cursors of the next sort
   int* err;
   int* pending;  // [items, slots] appended by the last injection, not yet counted
   double* diag_scratch;
@@ -197,6 +199,8 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
     L.fill = cv.take<int>(1);
   }
   S.hist = cv.take<int>((size_t)s.ntiles);
+  S.ccount = cv.take<int>(ng);
+  S.ccur = cv.take<int>(ng);
   S.err = cv.take<int>(1);
   S.pending = cv.take<int>(2);
   Geo g{};
@@ -226,6 +230,7 @@ struct envpic_sim {
   int stage = 0;     // next expected stage: 0 momentum, 1 envelope, 2 position, 3 field
   int cur = 0;       // particle buffer holding the current state
   int64_t sorted_at = 0;  // step whose positions the layout of P[cur] is sorted by
+  int64_t n_sorts = 0;    // sorts so far (selects tile or cell order)
   bool deferred = false, deposit_done = true;
   int chi_last = 0;  // deposit buffer of the last momentum stage
   // stage timing (events on the simulation's stream)
@@ -303,6 +308,8 @@ struct envpic_sim {
   virtual int check_err() = 0;
   virtual int clear_deposits() = 0;
 
+  // the momentum stage of the next step re-sorts the particles
+  bool presort() const { return n + 1 - sorted_at >= SORT_EVERY; }
   bool shift_due() const {
     return p.moving_window && (double)(n + 1) * p.dt >= (double)(shift + 1) * p.dx;
   }
@@ -414,15 +421,7 @@ template <class R> struct SimT : envpic_sim {
     return hip_check(hipStreamSynchronize(stream), "layout upload");
   }
 
-  // layout of the other buffer from the live particles of P[cur]
-  int rebuild_next_layout() {
-    const Geo g = geo();
-    launch_hist<R>(g, S.parts[cur], S.lay[cur], S.hist, sz.max_items, stream);
-    launch_scan(g, S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items,
-                S.lay[cur].fill, S.pending, S.err, stream);
-    sorted_at = n;  // the particles of P[cur] sit in their tiles
-    return launched("hist/scan");
-  }
+
 
   int init() override {
     int rc;
@@ -441,7 +440,7 @@ template <class R> struct SimT : envpic_sim {
     if (p.profile != ENVPIC_PROFILE_NONE) launch_init_particles<R>(g, plasma(), S.parts[cur], S.lay[cur].offsets, stream);
     launch_init_envelope<R>(g, S.grids, laser(), fp64_rows ? 1 : 0, stream);
     if ((rc = launched("init kernels"))) return rc;
-    if ((rc = rebuild_next_layout())) return rc;
+    sorted_at = n;  // the particles of P[cur] sit in their tiles
     if ((rc = hip_check(hipStreamSynchronize(stream), "init"))) return rc;
     return check_err();
   }
@@ -481,13 +480,16 @@ template <class R> struct SimT : envpic_sim {
     // re-sort when the particles have had SORT_EVERY steps to drift from
     // their tiles; in between, p is updated in place
     const bool scatter = n - sorted_at >= SORT_EVERY;
+    // every CELL_SORT_EVERY-th sort orders the tiles by cell again
+    const int mode = !scatter ? SCAT_NONE : (n_sorts % CELL_SORT_EVERY == 0 ? SCAT_CELL : SCAT_TILE);
     tick_begin();
-    launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.scr.w,
-                       S.err, sz.max_items, defer, scatter, stream);
+    launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.ccur,
+                       S.scr.w, S.err, sz.max_items, defer, mode, stream);
     tick_end(0);
     if (scatter) {
       cur = 1 - cur;
       sorted_at = n;
+      n_sorts += 1;
     }
     chi_last = d;
     stage = 1;
@@ -528,8 +530,8 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 2) return fail(ENVPIC_EORDER, "position stage out of order");
     const Geo g = geo();
     tick_begin();
-    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.hist, shift_due() ? 1 : 0, S.scr, S.err,
-                       sz.max_items, defer, stream);
+    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.ccount, shift_due() ? 1 : 0,
+                       presort() ? 1 : 0, S.scr, S.err, sz.max_items, defer, stream);
     tick_end(2);
     stage = 3;
     deferred = defer;
@@ -558,11 +560,13 @@ template <class R> struct SimT : envpic_sim {
       const Geo g = geo();
       launch_window<R>(g, S.grids, S.dep[0], S.dep[1], fp64_rows ? 1 : 0, stream);
       if (p.profile != ENVPIC_PROFILE_NONE)
-        launch_inject<R>(g, plasma(), S.parts[cur], S.lay[cur], S.hist, sz.capacity, sz.max_items, S.pending, S.err,
-                         stream);
+        launch_inject<R>(g, plasma(), S.parts[cur], S.lay[cur], S.ccount, presort() ? 1 : 0, sz.capacity,
+                         sz.max_items, S.pending, S.err, stream);
     }
+    // before a sort: per-cell cursors and tile totals, then the new layout
+    if (presort()) launch_cell_scan(geo(), S.ccount, S.ccur, S.hist, stream);
     launch_scan(geo(), S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items,
-                S.lay[cur].fill, S.pending, S.err, stream);
+                S.lay[cur].fill, S.pending, S.err, presort() ? 1 : 0, stream);
     tick_end(3);
     n += 1;
     stage = 0;
@@ -789,7 +793,7 @@ template <class R> struct SimT : envpic_sim {
         if ((rc = hip_check(hipMemcpyAsync(dst[c], h[c].data(), np * sizeof(R), hipMemcpyHostToDevice, stream), "parts"))) return rc;
       if ((rc = hip_check(hipMemcpyAsync(P.id, hid.data(), np * sizeof(uint32_t), hipMemcpyHostToDevice, stream), "id"))) return rc;
     }
-    if ((rc = rebuild_next_layout())) return rc;
+    sorted_at = n;  // the particles of P[cur] sit in their tiles
     return hip_check(hipStreamSynchronize(stream), "set_particles");
   }
 

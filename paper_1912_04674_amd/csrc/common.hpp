@@ -27,6 +27,14 @@ constexpr int HALO = SORT_EVERY + 1;  // LDS region margin around a tile (cells)
 constexpr int LX = TX + 2 * HALO + 1;
 constexpr int LR = TR + 2 * HALO + 1;
 constexpr int LN = LX * LR; // nodes of an LDS tile region
+// cells a tile's particles can occupy at a sort (its 16 x 16 cells plus
+// SORT_EVERY on each side): the per-cell counts of a work item live here
+constexpr int CR = TX + 2 * SORT_EVERY;
+constexpr int CRN = CR * CR;
+// how a sort moves the particles: by tile keeping their order, or by cell
+// with the placement of loading (every CELL_SORT_EVERY-th sort)
+constexpr int SCAT_NONE = 0, SCAT_TILE = 1, SCAT_CELL = 2;
+constexpr int CELL_SORT_EVERY = 8;
 constexpr int WG = 512;     // work-group size of the particle kernels
 constexpr int CHUNK = 4096; // largest work item (particles); small runs use smaller items
 // A particle's cell is one 32-bit word: lab column << 12 | radial row.  The

@@ -178,6 +178,17 @@ __device__ inline int transpose_rank(int r, int R) {
   return m * rows - max(0, m - L) + q;
 }
 
+// slot of the r-th particle (in cell order) of a tile of v particles: the
+// tile splits into ceil(v / chunk) equal work items (as the scan makes
+// them) and the particles of an item are placed as at loading
+__device__ inline int placed_rank(int r, int v, int chunk) {
+  const int nm = (v + chunk - 1) / chunk;
+  int k = (int)((long long)r * nm / v);
+  if (k + 1 < nm && (int)((long long)(k + 1) * v / nm) <= r) ++k;
+  const int lo = (int)((long long)k * v / nm), hi = (int)((long long)(k + 1) * v / nm);
+  return lo + transpose_rank(r - lo, hi - lo);
+}
+
 // the tile region of a work item: lab column X0 = T TX - HALO, row R0
 struct Region {
   int T, tcx, tcr;
@@ -206,16 +217,20 @@ template <class R, bool M1> struct SmemMom {
   C ex1[M1 ? LN : 1], er1[M1 ? LN : 1], et1[M1 ? LN : 1];
   C bx1[M1 ? LN : 1], br1[M1 ? LN : 1], bt1[M1 ? LN : 1];
   R ivol[LR];
-  int cnt[9], base[9];
+  int ccell[CRN];  // sort: particles per destination cell, then their first slot
 };
 constexpr int PPT = CHUNK / WG;  // particles per thread of a work item
 
-// SCATTER: move every particle into the next layout (tile order of x^n);
-// otherwise p is updated in place and the layout is kept.
-template <class R, bool M1, bool DEFER, bool SCATTER>
+// SCAT: SCAT_NONE updates p in place and keeps the layout; otherwise every
+// particle moves into the next layout (the tiles of x^n).  SCAT_TILE keeps
+// the particles' relative order (coalesced writes); SCAT_CELL orders each
+// tile by cell and places every work item as at loading, so that the lanes
+// of a wavefront hold particles of distinct cells again (the deposits'
+// LDS atomics do not collide), at the price of strided writes.
+template <class R, bool M1, bool DEFER, int SCAT>
 __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restrict__ chi_out,
                                                  Parts<R> src, Parts<R> dst, Layout Ls, Layout Ld,
-                                                 R* __restrict__ gscr, int* err) {
+                                                 int* __restrict__ ccur, R* __restrict__ gscr, int* err) {
   using C = typename cplx_of<R>::type;
   __shared__ SmemMom<R, M1> sm;
   const int item = blockIdx.x;
@@ -263,7 +278,8 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     const int j = q.R0 + k;
     sm.ivol[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (R)0;
   }
-  if (threadIdx.x < 9) sm.cnt[threadIdx.x] = 0;
+  if (SCAT != SCAT_NONE)
+    for (int k = threadIdx.x; k < (SCAT == SCAT_CELL ? CRN : 9); k += WG) sm.ccell[k] = 0;
   __syncthreads();
   // grad Phi by centred differences on the primal nodes (zero radial
   // derivative on the axis); the outermost ring of the region is unused
@@ -281,9 +297,9 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     }
   }
 
-  // ---- destination tile (3 x 3 neighbourhood) and rank of each particle,
-  // kept in registers (the loops over a thread's particles are unrolled).
-  // Without the scatter only the live flag is kept.
+  // ---- destination (tile of the 3 x 3 neighbourhood, or cell) and rank
+  // of each particle, kept in registers (the loops over a thread's
+  // particles are unrolled).  Without the scatter only the live flag is kept.
   int slot_rank[PPT];
   bool bad = false;
 #pragma unroll
@@ -293,11 +309,16 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     if (k < count) {
       const unsigned cw = src.cell[start + k];
       if (cw != kDead) {
-        if (SCATTER) {
+        if (SCAT == SCAT_TILE) {
           const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
           const int dtr = clampi(cell_jr(cw) / TR - q.tcr, -1, 1, bad);
           const int slot = (dtx + 1) * 3 + (dtr + 1);
-          slot_rank[u] = (slot << 24) | atomicAdd(&sm.cnt[slot], 1);
+          slot_rank[u] = (slot << 16) | atomicAdd(&sm.ccell[slot], 1);
+        } else if (SCAT == SCAT_CELL) {
+          const int sx = clampi(cell_ix(cw) - (q.T * TX - SORT_EVERY), 0, CR - 1, bad);
+          const int sr = clampi(cell_jr(cw) - (q.tcr * TR - SORT_EVERY), 0, CR - 1, bad);
+          const int slot = sx * CR + sr;
+          slot_rank[u] = (slot << 16) | atomicAdd(&sm.ccell[slot], 1);
         } else {
           slot_rank[u] = 0;
         }
@@ -305,32 +326,63 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     }
   }
   __syncthreads();
-  if (SCATTER && threadIdx.x < 9) {
-    const int c = sm.cnt[threadIdx.x];
-    if (c > 0) {
-      int tx2 = q.tcx + threadIdx.x / 3 - 1;
-      if (tx2 < 0) tx2 += g.ntxa;
-      if (tx2 >= g.ntxa) tx2 -= g.ntxa;
-      const int tr2 = q.tcr + threadIdx.x % 3 - 1;
-      sm.base[threadIdx.x] = atomicAdd(&Ld.cursor[tx2 * g.ntr + tr2], c);
+  // one reservation per destination tile, or per destination cell (its
+  // slots in cell order)
+  if (SCAT == SCAT_TILE) {
+    if (threadIdx.x < 9) {
+      const int c = sm.ccell[threadIdx.x];
+      if (c > 0) {
+        int tx2 = q.tcx + threadIdx.x / 3 - 1;
+        if (tx2 < 0) tx2 += g.ntxa;
+        if (tx2 >= g.ntxa) tx2 -= g.ntxa;
+        const int tr2 = q.tcr + threadIdx.x % 3 - 1;
+        sm.ccell[threadIdx.x] = atomicAdd(&Ld.cursor[tx2 * g.ntr + tr2], c);
+      }
     }
+    __syncthreads();
   }
-  if (SCATTER) __syncthreads();
+  if (SCAT == SCAT_CELL) {
+    for (int k = threadIdx.x; k < CRN; k += WG) {
+      const int c = sm.ccell[k];
+      if (c > 0) {
+        const int rel = (int)((long long)q.T * TX - SORT_EVERY + k / CR - g.shift);
+        const int j = q.tcr * TR - SORT_EVERY + k % CR;
+        sm.ccell[k] = atomicAdd(&ccur[(size_t)phys_col(g, rel) * g.pitch + j], c);
+      }
+    }
+    __syncthreads();
+  }
 
   // ---- gather, push, deposit, scatter
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (slot_rank[u] < 0) continue;
     const int p = start + threadIdx.x + u * WG;
+    const unsigned cw = src.cell[p];
     int d = p;
-    if (SCATTER) {
-      d = sm.base[slot_rank[u] >> 24] + (slot_rank[u] & 0xFFFFFF);
+    if (SCAT == SCAT_TILE) {
+      d = sm.ccell[slot_rank[u] >> 16] + (slot_rank[u] & 0xFFFF);
       if ((long long)d >= g.cap) {  // the scan has flagged the overflow
         bad = true;
         continue;
       }
     }
-    const unsigned cw = src.cell[p];
+    if (SCAT == SCAT_CELL) {
+      // rank in the destination tile's cell order, then the transposed
+      // placement inside its work item (as at loading)
+      const int r = sm.ccell[slot_rank[u] >> 16] + (slot_rank[u] & 0xFFFF);
+      const int key = tile_key(g, cell_ix(cw), cell_jr(cw));
+      const int off = Ld.offsets[key], v = Ld.offsets[key + 1] - off;
+      if (r >= v) {  // counts and particles disagree: flagged, never written
+        bad = true;
+        continue;
+      }
+      d = off + placed_rank(r, v, g.chunk);
+      if ((long long)d >= g.cap) {  // the scan has flagged the overflow
+        bad = true;
+        continue;
+      }
+    }
     const R fx = src.fx[p], fr = src.fr[p], th = src.th[p], w = src.w[p];
     R pv[3] = {src.px[p], src.py[p], src.pz[p]};
     const int a = clampi(cell_ix(cw) - q.X0, 1, LX - 3, bad);
@@ -389,7 +441,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
           lds_add(&sm.chi[(Px.i + aa) * LR + nb], (double)(wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivol[nb]));
         }
     }
-    if (SCATTER) {
+    if (SCAT != SCAT_NONE) {
       dst.cell[d] = cw;
       dst.fx[d] = fx;
       dst.fr[d] = fr;
@@ -425,7 +477,7 @@ template <class R, bool M1> struct SmemPos {
   double jx[LN], jr[LN];
   typename Acc1<R>::T jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
   R iax[LR], iar[LR], ivn[LR], ivh[LR];
-  int hist[9];
+  int ccell[CRN];  // before a sort: particles per cell of x^{n+1}
 };
 
 // one particle's move: old and new cells/offsets, transverse displacement
@@ -629,7 +681,7 @@ __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
       sm.jt1[k] = Acc1<R>::zero();
     }
   }
-  if (threadIdx.x < 9) sm.hist[threadIdx.x] = 0;
+  for (int k = threadIdx.x; k < CRN; k += WG) sm.ccell[k] = 0;
 }
 
 template <class R, bool M1>
@@ -663,29 +715,30 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
   }
 }
 
-__device__ inline void flush_hist(const int* h9, const Region& q, const Geo& g, int* hist) {
-  if (threadIdx.x < 9) {
-    const int c = h9[threadIdx.x];
+// the per-cell counts of a work item into the global per-cell counts
+__device__ inline void flush_cells(const int* cc, const Region& q, const Geo& g, int* ccount) {
+  for (int k = threadIdx.x; k < CRN; k += WG) {
+    const int c = cc[k];
     if (c > 0) {
-      int tx2 = q.tcx + threadIdx.x / 3 - 1;
-      if (tx2 < 0) tx2 += g.ntxa;
-      if (tx2 >= g.ntxa) tx2 -= g.ntxa;
-      const int tr2 = q.tcr + threadIdx.x % 3 - 1;
-      atomicAdd(&hist[tx2 * g.ntr + tr2], c);
+      const int rel = (int)((long long)q.T * TX - SORT_EVERY + k / CR - g.shift);
+      const int j = q.tcr * TR - SORT_EVERY + k % CR;
+      atomicAdd(&ccount[(size_t)phys_col(g, rel) * g.pitch + j], c);
     }
   }
 }
 
 // vacate: 1 when the window moves after this step (particles whose new
-// column is the window's first one are dropped after depositing)
+// column is the window's first one are dropped after depositing);
+// count_cells: 1 when the particles are re-sorted at the next step (their
+// new cells are counted into ccount)
 template <class R, bool M1, bool DEFER>
 __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restrict__ jx_out,
                                                  R* __restrict__ jr_out,
                                                  typename cplx_of<R>::type* __restrict__ jx1_out,
                                                  typename cplx_of<R>::type* __restrict__ jr1_out,
                                                  typename cplx_of<R>::type* __restrict__ jt1_out,
-                                                 Parts<R> P, Layout L, int* __restrict__ hist, int vacate,
-                                                 Parts<R> scr, int* err) {
+                                                 Parts<R> P, Layout L, int* __restrict__ ccount, int vacate,
+                                                 int count_cells, Parts<R> scr, int* err) {
   __shared__ SmemPos<R, M1> sm;
   const int item = blockIdx.x;
   if (item >= *L.n_items) return;
@@ -771,14 +824,16 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
       if (!DEFER) P.cell[p] = kDead;  // vacated column: dropped after depositing
       continue;
     }
-    const int dtx = clampi(mv.ix1 / TX - q.T, -1, 1, bad);
-    const int dtr = clampi(mv.jr1 / TR - q.tcr, -1, 1, bad);
-    atomicAdd(&sm.hist[(dtx + 1) * 3 + (dtr + 1)], 1);
+    if (count_cells) {
+      const int sx = clampi(mv.ix1 - (q.T * TX - SORT_EVERY), 0, CR - 1, bad);
+      const int sr = clampi(mv.jr1 - (q.tcr * TR - SORT_EVERY), 0, CR - 1, bad);
+      atomicAdd(&sm.ccell[sx * CR + sr], 1);
+    }
   }
   if (bad) atomicOr(err, ERR_HALO);
   __syncthreads();
   if (!DEFER) flush_current(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
-  flush_hist(sm.hist, q, g, hist);
+  if (count_cells) flush_cells(sm.ccell, q, g, ccount);
 }
 
 // ============================= deferred deposits (stage-by-stage API) ==
@@ -931,8 +986,8 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
 // is raised by the scan that follows (via *pending), after every block has
 // read it here.
 template <class R>
-__global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict__ hist, long long capacity,
-                         int max_items, int* __restrict__ pending, int* err) {
+__global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict__ ccount, int count_cells,
+                         long long capacity, int max_items, int* __restrict__ pending, int* err) {
   const long long col = g.shift + g.nx - 1;
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
   const int total = *L.fill;  // end of the used slots
@@ -941,22 +996,25 @@ __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict
     if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
     return;
   }
-  // live particles per tile row, counted in LDS first (a block spans at most
-  // blockDim / ppc + 1 rows, i.e. a few tile rows)
-  __shared__ int s_cnt[64];
+  // live particles per cell (one cell = ppc consecutive threads), counted in
+  // LDS first: a block spans blockDim / ppc + 1 rows at most
+  __shared__ int s_cnt[257];
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   const int j_first = (blockIdx.x * blockDim.x) / ppc;
-  for (int k = threadIdx.x; k < 64; k += blockDim.x) s_cnt[k] = 0;
+  for (int k = threadIdx.x; k < 257; k += blockDim.x) s_cnt[k] = 0;
   __syncthreads();
   if (idx < g.nr * ppc) {
     const int j = idx / ppc, k = idx - (idx / ppc) * ppc;
     const int t = j / TR, trt = min(TR, g.nr - t * TR);
     if (load_particle<R>(g, pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j, k))
-      atomicAdd(&s_cnt[min(63, t - j_first / TR)], 1);
+      atomicAdd(&s_cnt[j - j_first], 1);
   }
   __syncthreads();
-  if (threadIdx.x < 64 && s_cnt[threadIdx.x] > 0)
-    atomicAdd(&hist[tile_key(g, col, (j_first / TR + threadIdx.x) * TR)], s_cnt[threadIdx.x]);
+  if (count_cells) {
+    const int pc = phys_col(g, g.nx - 1);
+    for (int k = threadIdx.x; k < 257; k += blockDim.x)
+      if (s_cnt[k] > 0 && j_first + k < g.nr) atomicAdd(&ccount[(size_t)pc * g.pitch + j_first + k], s_cnt[k]);
+  }
   if (idx < g.ntr) {
     const int trt = min(TR, g.nr - idx * TR);
     L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), total + idx * TR * ppc, trt * ppc, 0);
@@ -968,73 +1026,56 @@ __global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict
 }
 
 // counts of live particles per tile of their current position
-template <class R>
-__global__ void k_hist(Geo g, Parts<R> P, Layout L, int* __restrict__ hist) {
-  // the particles of an item sit in its tile: count in LDS, one global add
-  __shared__ int cnt;
-  const int item = blockIdx.x;
-  if (item >= *L.n_items) return;
-  const int4 it = L.items[item];
-  if (threadIdx.x == 0) cnt = 0;
-  __syncthreads();
-  int mine = 0;
-  for (int k = threadIdx.x; k < it.z; k += blockDim.x) {
-    const unsigned cw = P.cell[it.y + k];
-    if (cw == kDead) continue;
-    const int key = tile_key(g, cell_ix(cw), cell_jr(cw));
-    if (key == it.x)
-      ++mine;
-    else
-      atomicAdd(&hist[key], 1);
-  }
-  if (mine) atomicAdd(&cnt, mine);
-  __syncthreads();
-  if (threadIdx.x == 0 && cnt) atomicAdd(&hist[it.x], cnt);
-}
 
 // ============================================================ launchers ==
 template <class R, bool M1, bool DEFER>
 static void launch_momentum_sc(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                               const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool scatter,
-                               hipStream_t st) {
-  if (scatter)
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, true>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+                               const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
+                               int scatter, hipStream_t st) {
+  if (scatter == SCAT_TILE)
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_TILE>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls,
+                       Ld, ccur, gscr, err);
+  else if (scatter == SCAT_CELL)
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_CELL>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls,
+                       Ld, ccur, gscr, err);
   else
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, false>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls, Ld, gscr, err);
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_NONE>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls,
+                       Ld, ccur, gscr, err);
 }
 
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                     const Layout& Ls, const Layout& Ld, R* gscr, int* err, int grid, bool defer, bool scatter,
-                     hipStream_t st) {
+                     const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
+                     int scatter, hipStream_t st) {
   if (grid <= 0) return;
   if (g.modes >= 2) {
     if (defer)
-      launch_momentum_sc<R, true, true>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, true, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
     else
-      launch_momentum_sc<R, true, false>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, true, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
   } else {
     if (defer)
-      launch_momentum_sc<R, false, true>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
     else
-      launch_momentum_sc<R, false, false>(g, f, chi, src, dst, Ls, Ld, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
   }
 }
 
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
-                     int* hist, int vacate, const Parts<R>& scr, int* err, int grid, bool defer, hipStream_t st) {
+                     int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
+                     hipStream_t st) {
   if (grid <= 0) return;
   if (g.modes >= 2) {
     if (defer)
-      hipLaunchKernelGGL((k_position<R, true, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+      hipLaunchKernelGGL((k_position<R, true, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
     else
-      hipLaunchKernelGGL((k_position<R, true, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+      hipLaunchKernelGGL((k_position<R, true, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
   } else {
     if (defer)
-      hipLaunchKernelGGL((k_position<R, false, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+      hipLaunchKernelGGL((k_position<R, false, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
     else
-      hipLaunchKernelGGL((k_position<R, false, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, hist, vacate, scr, err);
+      hipLaunchKernelGGL((k_position<R, false, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
   }
 }
 
@@ -1063,32 +1104,27 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
 }
 
 template <class R>
-void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* hist, long long capacity,
-                   int max_items, int* pending, int* err, hipStream_t st) {
+void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* ccount, int count_cells,
+                   long long capacity, int max_items, int* pending, int* err, hipStream_t st) {
   const int n = std::max(g.nr * g.ppc_x * g.ppc_r * g.ppc_t, g.ntr);
-  hipLaunchKernelGGL((k_inject<R>), dim3((n + 255) / 256), dim3(256), 0, st, g, pl, P, L, hist, capacity, max_items,
-                     pending, err);
+  hipLaunchKernelGGL((k_inject<R>), dim3((n + 255) / 256), dim3(256), 0, st, g, pl, P, L, ccount, count_cells, capacity,
+                     max_items, pending, err);
 }
 
-template <class R>
-void launch_hist(const Geo& g, const Parts<R>& P, const Layout& L, int* hist, int grid, hipStream_t st) {
-  if (grid <= 0) return;
-  hipLaunchKernelGGL((k_hist<R>), dim3(grid), dim3(256), 0, st, g, P, L, hist);
-}
 
 #define ENVPIC_INST(R)                                                                                          \
   template void launch_momentum<R>(const Geo&, const Grids<R>&, R*, const Parts<R>&, const Parts<R>&,           \
-                                   const Layout&, const Layout&, R*, int*, int, bool, bool, hipStream_t);       \
+                                   const Layout&, const Layout&, int*, R*, int*, int, bool, int, hipStream_t);  \
   template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
-                                   const Layout&, int*, int, const Parts<R>&, int*, int, bool, hipStream_t);    \
+                                   const Layout&, int*, int, int, const Parts<R>&, int*, int, bool,             \
+                                   hipStream_t);                                                                \
   template void launch_deposit_chi<R>(const Geo&, R*, const Parts<R>&, const Layout&, const R*, int*, int,      \
                                       hipStream_t);                                                             \
   template void launch_deposit_J<R>(const Geo&, const DepositBufs<R>&, const Parts<R>&, const Layout&, int,     \
                                     const Parts<R>&, int*, int, hipStream_t);                                   \
   template void launch_init_particles<R>(const Geo&, const Plasma&, const Parts<R>&, const int*, hipStream_t);  \
-  template void launch_inject<R>(const Geo&, const Plasma&, const Parts<R>&, const Layout&, int*, long long,    \
-                                 int, int*, int*, hipStream_t);                                                 \
-  template void launch_hist<R>(const Geo&, const Parts<R>&, const Layout&, int*, int, hipStream_t);
+  template void launch_inject<R>(const Geo&, const Plasma&, const Parts<R>&, const Layout&, int*, int,         \
+                                 long long, int, int*, int*, hipStream_t);
 ENVPIC_INST(float)
 ENVPIC_INST(double)
 #undef ENVPIC_INST

@@ -7,8 +7,42 @@
 
 namespace envpic {
 
+// ------------------------------------------------------------ cell scan --
+// One work group per tile: exclusive scan of its 16 x 16 cells' counts
+// (column-major, radius fastest) into the per-cell cursors the scatter
+// reserves from, the tile total into hist, and the counts cleared.
+__global__ __launch_bounds__(TX * TR) void k_cell_scan(Geo g, int* __restrict__ ccount, int* __restrict__ ccur,
+                                                       int* __restrict__ hist) {
+  __shared__ int s[TX * TR];
+  const int t = blockIdx.x;
+  const int tcx = t / g.ntr, tcr = t - (t / g.ntr) * g.ntr;
+  const int a = threadIdx.x / TR, b = threadIdx.x - (threadIdx.x / TR) * TR;
+  const long long col = (long long)lab_tile(g, tcx) * TX + a;
+  const int rel = (int)(col - g.shift), j = tcr * TR + b;
+  const bool valid = rel >= 0 && rel < g.nx && j < g.nr;
+  const size_t o = valid ? (size_t)phys_col(g, rel) * g.pitch + j : 0;
+  const int c = valid ? ccount[o] : 0;
+  s[threadIdx.x] = c;
+  __syncthreads();
+  for (int off = 1; off < TX * TR; off <<= 1) {
+    const int v = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
+    __syncthreads();
+    s[threadIdx.x] += v;
+    __syncthreads();
+  }
+  if (valid) {
+    ccur[o] = s[threadIdx.x] - c;
+    ccount[o] = 0;
+  }
+  if (threadIdx.x == TX * TR - 1) hist[t] = s[threadIdx.x];
+}
+
+void launch_cell_scan(const Geo& g, int* ccount, int* ccur, int* hist, hipStream_t st) {
+  hipLaunchKernelGGL(k_cell_scan, dim3(g.ntiles), dim3(TX * TR), 0, st, g, ccount, ccur, hist);
+}
+
 // ----------------------------------------------------------------- scan --
-// One work group of 1024 threads: exclusive scan of the tile counts into
+// One work group of 1024 threads: exclusive scan of the tile totals into
 // offsets (and the scatter cursors), work items (a tile of v particles gives
 // ceil(v / chunk) items of equal size), and a reset of the histogram for the
 // next step.  Flags when the particles plus one injected column would not
@@ -17,7 +51,7 @@ constexpr int SCAN_T = 1024;
 
 __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, Layout out, long long capacity,
                                                  int inj_max, int max_items, int* bump_items, int* bump_fill,
-                                                 int* pending, int* err) {
+                                                 int* pending, int* err, int sort) {
   __shared__ int s_c[SCAN_T], s_m[SCAN_T];
   const int nt = g.ntiles;
   const int tid = threadIdx.x;
@@ -27,6 +61,7 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
     pending[0] = 0;
     pending[1] = 0;
   }
+  if (!sort) return;
   const int per = (nt + SCAN_T - 1) / SCAN_T;
   const int t0 = min(nt, tid * per), t1 = min(nt, t0 + per);
   int c = 0, m = 0;
@@ -77,9 +112,9 @@ __global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, 
 }
 
 void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* bump_items, int* bump_fill, int* pending, int* err, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(SCAN_T), 0, st, g, hist, out, capacity, inj_max, max_items, bump_items,
-                     bump_fill, pending, err);
+                 int* bump_items, int* bump_fill, int* pending, int* err, int sort, hipStream_t st) {
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(sort ? SCAN_T : 64), 0, st, g, hist, out, capacity, inj_max, max_items,
+                     bump_items, bump_fill, pending, err, sort);
 }
 
 // ---------------------------------------------------------- diagnostics --
