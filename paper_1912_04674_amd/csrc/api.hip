@@ -542,7 +542,31 @@ template <class R> struct SimT : envpic_sim {
   int field() override {
     if (stage != 3 || !deposit_done) return fail(ENVPIC_EORDER, "field stage out of order");
     tick_begin();
-    launch_maxwell<R>(geo(), S.grids, S.dep[n & 1], S.dep[(n + 1) & 1], stream);
+    const Geo g = geo();
+    const bool shifting = shift_due(), pre = presort();
+    if (shifting) shift += 1;
+    const Geo gn = geo();
+    // the column entering the window is loaded first (it touches particles only)
+    if (shifting && p.profile != ENVPIC_PROFILE_NONE)
+      launch_inject<R>(gn, plasma(), S.parts[cur], S.lay[cur], S.ccount, pre ? 1 : 0, sz.capacity, sz.max_items,
+                       S.pending, S.err, stream);
+    FieldArgs fa{};
+    fa.gn = gn;
+    fa.shifting = shifting ? 1 : 0;
+    fa.fp64_rows = fp64_rows ? 1 : 0;
+    fa.presort = pre ? 1 : 0;
+    fa.ccount = S.ccount;
+    fa.ccur = S.ccur;
+    fa.hist = S.hist;
+    fa.out = S.lay[1 - cur];
+    fa.capacity = sz.capacity;
+    fa.inj_max = p.nr * sz.ppc;
+    fa.max_items = sz.max_items;
+    fa.bump_items = S.lay[cur].n_items;
+    fa.bump_fill = S.lay[cur].fill;
+    fa.pending = S.pending;
+    fa.err = S.err;
+    launch_field<R>(g, S.grids, S.dep[n & 1], S.dep[(n + 1) & 1], S.dep[0], S.dep[1], fa, stream);
     {
       Grids<R>& G = S.grids;  // the new E, B become the current ones
       std::swap(G.ex, G.ex_n);
@@ -555,23 +579,12 @@ template <class R> struct SimT : envpic_sim {
       std::swap(G.br1, G.br1_n);
       std::swap(G.bt1, G.bt1_n);
     }
-    if (shift_due()) {
-      shift += 1;
-      const Geo g = geo();
-      launch_window<R>(g, S.grids, S.dep[0], S.dep[1], fp64_rows ? 1 : 0, stream);
-      if (p.profile != ENVPIC_PROFILE_NONE)
-        launch_inject<R>(g, plasma(), S.parts[cur], S.lay[cur], S.ccount, presort() ? 1 : 0, sz.capacity,
-                         sz.max_items, S.pending, S.err, stream);
-    }
-    // before a sort: per-cell cursors and tile totals, then the new layout
-    if (presort()) launch_cell_scan(geo(), S.ccount, S.ccur, S.hist, stream);
-    launch_scan(geo(), S.hist, S.lay[1 - cur], sz.capacity, p.nr * sz.ppc, sz.max_items, S.lay[cur].n_items,
-                S.lay[cur].fill, S.pending, S.err, presort() ? 1 : 0, stream);
     tick_end(3);
     n += 1;
     stage = 0;
     return launched("field stage");
   }
+
 
   // ---------------------------------------------------------------- IO --
   struct FieldRef {

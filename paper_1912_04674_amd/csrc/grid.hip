@@ -10,6 +10,7 @@
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
+#include "scan.hpp"
 
 namespace envpic {
 
@@ -156,28 +157,38 @@ __device__ inline ENew<R, M1> ampere(const Geo& g, const Grids<R>& f, const Depo
   return e;
 }
 
-constexpr int MW_TI = 4, MW_TJ = 64;  // tile of a Maxwell work group: 4 columns x 64 rows
+constexpr int MW_TI = 8, MW_TJ = 64;  // tile of a Maxwell work group: 8 columns x 64 rows
+constexpr int MW_T = MW_TI * MW_TJ;   // threads of a field-stage work group
 
-template <class R, bool M1>
-__global__ __launch_bounds__(MW_TI * MW_TJ) void k_maxwell(Geo g, Grids<R> f, DepositBufs<R> din,
-                                                            DepositBufs<R> dnext) {
+template <class R, bool M1> struct MwShared {
   using C = typename cplx_of<R>::type;
-  constexpr int HI = MW_TI + 1, HJ = MW_TJ + 1, HN = HI * HJ;
-  __shared__ R s_ex[HN], s_er[HN];
-  __shared__ C s_ex1[M1 ? HN : 1], s_er1[M1 ? HN : 1], s_et1[M1 ? HN : 1];
-  const int i0 = blockIdx.y * MW_TI, j0 = blockIdx.x * MW_TJ;
-  // ---- E^{n+1} on the tile and its +1 column / +1 row
-  for (int k = threadIdx.x; k < HN; k += MW_TI * MW_TJ) {
+  static constexpr int HI = MW_TI + 1, HJ = MW_TJ + 1, HN = HI * HJ;
+  R ex[HN], er[HN];
+  C ex1[M1 ? HN : 1], er1[M1 ? HN : 1], et1[M1 ? HN : 1];
+};
+
+// The Maxwell tile (i0, j0): E^{n+1} on the tile and its +1 column / +1 row
+// into LDS, then the owned nodes' E^{n+1}, B^{n+3/2}, Bbar^{n+1} and the
+// cleared next deposits.  left_edge_zero: the window moves after this step
+// and column 1 becomes its left edge, where E_r (both modes) and E_t of
+// mode 1 are set to zero (B still sees the computed values).
+template <class R, bool M1>
+__device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din,
+                                    const DepositBufs<R>& dnext, int i0, int j0, bool left_edge_zero,
+                                    MwShared<R, M1>& sm) {
+  using C = typename cplx_of<R>::type;
+  constexpr int HJ = MwShared<R, M1>::HJ, HN = MwShared<R, M1>::HN;
+  for (int k = threadIdx.x; k < HN; k += MW_T) {
     const int a = k / HJ, b = k - (k / HJ) * HJ;
     const int i = i0 + a, j = j0 + b;
     if (i > g.nx || j > g.nr) continue;
     const ENew<R, M1> e = ampere<R, M1>(g, f, din, i, j);
-    s_ex[k] = e.ex;
-    s_er[k] = e.er;
+    sm.ex[k] = e.ex;
+    sm.er[k] = e.er;
     if (M1) {
-      s_ex1[k] = e.ex1;
-      s_er1[k] = e.er1;
-      s_et1[k] = e.et1;
+      sm.ex1[k] = e.ex1;
+      sm.er1[k] = e.er1;
+      sm.et1[k] = e.et1;
     }
   }
   __syncthreads();
@@ -187,18 +198,20 @@ __global__ __launch_bounds__(MW_TI * MW_TJ) void k_maxwell(Geo g, Grids<R> f, De
   const int k = a * HJ + b, kp = k + HJ;  // (i, j), (i+1, j)
   const size_t o = (size_t)phys_col(g, i) * g.pitch + j;
   const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  const bool ez = left_edge_zero && i == 1;
   // the new E of the owned node
-  if (j <= g.nr - 1) f.er_n[o] = s_er[k];
-  if (i <= g.nx - 1) f.ex_n[o] = s_ex[k];
+  if (j <= g.nr - 1) f.er_n[o] = ez ? (R)0 : sm.er[k];
+  if (i <= g.nx - 1) f.ex_n[o] = sm.ex[k];
   if (M1) {
-    if (i <= g.nx - 1) f.ex1_n[o] = s_ex1[k];
-    if (j <= g.nr - 1) f.er1_n[o] = s_er1[k];
-    f.et1_n[o] = s_et1[k];
+    const C z = mk<C>((R)0, (R)0);
+    if (i <= g.nx - 1) f.ex1_n[o] = sm.ex1[k];
+    if (j <= g.nr - 1) f.er1_n[o] = ez ? z : sm.er1[k];
+    f.et1_n[o] = ez ? z : sm.et1[k];
   }
   // ---- B^{n+3/2} and Bbar^{n+1}
   if (i <= g.nx - 1 && j <= g.nr - 1) {
     const R b0 = f.bt[o];
-    const R b1 = b0 + dt * ((s_ex[k + 1] - s_ex[k]) * idr - (s_er[kp] - s_er[k]) * idx_);
+    const R b1 = b0 + dt * ((sm.ex[k + 1] - sm.ex[k]) * idr - (sm.er[kp] - sm.er[k]) * idx_);
     f.bt_n[o] = b1;
     f.btb[o] = (R)0.5 * (b0 + b1);
   }
@@ -206,22 +219,22 @@ __global__ __launch_bounds__(MW_TI * MW_TJ) void k_maxwell(Geo g, Grids<R> f, De
     if (j <= g.nr - 1) {
       const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
       const C b0 = f.bx1[o];
-      const C curl = cadd(cscale(csub(cscale(s_et1[k + 1], (R)(j + 1)), cscale(s_et1[k], (R)j)), irh),
-                          cscale(cmuli(s_er1[k]), irh));
+      const C curl = cadd(cscale(csub(cscale(sm.et1[k + 1], (R)(j + 1)), cscale(sm.et1[k], (R)j)), irh),
+                          cscale(cmuli(sm.er1[k]), irh));
       const C b1 = csub(b0, cscale(curl, dt));
       f.bx1_n[o] = b1;
       f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
     }
     if (i <= g.nx - 1) {
-      const C exr = j == 0 ? cscale(s_ex1[k + 1], idr) : cscale(s_ex1[k], (R)(1.0 / (j * g.dr)));
+      const C exr = j == 0 ? cscale(sm.ex1[k + 1], idr) : cscale(sm.ex1[k], (R)(1.0 / (j * g.dr)));
       const C b0 = f.br1[o];
-      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(s_et1[kp], s_et1[k]), idx_)), dt));
+      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(sm.et1[kp], sm.et1[k]), idx_)), dt));
       f.br1_n[o] = b1;
       f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
       if (j <= g.nr - 1) {
         const C c0 = f.bt1[o];
-        const C c1 = cadd(c0, cscale(csub(cscale(csub(s_ex1[k + 1], s_ex1[k]), idr),
-                                          cscale(csub(s_er1[kp], s_er1[k]), idx_)), dt));
+        const C c1 = cadd(c0, cscale(csub(cscale(csub(sm.ex1[k + 1], sm.ex1[k]), idr),
+                                          cscale(csub(sm.er1[kp], sm.er1[k]), idx_)), dt));
         f.bt1_n[o] = c1;
         f.btb1[o] = cscale(cadd(c0, c1), (R)0.5);
       }
@@ -239,13 +252,16 @@ __global__ __launch_bounds__(MW_TI * MW_TJ) void k_maxwell(Geo g, Grids<R> f, De
 }
 
 // ----------------------------------------------------- window shift --
-// After the shift (g holds the new shift): the primal column entering at the
-// right (rel = nx) and the half-shifted column entering (rel = nx - 1) start
-// at zero, and the new left edge (rel = 0) takes its boundary values.
+// After the shift (g holds the new shift), row j: the primal column entering
+// at the right (rel = nx) and the half-shifted column entering (rel = nx - 1)
+// start at zero, and the new left edge (rel = 0) takes its boundary values
+// (zero envelope; E_r and mode-1 E_t there are zeroed by the Maxwell tile).
+// Runs in the field-stage kernel before the host swaps the E/B copies, so
+// E and B are written in their new (_n) copies.
 template <class R, bool M1>
-__global__ void k_window(Geo g, Grids<R> f, DepositBufs<R> d0, DepositBufs<R> d1, int fp64_rows) {
+__device__ inline void window_row(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d0,
+                                  const DepositBufs<R>& d1, int fp64_rows, int j) {
   using C = typename cplx_of<R>::type;
-  const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j > g.nr) return;
   const C z = mk<C>((R)0, (R)0);
   const int pn = phys_col(g, g.nx), pd = phys_col(g, g.nx - 1), pl = phys_col(g, 0);
@@ -253,18 +269,17 @@ __global__ void k_window(Geo g, Grids<R> f, DepositBufs<R> d0, DepositBufs<R> d1
   // primal-x grids at the entering column
   f.env[on] = z;
   f.envp[on] = z;
-  f.er[on] = 0;
+  f.er_n[on] = 0;
   d0.chi[on] = 0; d1.chi[on] = 0;
   d0.jr[on] = 0; d1.jr[on] = 0;
   // half-shifted-x grids at the entering column
-  f.ex[od] = 0;
-  f.bt[od] = 0;
+  f.ex_n[od] = 0;
+  f.bt_n[od] = 0;
   f.btb[od] = 0;
   d0.jx[od] = 0; d1.jx[od] = 0;
   // boundary values at the new left edge
   f.env[ol] = z;
   f.envp[ol] = z;
-  f.er[ol] = 0;
   if (fp64_rows && j <= 1) {
     f.ax[pn * 2 + j] = make_double2(0.0, 0.0);
     f.axp[pn * 2 + j] = make_double2(0.0, 0.0);
@@ -272,12 +287,42 @@ __global__ void k_window(Geo g, Grids<R> f, DepositBufs<R> d0, DepositBufs<R> d1
     f.axp[pl * 2 + j] = make_double2(0.0, 0.0);
   }
   if (M1) {
-    f.er1[on] = z; f.et1[on] = z; f.bx1[on] = z; f.bxb1[on] = z;
+    f.er1_n[on] = z; f.et1_n[on] = z; f.bx1_n[on] = z; f.bxb1[on] = z;
     d0.jr1[on] = z; d1.jr1[on] = z; d0.jt1[on] = z; d1.jt1[on] = z;
-    f.ex1[od] = z; f.br1[od] = z; f.bt1[od] = z; f.brb1[od] = z; f.btb1[od] = z;
+    f.ex1_n[od] = z; f.br1_n[od] = z; f.bt1_n[od] = z; f.brb1[od] = z; f.btb1[od] = z;
     d0.jx1[od] = z; d1.jx1[od] = z;
-    f.er1[ol] = z; f.et1[ol] = z;
   }
+}
+
+// --------------------------------------------------------- field stage --
+// One kernel for the field stage, its work groups in three roles: Maxwell
+// tiles (geometry before the shift); if the window moves, the rows of its
+// column resets (geometry after it); before a sort, the per-tile cell scans
+// (two tiles per group).  No role reads another's output.
+template <class R, bool M1>
+__global__ __launch_bounds__(MW_T) void k_field(Geo g, Grids<R> f, DepositBufs<R> din, DepositBufs<R> dnext,
+                                               DepositBufs<R> d0, DepositBufs<R> d1, FieldArgs fa) {
+  __shared__ MwShared<R, M1> sm;
+  __shared__ int s_a[MW_T];
+  const int blk = blockIdx.x;
+  if (blk < fa.nb_mw) {
+    maxwell_tile<R, M1>(g, f, din, dnext, (blk / fa.nbx_mw) * MW_TI, (blk % fa.nbx_mw) * MW_TJ, fa.shifting != 0, sm);
+  } else if (blk < fa.nb_mw + fa.nb_win) {
+    window_row<R, M1>(fa.gn, f, d0, d1, fa.fp64_rows, (blk - fa.nb_mw) * MW_T + threadIdx.x);
+  } else {
+    const int t = 2 * (blk - fa.nb_mw - fa.nb_win) + threadIdx.x / (TX * TR);
+    const int lt = threadIdx.x % (TX * TR);
+    cell_scan_tile(fa.gn, t, lt, fa.ccount, fa.ccur, fa.hist, s_a + (threadIdx.x / (TX * TR)) * (TX * TR));
+  }
+}
+
+// the layout scan over all tile totals (or only the injected column's items
+// added to the layout in use), one work group
+constexpr int SCAN_T = 1024;
+__global__ __launch_bounds__(SCAN_T) void k_layout_scan(FieldArgs fa) {
+  __shared__ int s_a[SCAN_T], s_b[SCAN_T];
+  layout_scan<SCAN_T>(fa.gn, fa.hist, fa.out, fa.capacity, fa.inj_max, fa.max_items, fa.bump_items, fa.bump_fill,
+                      fa.pending, fa.err, fa.presort, s_a, s_b);
 }
 
 // ---------------------------------------------------- initial envelope --
@@ -333,23 +378,18 @@ void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_row
 }
 
 template <class R>
-void launch_maxwell(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
-                    hipStream_t st) {
-  const dim3 grid((g.nr + 1 + MW_TJ - 1) / MW_TJ, (g.nx + 1 + MW_TI - 1) / MW_TI);
+void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
+                  const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st) {
+  fa.nbx_mw = (g.nr + 1 + MW_TJ - 1) / MW_TJ;
+  fa.nb_mw = fa.nbx_mw * ((g.nx + 1 + MW_TI - 1) / MW_TI);
+  fa.nb_win = fa.shifting ? (g.nr + 1 + MW_T - 1) / MW_T : 0;
+  const int nb_cs = fa.presort ? (g.ntiles + 1) / 2 : 0;
+  const int grid = fa.nb_mw + fa.nb_win + nb_cs;
   if (g.modes >= 2)
-    hipLaunchKernelGGL((k_maxwell<R, true>), grid, dim3(MW_TI * MW_TJ), 0, st, g, f, din, dnext);
+    hipLaunchKernelGGL((k_field<R, true>), dim3(grid), dim3(MW_T), 0, st, g, f, din, dnext, d0, d1, fa);
   else
-    hipLaunchKernelGGL((k_maxwell<R, false>), grid, dim3(MW_TI * MW_TJ), 0, st, g, f, din, dnext);
-}
-
-template <class R>
-void launch_window(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d0, const DepositBufs<R>& d1,
-                   int fp64_rows, hipStream_t st) {
-  const int blocks = (g.nr + 1 + 255) / 256;
-  if (g.modes >= 2)
-    hipLaunchKernelGGL((k_window<R, true>), dim3(blocks), dim3(256), 0, st, g, f, d0, d1, fp64_rows);
-  else
-    hipLaunchKernelGGL((k_window<R, false>), dim3(blocks), dim3(256), 0, st, g, f, d0, d1, fp64_rows);
+    hipLaunchKernelGGL((k_field<R, false>), dim3(grid), dim3(MW_T), 0, st, g, f, din, dnext, d0, d1, fa);
+  hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(fa.presort ? SCAN_T : 64), 0, st, fa);
 }
 
 template <class R>
@@ -359,10 +399,8 @@ void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int f
 
 #define ENVPIC_INST(R)                                                                                      \
   template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, hipStream_t);                \
-  template void launch_maxwell<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&, \
-                                  hipStream_t);                                                             \
-  template void launch_window<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&, \
-                                 int, hipStream_t);                                                         \
+  template void launch_field<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&,   \
+                                const DepositBufs<R>&, const DepositBufs<R>&, FieldArgs, hipStream_t);      \
   template void launch_init_envelope<R>(const Geo&, const Grids<R>&, const Laser&, int, hipStream_t);
 ENVPIC_INST(float)
 ENVPIC_INST(double)

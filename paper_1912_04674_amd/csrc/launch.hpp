@@ -38,23 +38,31 @@ void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layo
 
 template <class R>
 void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st);
+// arguments of the field-stage kernel besides the grids and deposits
+struct FieldArgs {
+  Geo gn;                      // geometry after the window shift (as before it when there is none)
+  int shifting, fp64_rows, presort;
+  int nb_mw, nbx_mw, nb_win;   // work-group roles (set by the launcher)
+  int* ccount;                 // per-cell counts -> cursors (ccur), tile totals (hist)
+  int* ccur;
+  int* hist;
+  Layout out;                  // the next layout
+  long long capacity;
+  int inj_max, max_items;
+  int* bump_items;             // the layout in use: items and fill raised by an injection
+  int* bump_fill;
+  int* pending;
+  int* err;
+};
+// E^{n+1}, B^{n+3/2}, Bbar^{n+1} into the second E/B copies (the caller
+// swaps them), the next deposits cleared, the window's column resets (if
+// shifting), the per-cell and layout scans (before a sort) or the injected
+// column's items added to the layout in use
 template <class R>
-void launch_maxwell(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
-                    hipStream_t st);
-template <class R>
-void launch_window(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d0, const DepositBufs<R>& d1,
-                   int fp64_rows, hipStream_t st);
+void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
+                  const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st);
 template <class R>
 void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st);
-
-// per tile: exclusive scan of its cells' counts into the per-cell cursors
-// (cell order within the tile), the tile total into hist, counts cleared
-void launch_cell_scan(const Geo& g, int* ccount, int* ccur, int* hist, hipStream_t st);
-// the items (pending[0]) and slots (pending[1]) appended by an injection
-// are first added to *bump_items and *bump_fill of the layout in use; with
-// sort = 0 that is all it does
-void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* bump_items, int* bump_fill, int* pending, int* err, int sort, hipStream_t st);
 
 int diag_scratch_doubles(int max_items, const Geo& g);
 template <class R>

@@ -1,121 +1,11 @@
-// sort_diag.hip -- the counting-sort scan of the per-tile histogram into the
-// next particle layout and its work items, and the FP64 conserved-sum
-// diagnostics (wavefront/work-group tree reductions, summed in a fixed order).
+// sort_diag.hip -- the FP64 conserved-sum diagnostics (work-group tree
+// reductions, summed in a fixed order).  The counting sort's scans are in
+// scan.hpp (run inside the field-stage kernel).
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
 
 namespace envpic {
-
-// ------------------------------------------------------------ cell scan --
-// One work group per tile: exclusive scan of its 16 x 16 cells' counts
-// (column-major, radius fastest) into the per-cell cursors the scatter
-// reserves from, the tile total into hist, and the counts cleared.
-__global__ __launch_bounds__(TX * TR) void k_cell_scan(Geo g, int* __restrict__ ccount, int* __restrict__ ccur,
-                                                       int* __restrict__ hist) {
-  __shared__ int s[TX * TR];
-  const int t = blockIdx.x;
-  const int tcx = t / g.ntr, tcr = t - (t / g.ntr) * g.ntr;
-  const int a = threadIdx.x / TR, b = threadIdx.x - (threadIdx.x / TR) * TR;
-  const long long col = (long long)lab_tile(g, tcx) * TX + a;
-  const int rel = (int)(col - g.shift), j = tcr * TR + b;
-  const bool valid = rel >= 0 && rel < g.nx && j < g.nr;
-  const size_t o = valid ? (size_t)phys_col(g, rel) * g.pitch + j : 0;
-  const int c = valid ? ccount[o] : 0;
-  s[threadIdx.x] = c;
-  __syncthreads();
-  for (int off = 1; off < TX * TR; off <<= 1) {
-    const int v = (int)threadIdx.x >= off ? s[threadIdx.x - off] : 0;
-    __syncthreads();
-    s[threadIdx.x] += v;
-    __syncthreads();
-  }
-  if (valid) {
-    ccur[o] = s[threadIdx.x] - c;
-    ccount[o] = 0;
-  }
-  if (threadIdx.x == TX * TR - 1) hist[t] = s[threadIdx.x];
-}
-
-void launch_cell_scan(const Geo& g, int* ccount, int* ccur, int* hist, hipStream_t st) {
-  hipLaunchKernelGGL(k_cell_scan, dim3(g.ntiles), dim3(TX * TR), 0, st, g, ccount, ccur, hist);
-}
-
-// ----------------------------------------------------------------- scan --
-// One work group of 1024 threads: exclusive scan of the tile totals into
-// offsets (and the scatter cursors), work items (a tile of v particles gives
-// ceil(v / chunk) items of equal size), and a reset of the histogram for the
-// next step.  Flags when the particles plus one injected column would not
-// fit.
-constexpr int SCAN_T = 1024;
-
-__global__ __launch_bounds__(SCAN_T) void k_scan(Geo g, int* __restrict__ hist, Layout out, long long capacity,
-                                                 int inj_max, int max_items, int* bump_items, int* bump_fill,
-                                                 int* pending, int* err, int sort) {
-  __shared__ int s_c[SCAN_T], s_m[SCAN_T];
-  const int nt = g.ntiles;
-  const int tid = threadIdx.x;
-  if (tid == 0 && pending != nullptr && pending[0] != 0) {
-    *bump_items += pending[0];  // items and slots of the column injected before this scan
-    *bump_fill += pending[1];
-    pending[0] = 0;
-    pending[1] = 0;
-  }
-  if (!sort) return;
-  const int per = (nt + SCAN_T - 1) / SCAN_T;
-  const int t0 = min(nt, tid * per), t1 = min(nt, t0 + per);
-  int c = 0, m = 0;
-  for (int t = t0; t < t1; ++t) {
-    const int v = hist[t];
-    c += v;
-    m += (v + g.chunk - 1) / g.chunk;
-  }
-  s_c[tid] = c;
-  s_m[tid] = m;
-  __syncthreads();
-  for (int off = 1; off < SCAN_T; off <<= 1) {
-    const int vc = tid >= off ? s_c[tid - off] : 0;
-    const int vm = tid >= off ? s_m[tid - off] : 0;
-    __syncthreads();
-    s_c[tid] += vc;
-    s_m[tid] += vm;
-    __syncthreads();
-  }
-  int ec = s_c[tid] - c, em = s_m[tid] - m;
-  const int total = s_c[SCAN_T - 1], n_items = s_m[SCAN_T - 1];
-  // room kept for the columns injected before the next sort (one per step)
-  const int item_cap = max_items - SORT_EVERY * g.ntr;
-  for (int t = t0; t < t1; ++t) {
-    const int v = hist[t];
-    out.offsets[t] = ec;
-    out.cursor[t] = ec;
-    const int nm = (v + g.chunk - 1) / g.chunk;
-    for (int k = 0; k < nm; ++k) {
-      // the nm items of a tile share its particles evenly
-      const int lo = (int)((long long)k * v / nm), hi = (int)((long long)(k + 1) * v / nm);
-      const int st = ec + lo, cn = hi - lo;
-      // items never reach past the buffer (an overflow is flagged below)
-      out.items[em + k] = (em + k < item_cap && (long long)st + cn <= capacity) ? make_int4(t, st, cn, 0)
-                                                                                : make_int4(t, 0, 0, 0);
-    }
-    ec += v;
-    em += nm;
-    hist[t] = 0;
-  }
-  if (tid == SCAN_T - 1) {
-    out.offsets[nt] = total;
-    *out.fill = total;
-    *out.n_items = min(n_items, item_cap);
-    if (n_items > item_cap) atomicOr(err, ERR_ITEMS);
-    if ((long long)total + (long long)SORT_EVERY * inj_max > capacity) atomicOr(err, ERR_CAPACITY);
-  }
-}
-
-void launch_scan(const Geo& g, int* hist, const Layout& out, long long capacity, int inj_max, int max_items,
-                 int* bump_items, int* bump_fill, int* pending, int* err, int sort, hipStream_t st) {
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(sort ? SCAN_T : 64), 0, st, g, hist, out, capacity, inj_max, max_items,
-                     bump_items, bump_fill, pending, err, sort);
-}
 
 // ---------------------------------------------------------- diagnostics --
 constexpr int DG = 256;
