@@ -373,6 +373,10 @@ template <class R> struct SimT : envpic_sim {
     const double fix = cmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 49) / cmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
     g.fix = (float)fix;
     g.unfix = 1.0 / (double)g.fix;
+    // the chi and mode-0 current sums: 2^49 over the largest |w S| = w_max
+    const double fix0 = wmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 49) / wmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
+    g.fix0 = (float)fix0;
+    g.unfix0 = 1.0 / (double)g.fix0;
     return g;
   }
   Plasma plasma() const {

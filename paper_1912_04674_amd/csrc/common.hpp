@@ -73,6 +73,8 @@ struct Geo {
   double dx, dr, dt;
   float fix;         // fixed-point scale of the FP32 path's mode-1 current sums
   double unfix;      // 1 / fix
+  float fix0;        // fixed-point scale of the FP32 path's chi and mode-0 current sums
+  double unfix0;     // 1 / fix0
   int chunk;         // particles per work item at most (<= CHUNK, a multiple of WG)
 };
 

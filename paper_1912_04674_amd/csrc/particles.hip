@@ -99,6 +99,28 @@ template <> struct Acc1<float> {
   __device__ static float im(const T& v, const Geo& g) { return (float)((double)v.y * g.unfix); }
 };
 
+// Mode-0 deposit accumulators (chi, and J_x, J_r of the Esirkepov scheme).
+// A contribution is w S: the weight times shape factors (or, for the
+// currents, a partial sum of shape differences in [-1, 1]) without the
+// inverse node volume or face area, which depend on the row only and are
+// applied once per node at the flush.  The FP64 path sums FP64 words; the
+// FP32 path sums 64-bit fixed point scaled by g.fix0 = 2^49 / w_max, so a
+// contribution is at most 2^49 and the <= CHUNK contributions of a work item
+// to one node stay below 2^63 (exact, order-independent sums).
+template <class R> struct Acc0;
+template <> struct Acc0<double> {
+  using T = double;
+  __device__ static double scale(const Geo&) { return 1.0; }
+  __device__ static void add(T* a, double v) { atomicAdd(a, v); }
+  __device__ static double val(T v, const Geo&) { return v; }
+};
+template <> struct Acc0<float> {
+  using T = long long;
+  __device__ static float scale(const Geo& g) { return g.fix0; }
+  __device__ static void add(T* a, float v) { atomicAdd((unsigned long long*)a, (unsigned long long)to_fixed(v)); }
+  __device__ static double val(T v, const Geo& g) { return (double)v * g.unfix0; }
+};
+
 // Elementary functions.  The FP32 path uses the hardware reciprocal, square
 // root, reciprocal square root and sine/cosine (about 1 ulp, or ~1e-6 for
 // the direction cosines of the azimuth, far inside the FP32 path's
@@ -207,13 +229,13 @@ __device__ inline Region region_of(const Geo& g, int key) {
 }
 
 // ================================================== momentum pass ==
-// Deposits accumulate in FP64 LDS words for both precisions: ds_add_f64 runs
-// at a much higher rate than ds_add_f32 on gfx950 (measured), and the
+// The chi deposit accumulates in 64-bit LDS words (Acc0): 64-bit atomics
+// run at a much higher rate than ds_add_f32 on gfx950 (measured), and the
 // accumulated sums are rounded once, at the flush.
 template <class R, bool M1> struct SmemMom {
   using C = typename cplx_of<R>::type;
   R ex[LN], er[LN], bt[LN], phi[LN], gx[LN], gr[LN];
-  double chi[LN];
+  typename Acc0<R>::T chi[LN];
   C ex1[M1 ? LN : 1], er1[M1 ? LN : 1], et1[M1 ? LN : 1];
   C bx1[M1 ? LN : 1], br1[M1 ? LN : 1], bt1[M1 ? LN : 1];
   R ivol[LR];
@@ -261,7 +283,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     sm.er[k] = px ? hs * ver : (R)0;
     sm.bt[k] = dxok ? hs * vbt : (R)0;
     sm.phi[k] = (px && pr) ? (R)0.5 * cnorm(venv) : (R)0;
-    sm.chi[k] = 0.0;
+    sm.chi[k] = 0;
     if (M1) {
       const C z = mk<C>((R)0, (R)0);
       const C e1 = f.ex1[in], r1 = f.er1[ih], t1 = f.et1[in];
@@ -432,14 +454,13 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     if (DEFER) {
       gscr[d] = (R)1 / igb;
     } else {
-      const R wg = w * igb;
+      const R wg = w * igb * Acc0<R>::scale(g);
 #pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
+      for (int aa = 0; aa < 2; ++aa) {
+        const R wa = wg * (aa ? Px.b : Px.a);
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb) {
-          const int nb = Pr.i + bb;
-          lds_add(&sm.chi[(Px.i + aa) * LR + nb], (double)(wg * (aa ? Px.b : Px.a) * (bb ? Pr.b : Pr.a) * sm.ivol[nb]));
-        }
+        for (int bb = 0; bb < 2; ++bb) Acc0<R>::add(&sm.chi[(Px.i + aa) * LR + Pr.i + bb], wa * (bb ? Pr.b : Pr.a));
+      }
     }
     if (SCAT != SCAT_NONE) {
       dst.cell[d] = cw;
@@ -461,12 +482,11 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   if (DEFER) return;
   __syncthreads();
   for (int k = threadIdx.x; k < LN; k += WG) {
-    const R v = (R)sm.chi[k];
-    if (v == (R)0) continue;
+    if (sm.chi[k] == 0) continue;
     const int a = k / LR, b = k - (k / LR) * LR;
     const int rel = q.relX0 + a, j = q.R0 + b;
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
-    atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], v);
+    atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], (R)(Acc0<R>::val(sm.chi[k], g) * sm.ivol[b]));
   }
 }
 
@@ -474,7 +494,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
 template <class R, bool M1> struct SmemPos {
   using C = typename cplx_of<R>::type;
   R phh[LN];
-  double jx[LN], jr[LN];
+  typename Acc0<R>::T jx[LN], jr[LN];
   typename Acc1<R>::T jx1[M1 ? LN : 1], jr1[M1 ? LN : 1], jt1[M1 ? LN : 1];
   R iax[LR], iar[LR], ivn[LR], ivh[LR];
   int ccell[CRN];  // before a sort: particles per cell of x^{n+1}
@@ -564,20 +584,23 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
   // J_x (i+1/2, j): flux accumulated along x; the third partial sum is zero
   const R cx0 = S1x[0] - S0x[0], cx1 = cx0 + S1x[1] - S0x[1];
   const R cr0 = S1r[0] - S0r[0], cr1 = cr0 + S1r[1] - S0r[1];
-  double* jx = &sm.jx[amin * LR + bmin];
-  double* jr = &sm.jr[amin * LR + bmin];
+  // (the face areas are applied at the flush)
+  using A0 = Acc0<R>;
+  typename A0::T* jx = &sm.jx[amin * LR + bmin];
+  typename A0::T* jr = &sm.jr[amin * LR + bmin];
+  const R hw = (R)0.5 * w * A0::scale(g);
 #pragma unroll
   for (int bb = 0; bb < 3; ++bb) {
-    const R sr = (S0r[bb] + S1r[bb]) * (R)0.5 * w * sm.iax[bmin + bb];
-    if (cx0 != (R)0) lds_add(&jx[bb], (double)(cx0 * sr));
-    if (cx1 != (R)0) lds_add(&jx[LR + bb], (double)(cx1 * sr));
+    const R sr = (S0r[bb] + S1r[bb]) * hw;
+    if (cx0 != (R)0) A0::add(&jx[bb], cx0 * sr);
+    if (cx1 != (R)0) A0::add(&jx[LR + bb], cx1 * sr);
   }
   // J_r (i, j+1/2): flux accumulated along r
 #pragma unroll
   for (int aa = 0; aa < 3; ++aa) {
-    const R sx = (S0x[aa] + S1x[aa]) * (R)0.5 * w;
-    if (cr0 != (R)0) lds_add(&jr[aa * LR], (double)(cr0 * sx * sm.iar[bmin]));
-    if (cr1 != (R)0) lds_add(&jr[aa * LR + 1], (double)(cr1 * sx * sm.iar[bmin + 1]));
+    const R sx = (S0x[aa] + S1x[aa]) * hw;
+    if (cr0 != (R)0) A0::add(&jr[aa * LR], cr0 * sx);
+    if (cr1 != (R)0) A0::add(&jr[aa * LR + 1], cr1 * sx);
   }
   if (M1) {
     // Cartesian mid-point of the old and new positions: in the frame of the
@@ -673,8 +696,8 @@ __device__ inline void stage_pos_constants(SmemPos<R, M1>& sm, const Region& q, 
 template <class R, bool M1>
 __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
   for (int k = threadIdx.x; k < LN; k += WG) {
-    sm.jx[k] = 0.0;
-    sm.jr[k] = 0.0;
+    sm.jx[k] = 0;
+    sm.jr[k] = 0;
     if (M1) {
       sm.jx1[k] = Acc1<R>::zero();
       sm.jr1[k] = Acc1<R>::zero();
@@ -695,8 +718,8 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
     const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
     const bool dxok = rel <= g.nx - 1, drok = j <= g.nr - 1;
-    if (dxok && sm.jx[k] != 0.0) atomicAdd(&jx_out[o], (R)sm.jx[k]);
-    if (drok && sm.jr[k] != 0.0) atomicAdd(&jr_out[o], (R)sm.jr[k]);
+    if (dxok && sm.jx[k] != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(sm.jx[k], g) * sm.iax[b]));
+    if (drok && sm.jr[k] != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(sm.jr[k], g) * sm.iar[b]));
     if (M1) {
       using A = Acc1<R>;
       if (dxok && A::nonzero(sm.jx1[k])) {
