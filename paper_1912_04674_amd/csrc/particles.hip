@@ -69,30 +69,33 @@ __device__ inline void lds_add(double* a, double v) { atomicAdd(a, v); }
 // magnitude and the <= 2 CHUNK contributions of a work item to one node stay
 // below 2^63.  The float -> int64 conversion adds 1.5 2^52 in FP64 and reads
 // the mantissa bits (round to nearest, exact for |x| < 2^51).
+// add_prod(a, u, x, y) adds u x and u y, formed in FP64 (the float -> int64
+// conversion then costs one FMA with the magic constant and one subtract).
 template <class R> struct Acc1;
 template <> struct Acc1<double> {
   using T = double2;
   __device__ static T zero() { return make_double2(0.0, 0.0); }
   __device__ static double scale(const Geo&) { return 1.0; }
-  __device__ static void add(T* a, double re, double im) {
-    atomicAdd(&a->x, re);
-    atomicAdd(&a->y, im);
+  __device__ static void add_prod(T* a, double u, double x, double y) {
+    atomicAdd(&a->x, u * x);
+    atomicAdd(&a->y, u * y);
   }
   __device__ static bool nonzero(const T& v) { return v.x != 0.0 || v.y != 0.0; }
   __device__ static double re(const T& v, const Geo&) { return v.x; }
   __device__ static double im(const T& v, const Geo&) { return v.y; }
 };
-__device__ inline long long to_fixed(float x) {
+// nearest integer to u x (|u x| < 2^51): the mantissa bits of u x + 1.5 2^52
+__device__ inline long long fixed_prod(double u, double x) {
   const double m = 6755399441055744.0;  // 1.5 * 2^52
-  return __double_as_longlong((double)x + m) - __double_as_longlong(m);
+  return __double_as_longlong(fma(u, x, m)) - __double_as_longlong(m);
 }
 template <> struct Acc1<float> {
   using T = longlong2;
   __device__ static T zero() { return make_longlong2(0, 0); }
   __device__ static float scale(const Geo& g) { return g.fix; }
-  __device__ static void add(T* a, float re, float im) {  // re, im already scaled
-    atomicAdd((unsigned long long*)&a->x, (unsigned long long)to_fixed(re));
-    atomicAdd((unsigned long long*)&a->y, (unsigned long long)to_fixed(im));
+  __device__ static void add_prod(T* a, double u, double x, double y) {  // already scaled
+    atomicAdd((unsigned long long*)&a->x, (unsigned long long)fixed_prod(u, x));
+    atomicAdd((unsigned long long*)&a->y, (unsigned long long)fixed_prod(u, y));
   }
   __device__ static bool nonzero(const T& v) { return v.x != 0 || v.y != 0; }
   __device__ static float re(const T& v, const Geo& g) { return (float)((double)v.x * g.unfix); }
@@ -111,13 +114,15 @@ template <class R> struct Acc0;
 template <> struct Acc0<double> {
   using T = double;
   __device__ static double scale(const Geo&) { return 1.0; }
-  __device__ static void add(T* a, double v) { atomicAdd(a, v); }
+  __device__ static void add_prod(T* a, double u, double x) { atomicAdd(a, u * x); }
   __device__ static double val(T v, const Geo&) { return v; }
 };
 template <> struct Acc0<float> {
   using T = long long;
-  __device__ static float scale(const Geo& g) { return g.fix0; }
-  __device__ static void add(T* a, float v) { atomicAdd((unsigned long long*)a, (unsigned long long)to_fixed(v)); }
+  __device__ static double scale(const Geo& g) { return g.fix0; }
+  __device__ static void add_prod(T* a, double u, double x) {
+    atomicAdd((unsigned long long*)a, (unsigned long long)fixed_prod(u, x));
+  }
   __device__ static double val(T v, const Geo& g) { return (double)v * g.unfix0; }
 };
 
@@ -454,12 +459,13 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     if (DEFER) {
       gscr[d] = (R)1 / igb;
     } else {
-      const R wg = w * igb * Acc0<R>::scale(g);
+      const R wg = w * igb * (R)Acc0<R>::scale(g);
 #pragma unroll
       for (int aa = 0; aa < 2; ++aa) {
-        const R wa = wg * (aa ? Px.b : Px.a);
+        const double wa = (double)(wg * (aa ? Px.b : Px.a));
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb) Acc0<R>::add(&sm.chi[(Px.i + aa) * LR + Pr.i + bb], wa * (bb ? Pr.b : Pr.a));
+        for (int bb = 0; bb < 2; ++bb)
+          Acc0<R>::add_prod(&sm.chi[(Px.i + aa) * LR + Pr.i + bb], wa, (double)(bb ? Pr.b : Pr.a));
       }
     }
     if (SCAT != SCAT_NONE) {
@@ -588,19 +594,20 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
   using A0 = Acc0<R>;
   typename A0::T* jx = &sm.jx[amin * LR + bmin];
   typename A0::T* jr = &sm.jr[amin * LR + bmin];
-  const R hw = (R)0.5 * w * A0::scale(g);
+  const double hw = 0.5 * (double)w * A0::scale(g);
+  const double cx0d = cx0, cx1d = cx1, cr0d = cr0, cr1d = cr1;
 #pragma unroll
   for (int bb = 0; bb < 3; ++bb) {
-    const R sr = (S0r[bb] + S1r[bb]) * hw;
-    if (cx0 != (R)0) A0::add(&jx[bb], cx0 * sr);
-    if (cx1 != (R)0) A0::add(&jx[LR + bb], cx1 * sr);
+    const double sr = (double)(S0r[bb] + S1r[bb]) * hw;
+    if (cx0 != (R)0) A0::add_prod(&jx[bb], cx0d, sr);
+    if (cx1 != (R)0) A0::add_prod(&jx[LR + bb], cx1d, sr);
   }
   // J_r (i, j+1/2): flux accumulated along r
 #pragma unroll
   for (int aa = 0; aa < 3; ++aa) {
-    const R sx = (S0x[aa] + S1x[aa]) * hw;
-    if (cr0 != (R)0) A0::add(&jr[aa * LR], cr0 * sx);
-    if (cr1 != (R)0) A0::add(&jr[aa * LR + 1], cr1 * sx);
+    const double sx = (double)(S0x[aa] + S1x[aa]) * hw;
+    if (cr0 != (R)0) A0::add_prod(&jr[aa * LR], cr0d, sx);
+    if (cr1 != (R)0) A0::add_prod(&jr[aa * LR + 1], cr1d, sx);
   }
   if (M1) {
     // Cartesian mid-point of the old and new positions: in the frame of the
@@ -658,7 +665,7 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
     // accumulator scale folded in; radial weights times inverse volumes
     const R q2 = (R)-2 * w * Acc1<R>::scale(g);
     const R vx = q2 * mv.vx, vr = q2 * (mv.vy * c + mv.vz * s), vt = q2 * (mv.vz * c - mv.vy * s);
-    const R xc = vx * c, xs = vx * s, rc = vr * c, rs = vr * s, tc = vt * c, ts = vt * s;
+    const double xc = vx * c, xs = vx * s, rc = vr * c, rs = vr * s, tc = vt * c, ts = vt * s;
     const R pv[2] = {Pr.a * sm.ivn[Pr.i], Pr.b * sm.ivn[Pr.i + 1]};
     // J_r1 rows; row -1/2 folds onto +1/2 (even for mode 1)
     const int dn0 = (q.R0 + Dr.i == -1) ? Dr.i + 1 : Dr.i, dn1 = Dr.i + 1;
@@ -669,10 +676,10 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
       const R wdx = aa ? Dx.b : Dx.a, wpx = aa ? Px.b : Px.a;
 #pragma unroll
       for (int bb = 0; bb < 2; ++bb) {
-        const R ux = wdx * pv[bb], ur = wpx * dv[bb], ut = wpx * pv[bb];
-        Acc1<R>::add(&sm.jx1[(Dx.i + aa) * LR + Pr.i + bb], ux * xc, ux * xs);  // (i+1/2, j)
-        Acc1<R>::add(&sm.jr1[(Px.i + aa) * LR + dn[bb]], ur * rc, ur * rs);     // (i, j+1/2)
-        Acc1<R>::add(&sm.jt1[(Px.i + aa) * LR + Pr.i + bb], ut * tc, ut * ts);  // (i, j)
+        const double ux = wdx * pv[bb], ur = wpx * dv[bb], ut = wpx * pv[bb];
+        Acc1<R>::add_prod(&sm.jx1[(Dx.i + aa) * LR + Pr.i + bb], ux, xc, xs);  // (i+1/2, j)
+        Acc1<R>::add_prod(&sm.jr1[(Px.i + aa) * LR + dn[bb]], ur, rc, rs);     // (i, j+1/2)
+        Acc1<R>::add_prod(&sm.jt1[(Px.i + aa) * LR + Pr.i + bb], ut, tc, ts);  // (i, j)
       }
     }
   }
