@@ -192,12 +192,15 @@ int envpic_set_particles(envpic_sim* s, int64_t n, const double* x, const double
                          const double* z, const double* px, const double* py, const double* pz,
                          const double* w, const uint32_t* id);
 
-/* Stage timing: with timing enabled, HIP events are recorded on the
- * simulation's stream around the kernels of each stage (momentum, envelope,
- * position, field = Maxwell + window + injection + sort scan).
- * envpic_get_timing synchronises and writes the average milliseconds per
- * launch into out_ms[4] and the launch counts into counts[4] (either may be
- * NULL); enabling or disabling resets the sums. */
+/* Stage timing: with enable = k > 0, HIP events (without a system-scope
+ * fence) are recorded on the simulation's stream around the kernels of each
+ * stage (momentum, envelope, position, field = Maxwell + window + injection +
+ * sort scans) of every step whose index is a multiple of k (k = 1: every
+ * step; a k coprime to the sort periods 3 and 24 samples every variant
+ * evenly); enable = 0 turns timing off.  envpic_get_timing synchronises and
+ * writes the average milliseconds per timed launch into out_ms[4] and the
+ * timed launch counts into counts[4] (either may be NULL); every call of
+ * envpic_set_timing resets the sums. */
 int envpic_set_timing(envpic_sim* s, int enable);
 int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts);
 

@@ -238,7 +238,7 @@ struct envpic_sim {
     int stage;
     hipEvent_t a, b;
   };
-  bool timing = false;
+  int timing = 0;  // record the stage events on every timing-th step (0: off)
   std::vector<hipEvent_t> ev_pool;
   std::vector<Tick> ticks;
   hipEvent_t ev_open = nullptr;
@@ -251,17 +251,19 @@ struct envpic_sim {
       ev_pool.pop_back();
       return e;
     }
+    // timing only: no system-scope fence (no cache writeback and
+    // invalidation between the stages being timed)
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
   }
   void tick_begin() {
-    if (!timing) return;
+    if (timing <= 0 || n % timing != 0) return;
     ev_open = take_event();
     if (ev_open) (void)hipEventRecord(ev_open, stream);
   }
   void tick_end(int stage) {
-    if (!timing || !ev_open) return;
+    if (!ev_open) return;
     hipEvent_t e = take_event();
     if (!e) return;
     (void)hipEventRecord(e, stream);
@@ -1033,7 +1035,7 @@ int envpic_set_timing(envpic_sim* s, int enable) {
     s->t_ms[k] = 0.0;
     s->t_n[k] = 0;
   }
-  s->timing = enable != 0;
+  s->timing = enable > 0 ? enable : 0;
   return ENVPIC_OK;
 }
 

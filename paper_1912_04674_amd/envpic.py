@@ -252,8 +252,9 @@ class Sim:
         _check(lib().envpic_set_particles(self._h, n, *(_dptr(a) for a in arrs),
                                           ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
 
-    def set_timing(self, enable=True):
-        _check(lib().envpic_set_timing(self._h, int(bool(enable))))
+    def set_timing(self, enable=True, every=1):
+        """Record stage events on every `every`-th step (off if not enable)."""
+        _check(lib().envpic_set_timing(self._h, int(every) if enable else 0))
 
     def timing(self):
         """Average ms per launch and launch counts of the momentum, envelope,

@@ -381,6 +381,11 @@ def test_stage_timing_does_not_change_results(E):
     assert all(ms > 0 for ms, _ in t.values()), t
     b.step(7)
     compare_fields(a, b, 1e-12, names=("env", "chi", "ex", "er", "bt"), modes=1)
+    # sampled: steps 7..12, timed where the step index is a multiple of 3
+    a.set_timing(True, every=3)
+    a.step(6)
+    t = a.timing()
+    assert all(n == 2 for _, n in t.values()), t
     a.set_timing(False)
     a.step(1)
     assert all(n == 0 for _, n in a.timing().values())
