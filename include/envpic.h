@@ -11,10 +11,11 @@
  *   2. envelope stage  (Sec. 3, Eq. envelope_solver and the cylindrical
  *      Laplacian after it): A^{n+1} from A^n, A^{n-1}, chi^n;
  *   3. position stage  (Sec. 2, Eq. EquationsOfMotion): x^n -> x^{n+1} with
- *      gbar from Phi^{n+1/2}, deposit J^{n+1/2};
+ *      gbar from Phi^{n+1/2}, deposit J^{n+1/2}; when the window moves at
+ *      this step, the plasma of the entering column is loaded (Sec. 4);
  *   4. field stage     (Sec. 2, Eq. MaxwellEqsCylindrical; Sec. 3, FDTD with
- *      dt/2 staggering): E^{n+1}, B^{n+3/2}, Bbar^{n+1}; moving window and
- *      injection (Sec. 4); particle tile sort for the next step.
+ *      dt/2 staggering): E^{n+1}, B^{n+3/2}, Bbar^{n+1}; moving window
+ *      (Sec. 4); particle tile sort for the next step.
  *
  * Units (Sec. 2): lengths c/w0, time 1/w0, momenta m_e c, fields
  * m_e c w0 / e, densities n_c.  Electrons only (charge -1, mass 1).
@@ -194,10 +195,10 @@ int envpic_set_particles(envpic_sim* s, int64_t n, const double* x, const double
 
 /* Stage timing: with enable = k > 0, HIP events (without a system-scope
  * fence) are recorded on the simulation's stream around the kernels of each
- * stage (momentum, envelope, position, field = Maxwell + window + injection +
- * sort scans) of every step whose index is a multiple of k (k = 1: every
- * step; a k coprime to the sort periods 3 and 24 samples every variant
- * evenly); enable = 0 turns timing off.  envpic_get_timing synchronises and
+ * stage (momentum; envelope; position = push, deposit, injection; field =
+ * Maxwell, window, sort scans) of every step whose index is a multiple of k
+ * (k = 1: every step; a k coprime to the sort periods 3 and 24 samples every
+ * variant evenly); enable = 0 turns timing off.  envpic_get_timing synchronises and
  * writes the average milliseconds per timed launch into out_ms[4] and the
  * timed launch counts into counts[4] (either may be NULL); every call of
  * envpic_set_timing resets the sums. */

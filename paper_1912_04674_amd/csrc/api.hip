@@ -347,7 +347,9 @@ template <class R> struct SimT : envpic_sim {
     return nmax * 2.0 * pi * (p.nr * p.dr) * (p.dr / p.ppc_r) * (p.dx / p.ppc_x) / p.ppc_t;
   }
 
-  Geo geo() const {
+  Geo geo() const { return geo_at(shift); }
+  // the geometry with the window's left edge at lab column sh
+  Geo geo_at(int64_t sh) const {
     Geo g{};
     g.nx = p.nx;
     g.nr = p.nr;
@@ -360,10 +362,10 @@ template <class R> struct SimT : envpic_sim {
     g.ppc_x = p.ppc_x;
     g.ppc_r = p.ppc_r;
     g.ppc_t = p.ppc_t;
-    g.shift = shift;
+    g.shift = sh;
     g.cap = sz.capacity;
-    g.base = (int)(shift % sz.nxa);
-    const long long c = shift - 2;
+    g.base = (int)(sh % sz.nxa);
+    const long long c = sh - 2;
     g.t_lo = (int)(c >= 0 ? c / TX : -((-c + TX - 1) / TX));
     g.dx = p.dx;
     g.dr = p.dr;
@@ -535,9 +537,20 @@ template <class R> struct SimT : envpic_sim {
   int position(bool defer) override {
     if (stage != 2) return fail(ENVPIC_EORDER, "position stage out of order");
     const Geo g = geo();
+    const bool shifting = shift_due();
+    // the plasma of the column entering the window at this step's shift is
+    // loaded by extra work groups of the same launch (particles appended
+    // past the live range; the field stage adds its items to the layout)
+    InjectArgs inj{};
+    inj.gn = geo_at(shift + 1);
+    inj.pl = plasma();
+    inj.capacity = sz.capacity;
+    inj.max_items = sz.max_items;
+    inj.pending = S.pending;
+    inj.blocks = (shifting && p.profile != ENVPIC_PROFILE_NONE) ? inject_blocks<R>(inj.gn) : 0;
     tick_begin();
-    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.ccount, shift_due() ? 1 : 0,
-                       presort() ? 1 : 0, S.scr, S.err, sz.max_items, defer, stream);
+    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.ccount, shifting ? 1 : 0,
+                       presort() ? 1 : 0, S.scr, S.err, sz.max_items, defer, inj, stream);
     tick_end(2);
     stage = 3;
     deferred = defer;
@@ -552,10 +565,6 @@ template <class R> struct SimT : envpic_sim {
     const bool shifting = shift_due(), pre = presort();
     if (shifting) shift += 1;
     const Geo gn = geo();
-    // the column entering the window is loaded first (it touches particles only)
-    if (shifting && p.profile != ENVPIC_PROFILE_NONE)
-      launch_inject<R>(gn, plasma(), S.parts[cur], S.lay[cur], S.ccount, pre ? 1 : 0, sz.capacity, sz.max_items,
-                       S.pending, S.err, stream);
     FieldArgs fa{};
     fa.gn = gn;
     fa.shifting = shifting ? 1 : 0;

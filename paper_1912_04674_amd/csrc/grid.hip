@@ -298,13 +298,22 @@ __device__ inline void window_row(const Geo& g, const Grids<R>& f, const Deposit
 // One kernel for the field stage, its work groups in three roles: Maxwell
 // tiles (geometry before the shift); if the window moves, the rows of its
 // column resets (geometry after it); before a sort, the per-tile cell scans
-// (two tiles per group).  No role reads another's output.
+// (two tiles per group).  No role reads another's output.  On a step
+// without a sort, one thread also adds the items and slots of a column
+// injected by the position pass to the layout in use.
 template <class R, bool M1>
 __global__ __launch_bounds__(MW_T) void k_field(Geo g, Grids<R> f, DepositBufs<R> din, DepositBufs<R> dnext,
                                                DepositBufs<R> d0, DepositBufs<R> d1, FieldArgs fa) {
   __shared__ MwShared<R, M1> sm;
   __shared__ int s_a[MW_T];
   const int blk = blockIdx.x;
+  if (!fa.presort && blk == 0 && threadIdx.x == 0 && fa.pending[0] != 0) {
+    // an injected column's items and slots join the layout in use
+    *fa.bump_items += fa.pending[0];
+    *fa.bump_fill += fa.pending[1];
+    fa.pending[0] = 0;
+    fa.pending[1] = 0;
+  }
   if (blk < fa.nb_mw) {
     maxwell_tile<R, M1>(g, f, din, dnext, (blk / fa.nbx_mw) * MW_TI, (blk % fa.nbx_mw) * MW_TJ, fa.shifting != 0, sm);
   } else if (blk < fa.nb_mw + fa.nb_win) {
@@ -316,8 +325,8 @@ __global__ __launch_bounds__(MW_T) void k_field(Geo g, Grids<R> f, DepositBufs<R
   }
 }
 
-// the layout scan over all tile totals (or only the injected column's items
-// added to the layout in use), one work group
+// before a sort: the injected column's items and slots added to the layout
+// in use, then the scan of all tile totals into the next layout (one group)
 constexpr int SCAN_T = 1024;
 __global__ __launch_bounds__(SCAN_T) void k_layout_scan(FieldArgs fa) {
   __shared__ int s_a[SCAN_T], s_b[SCAN_T];
@@ -389,7 +398,7 @@ void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, co
     hipLaunchKernelGGL((k_field<R, true>), dim3(grid), dim3(MW_T), 0, st, g, f, din, dnext, d0, d1, fa);
   else
     hipLaunchKernelGGL((k_field<R, false>), dim3(grid), dim3(MW_T), 0, st, g, f, din, dnext, d0, d1, fa);
-  hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(fa.presort ? SCAN_T : 64), 0, st, fa);
+  if (fa.presort) hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(SCAN_T), 0, st, fa);
 }
 
 template <class R>

@@ -19,11 +19,22 @@ template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                      const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
                      int scatter, hipStream_t st);
+// the plasma of the column entering the window at this step's shift,
+// loaded by extra work groups of the position pass (blocks == 0: none)
+struct InjectArgs {
+  Geo gn;  // geometry after the shift
+  Plasma pl;
+  long long capacity;
+  int max_items;
+  int* pending;  // items and slots appended, added to the layout by the field stage
+  int blocks;
+};
 // count_cells: add the particles' new cells into ccount (before a sort)
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
                      int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
-                     hipStream_t st);
+                     const InjectArgs& inj, hipStream_t st);
+template <class R> int inject_blocks(const Geo& g);
 template <class R>
 void launch_deposit_chi(const Geo& g, R* chi, const Parts<R>& P, const Layout& L, const R* gscr, int* err, int grid,
                         hipStream_t st);
@@ -32,9 +43,6 @@ void launch_deposit_J(const Geo& g, const DepositBufs<R>& d, const Parts<R>& P, 
                       const Parts<R>& scr, int* err, int grid, hipStream_t st);
 template <class R>
 void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, const int* offsets, hipStream_t st);
-template <class R>
-void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* ccount, int count_cells,
-                   long long capacity, int max_items, int* pending, int* err, hipStream_t st);
 
 template <class R>
 void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st);

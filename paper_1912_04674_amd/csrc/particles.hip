@@ -757,6 +757,89 @@ __device__ inline void flush_cells(const int* cc, const Region& q, const Geo& g,
   }
 }
 
+// ============================================== loading / injection ==
+// Plasma of lab cell column `col`, radial cell j: regular in x and r, one
+// SplitMix64 angle per cell with equally spaced angles inside the cell,
+// weights n 2 pi r (dr/N_r)(dx/N_x)/N_theta.  Particle k of the cell is
+// stored at base + transpose_rank(r0 + k, n_range).  Returns 1 if live.
+template <class R>
+__device__ inline int load_particle(const Geo& g, const Plasma& pl, Parts<R> P, int base, int r0, int n_range,
+                                    long long col, int j, int k) {
+  const double pi = 3.14159265358979323846;
+  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
+  const int t = k % g.ppc_t, b = (k / g.ppc_t) % g.ppc_r, a = k / (g.ppc_t * g.ppc_r);
+  const double fx = (a + 0.5) / g.ppc_x, fr = (b + 0.5) / g.ppc_r;
+  const double xl = ((double)col + fx) * g.dx;
+  const double r = (j + fr) * g.dr;
+  const double n = plasma_density(pl, xl, col, j);
+  const int s = base + transpose_rank(r0 + k, n_range);
+  P.px[s] = 0;
+  P.py[s] = 0;
+  P.pz[s] = 0;
+  P.id[s] = (uint32_t)(col * (long long)g.nr * ppc + (long long)j * ppc + k);
+  if (!(n > 0.0)) {
+    P.cell[s] = kDead;
+    P.fx[s] = 0;
+    P.fr[s] = 0;
+    P.th[s] = 0;
+    P.w[s] = 0;
+    return 0;
+  }
+  const double th0 = 2.0 * pi * counter_uniform(pl.seed, STREAM_ANGLE, col, j);
+  double th = th0 + 2.0 * pi * t / g.ppc_t;  // in [0, 4 pi): fold into (-pi, pi]
+  if (th > pi) th -= 2.0 * pi;
+  if (th > pi) th -= 2.0 * pi;
+  P.cell[s] = pack_cell((int)col, j);
+  P.fx[s] = (R)fx;
+  P.fr[s] = (R)fr;
+  P.th[s] = (R)th;
+  P.w[s] = (R)(n * 2.0 * pi * r * (g.dr / g.ppc_r) * (g.dx / g.ppc_x) / g.ppc_t);
+  return 1;
+}
+
+// One work group (WG threads, group index blk) of the injection: the
+// plasma of lab column gn.shift + nx - 1 appended at the layout's fill
+// pointer, tile by tile, with one work item per tile; s_cnt holds WG + 1 ints.
+template <class R>
+__device__ void inject_block(const InjectArgs& ia, Parts<R> P, const Layout& L, int* __restrict__ ccount,
+                             int count_cells, int* err, int blk, int* s_cnt) {
+  const Geo& g = ia.gn;
+  const long long col = g.shift + g.nx - 1;
+  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
+  const int total = *L.fill;  // end of the used slots
+  const int base_items = *L.n_items;
+  if ((long long)total + (long long)g.nr * ppc > ia.capacity || base_items + g.ntr > ia.max_items || col > COL_MAX) {
+    if (blk == 0 && threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
+    return;
+  }
+  // live particles per cell (one cell = ppc consecutive threads), counted in
+  // LDS first: a group spans WG / ppc + 1 rows at most
+  const int idx = blk * WG + threadIdx.x;
+  const int j_first = (blk * WG) / ppc;
+  for (int k = threadIdx.x; k < WG + 1; k += WG) s_cnt[k] = 0;
+  __syncthreads();
+  if (idx < g.nr * ppc) {
+    const int j = idx / ppc, k = idx - (idx / ppc) * ppc;
+    const int t = j / TR, trt = min(TR, g.nr - t * TR);
+    if (load_particle<R>(g, ia.pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j, k))
+      atomicAdd(&s_cnt[j - j_first], 1);
+  }
+  __syncthreads();
+  if (count_cells) {
+    const int pc = phys_col(g, g.nx - 1);
+    for (int k = threadIdx.x; k < WG + 1; k += WG)
+      if (s_cnt[k] > 0 && j_first + k < g.nr) atomicAdd(&ccount[(size_t)pc * g.pitch + j_first + k], s_cnt[k]);
+  }
+  if (idx < g.ntr) {
+    const int trt = min(TR, g.nr - idx * TR);
+    L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), total + idx * TR * ppc, trt * ppc, 0);
+  }
+  if (idx == 0) {
+    ia.pending[0] = g.ntr;       // items appended
+    ia.pending[1] = g.nr * ppc;  // slots appended
+  }
+}
+
 // vacate: 1 when the window moves after this step (particles whose new
 // column is the window's first one are dropped after depositing);
 // count_cells: 1 when the particles are re-sorted at the next step (their
@@ -768,9 +851,16 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
                                                  typename cplx_of<R>::type* __restrict__ jr1_out,
                                                  typename cplx_of<R>::type* __restrict__ jt1_out,
                                                  Parts<R> P, Layout L, int* __restrict__ ccount, int vacate,
-                                                 int count_cells, Parts<R> scr, int* err) {
+                                                 int count_cells, Parts<R> scr, int* err, int item_blocks,
+                                                 InjectArgs inj) {
   __shared__ SmemPos<R, M1> sm;
   const int item = blockIdx.x;
+  if (item >= item_blocks) {
+    // the phi staging area is free in these groups: it holds the row counts
+    static_assert(sizeof(sm.phh) >= (WG + 1) * sizeof(int), "row counts do not fit");
+    inject_block<R>(inj, P, L, ccount, count_cells, err, item - item_blocks, reinterpret_cast<int*>(sm.phh));
+    return;
+  }
   if (item >= *L.n_items) return;
   const int4 it = L.items[item];
   const int start = it.y, count = it.z;
@@ -954,46 +1044,6 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
   flush_current(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
 }
 
-// ============================================== loading / injection ==
-// Plasma of lab cell column `col`, radial cell j: regular in x and r, one
-// SplitMix64 angle per cell with equally spaced angles inside the cell,
-// weights n 2 pi r (dr/N_r)(dx/N_x)/N_theta.  Particle k of the cell is
-// stored at base + transpose_rank(r0 + k, n_range).  Returns 1 if live.
-template <class R>
-__device__ inline int load_particle(const Geo& g, const Plasma& pl, Parts<R> P, int base, int r0, int n_range,
-                                    long long col, int j, int k) {
-  const double pi = 3.14159265358979323846;
-  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
-  const int t = k % g.ppc_t, b = (k / g.ppc_t) % g.ppc_r, a = k / (g.ppc_t * g.ppc_r);
-  const double fx = (a + 0.5) / g.ppc_x, fr = (b + 0.5) / g.ppc_r;
-  const double xl = ((double)col + fx) * g.dx;
-  const double r = (j + fr) * g.dr;
-  const double n = plasma_density(pl, xl, col, j);
-  const int s = base + transpose_rank(r0 + k, n_range);
-  P.px[s] = 0;
-  P.py[s] = 0;
-  P.pz[s] = 0;
-  P.id[s] = (uint32_t)(col * (long long)g.nr * ppc + (long long)j * ppc + k);
-  if (!(n > 0.0)) {
-    P.cell[s] = kDead;
-    P.fx[s] = 0;
-    P.fr[s] = 0;
-    P.th[s] = 0;
-    P.w[s] = 0;
-    return 0;
-  }
-  const double th0 = 2.0 * pi * counter_uniform(pl.seed, STREAM_ANGLE, col, j);
-  double th = th0 + 2.0 * pi * t / g.ppc_t;  // in [0, 4 pi): fold into (-pi, pi]
-  if (th > pi) th -= 2.0 * pi;
-  if (th > pi) th -= 2.0 * pi;
-  P.cell[s] = pack_cell((int)col, j);
-  P.fx[s] = (R)fx;
-  P.fr[s] = (R)fr;
-  P.th[s] = (R)th;
-  P.w[s] = (R)(n * 2.0 * pi * r * (g.dr / g.ppc_r) * (g.dx / g.ppc_x) / g.ppc_t);
-  return 1;
-}
-
 // initial loading of window cells in tile-major order (offsets per tile
 // from the host, cells of a tile column-major inside the tile)
 template <class R>
@@ -1009,53 +1059,6 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
   for (int k = 0; k < ppc; ++k) load_particle<R>(g, pl, P, offsets[key], local * ppc, tct * trt * ppc, col, j, k);
 }
-
-// injection of the cell column entering the window after a shift (g holds
-// the new shift), one thread per particle; particles are appended after the
-// live range of P and get one work item per tile row.  The item count of L
-// is raised by the scan that follows (via *pending), after every block has
-// read it here.
-template <class R>
-__global__ void k_inject(Geo g, Plasma pl, Parts<R> P, Layout L, int* __restrict__ ccount, int count_cells,
-                         long long capacity, int max_items, int* __restrict__ pending, int* err) {
-  const long long col = g.shift + g.nx - 1;
-  const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
-  const int total = *L.fill;  // end of the used slots
-  const int base_items = *L.n_items;
-  if ((long long)total + (long long)g.nr * ppc > capacity || base_items + g.ntr > max_items || col > COL_MAX) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
-    return;
-  }
-  // live particles per cell (one cell = ppc consecutive threads), counted in
-  // LDS first: a block spans blockDim / ppc + 1 rows at most
-  __shared__ int s_cnt[257];
-  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  const int j_first = (blockIdx.x * blockDim.x) / ppc;
-  for (int k = threadIdx.x; k < 257; k += blockDim.x) s_cnt[k] = 0;
-  __syncthreads();
-  if (idx < g.nr * ppc) {
-    const int j = idx / ppc, k = idx - (idx / ppc) * ppc;
-    const int t = j / TR, trt = min(TR, g.nr - t * TR);
-    if (load_particle<R>(g, pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j, k))
-      atomicAdd(&s_cnt[j - j_first], 1);
-  }
-  __syncthreads();
-  if (count_cells) {
-    const int pc = phys_col(g, g.nx - 1);
-    for (int k = threadIdx.x; k < 257; k += blockDim.x)
-      if (s_cnt[k] > 0 && j_first + k < g.nr) atomicAdd(&ccount[(size_t)pc * g.pitch + j_first + k], s_cnt[k]);
-  }
-  if (idx < g.ntr) {
-    const int trt = min(TR, g.nr - idx * TR);
-    L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), total + idx * TR * ppc, trt * ppc, 0);
-  }
-  if (idx == 0) {
-    pending[0] = g.ntr;           // items appended
-    pending[1] = g.nr * ppc;      // slots appended
-  }
-}
-
-// counts of live particles per tile of their current position
 
 // ============================================================ launchers ==
 template <class R, bool M1, bool DEFER>
@@ -1091,21 +1094,27 @@ void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& sr
   }
 }
 
+template <class R> int inject_blocks(const Geo& g) {
+  const int n = std::max(g.nr * g.ppc_x * g.ppc_r * g.ppc_t, g.ntr);
+  return (n + WG - 1) / WG;
+}
+
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
                      int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
-                     hipStream_t st) {
+                     const InjectArgs& inj, hipStream_t st) {
   if (grid <= 0) return;
+  const dim3 blocks(grid + inj.blocks);
   if (g.modes >= 2) {
     if (defer)
-      hipLaunchKernelGGL((k_position<R, true, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
+      hipLaunchKernelGGL((k_position<R, true, true>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
     else
-      hipLaunchKernelGGL((k_position<R, true, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
+      hipLaunchKernelGGL((k_position<R, true, false>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
   } else {
     if (defer)
-      hipLaunchKernelGGL((k_position<R, false, true>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
+      hipLaunchKernelGGL((k_position<R, false, true>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
     else
-      hipLaunchKernelGGL((k_position<R, false, false>), dim3(grid), dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err);
+      hipLaunchKernelGGL((k_position<R, false, false>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
   }
 }
 
@@ -1133,13 +1142,6 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
   hipLaunchKernelGGL((k_init_particles<R>), dim3(grid), dim3(256), 0, st, g, pl, P, offsets);
 }
 
-template <class R>
-void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layout& L, int* ccount, int count_cells,
-                   long long capacity, int max_items, int* pending, int* err, hipStream_t st) {
-  const int n = std::max(g.nr * g.ppc_x * g.ppc_r * g.ppc_t, g.ntr);
-  hipLaunchKernelGGL((k_inject<R>), dim3((n + 255) / 256), dim3(256), 0, st, g, pl, P, L, ccount, count_cells, capacity,
-                     max_items, pending, err);
-}
 
 
 #define ENVPIC_INST(R)                                                                                          \
@@ -1147,14 +1149,13 @@ void launch_inject(const Geo& g, const Plasma& pl, const Parts<R>& P, const Layo
                                    const Layout&, const Layout&, int*, R*, int*, int, bool, int, hipStream_t);  \
   template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
                                    const Layout&, int*, int, int, const Parts<R>&, int*, int, bool,             \
-                                   hipStream_t);                                                                \
+                                   const InjectArgs&, hipStream_t);                                             \
+  template int inject_blocks<R>(const Geo&);                                                                    \
   template void launch_deposit_chi<R>(const Geo&, R*, const Parts<R>&, const Layout&, const R*, int*, int,      \
                                       hipStream_t);                                                             \
   template void launch_deposit_J<R>(const Geo&, const DepositBufs<R>&, const Parts<R>&, const Layout&, int,     \
                                     const Parts<R>&, int*, int, hipStream_t);                                   \
-  template void launch_init_particles<R>(const Geo&, const Plasma&, const Parts<R>&, const int*, hipStream_t);  \
-  template void launch_inject<R>(const Geo&, const Plasma&, const Parts<R>&, const Layout&, int*, int,         \
-                                 long long, int, int*, int*, hipStream_t);
+  template void launch_init_particles<R>(const Geo&, const Plasma&, const Parts<R>&, const int*, hipStream_t);
 ENVPIC_INST(float)
 ENVPIC_INST(double)
 #undef ENVPIC_INST
