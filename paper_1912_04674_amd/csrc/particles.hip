@@ -248,6 +248,19 @@ template <class R, bool M1> struct SmemMom {
 };
 constexpr int PPT = CHUNK / WG;  // particles per thread of a work item
 
+// Work item of work group b (of n groups).  Work groups are dealt to the 8
+// XCDs in turn; runs of XG consecutive items (radially adjacent tiles, whose
+// LDS regions overlap) are given to one XCD so that the halo lines they
+// share are fetched into that XCD's L2 once, and the runs rotate over the
+// XCDs, which keeps their loads even.  A bijection of [0, n).
+constexpr int XCDS = 8, XG = 4;
+__device__ inline int item_of(int b, int n) {
+  constexpr int sg = XCDS * XG;
+  if (b >= (n / sg) * sg) return b;
+  const int q = b / XCDS, x = b - q * XCDS;
+  return ((q / XG) * XCDS + x) * XG + (q - (q / XG) * XG);
+}
+
 // SCAT: SCAT_NONE updates p in place and keeps the layout; otherwise every
 // particle moves into the next layout (the tiles of x^n).  SCAT_TILE keeps
 // the particles' relative order (coalesced writes); SCAT_CELL orders each
@@ -260,7 +273,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
                                                  int* __restrict__ ccur, R* __restrict__ gscr, int* err) {
   using C = typename cplx_of<R>::type;
   __shared__ SmemMom<R, M1> sm;
-  const int item = blockIdx.x;
+  const int item = item_of(blockIdx.x, gridDim.x);
   if (item >= *Ls.n_items) return;
   const int4 it = Ls.items[item];
   const int start = it.y, count = it.z;
@@ -854,13 +867,13 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
                                                  int count_cells, Parts<R> scr, int* err, int item_blocks,
                                                  InjectArgs inj) {
   __shared__ SmemPos<R, M1> sm;
-  const int item = blockIdx.x;
-  if (item >= item_blocks) {
+  if ((int)blockIdx.x >= item_blocks) {
     // the phi staging area is free in these groups: it holds the row counts
     static_assert(sizeof(sm.phh) >= (WG + 1) * sizeof(int), "row counts do not fit");
-    inject_block<R>(inj, P, L, ccount, count_cells, err, item - item_blocks, reinterpret_cast<int*>(sm.phh));
+    inject_block<R>(inj, P, L, ccount, count_cells, err, blockIdx.x - item_blocks, reinterpret_cast<int*>(sm.phh));
     return;
   }
+  const int item = item_of(blockIdx.x, item_blocks);
   if (item >= *L.n_items) return;
   const int4 it = L.items[item];
   const int start = it.y, count = it.z;
@@ -963,7 +976,7 @@ __global__ __launch_bounds__(WG) void k_deposit_chi(Geo g, R* __restrict__ chi_o
                                                     Layout L, const R* __restrict__ gscr, int* err) {
   __shared__ double acc[LN];
   __shared__ R ivol[LR];
-  const int item = blockIdx.x;
+  const int item = item_of(blockIdx.x, gridDim.x);
   if (item >= *L.n_items) return;
   const int4 it = L.items[item];
   const Region q = region_of(g, it.x);
@@ -1008,7 +1021,7 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
                                                   typename cplx_of<R>::type* __restrict__ jt1_out,
                                                   Parts<R> P, Layout L, int vacate, Parts<R> scr, int* err) {
   __shared__ SmemPos<R, M1> sm;
-  const int item = blockIdx.x;
+  const int item = item_of(blockIdx.x, gridDim.x);
   if (item >= *L.n_items) return;
   const int4 it = L.items[item];
   const Region q = region_of(g, it.x);
