@@ -178,11 +178,8 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
                                     MwShared<R, M1>& sm) {
   using C = typename cplx_of<R>::type;
   constexpr int HJ = MwShared<R, M1>::HJ, HN = MwShared<R, M1>::HN;
-  for (int k = threadIdx.x; k < HN; k += MW_T) {
-    const int a = k / HJ, b = k - (k / HJ) * HJ;
-    const int i = i0 + a, j = j0 + b;
-    if (i > g.nx || j > g.nr) continue;
-    const ENew<R, M1> e = ampere<R, M1>(g, f, din, i, j);
+  static_assert(HN <= 2 * MW_T, "two nodes per thread at most");
+  auto put = [&](int k, const ENew<R, M1>& e) {
     sm.ex[k] = e.ex;
     sm.er[k] = e.er;
     if (M1) {
@@ -190,13 +187,42 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
       sm.er1[k] = e.er1;
       sm.et1[k] = e.et1;
     }
+  };
+  // E^{n+1} on the tile and its +1 column / row: node k and, in the first
+  // wavefronts, node k + MW_T as well, both in one straight-line block so
+  // that their loads are in flight together (indices clamped into the grid;
+  // nodes outside it are not stored and never read)
+  {
+    const int k0 = threadIdx.x, k1 = threadIdx.x + MW_T;
+    const int a0 = k0 / HJ, b0 = k0 - (k0 / HJ) * HJ;
+    const bool ok0 = i0 + a0 <= g.nx && j0 + b0 <= g.nr;
+    if ((int)(threadIdx.x & ~63u) < HN - MW_T) {  // wavefront-uniform
+      const int k1c = min(k1, HN - 1);
+      const int a1 = k1c / HJ, b1 = k1c - (k1c / HJ) * HJ;
+      const bool ok1 = k1 < HN && i0 + a1 <= g.nx && j0 + b1 <= g.nr;
+      const ENew<R, M1> e0 = ampere<R, M1>(g, f, din, min(i0 + a0, g.nx), min(j0 + b0, g.nr));
+      const ENew<R, M1> e1 = ampere<R, M1>(g, f, din, min(i0 + a1, g.nx), min(j0 + b1, g.nr));
+      if (ok0) put(k0, e0);
+      if (ok1) put(k1, e1);
+    } else if (ok0) {
+      put(k0, ampere<R, M1>(g, f, din, i0 + a0, j0 + b0));
+    }
   }
-  __syncthreads();
   const int a = threadIdx.x / MW_TJ, b = threadIdx.x - (threadIdx.x / MW_TJ) * MW_TJ;
   const int i = i0 + a, j = j0 + b;
-  if (i > g.nx || j > g.nr) return;
+  const bool own = i <= g.nx && j <= g.nr;
+  const size_t o = (size_t)phys_col(g, own ? i : 0) * g.pitch + (own ? j : 0);
+  // B^{n+1/2} of the owned node, loaded before the barrier
+  const R bt0 = f.bt[o];
+  C bx0{}, br0{}, btc0{};
+  if (M1) {
+    bx0 = f.bx1[o];
+    br0 = f.br1[o];
+    btc0 = f.bt1[o];
+  }
+  __syncthreads();
+  if (!own) return;
   const int k = a * HJ + b, kp = k + HJ;  // (i, j), (i+1, j)
-  const size_t o = (size_t)phys_col(g, i) * g.pitch + j;
   const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
   const bool ez = left_edge_zero && i == 1;
   // the new E of the owned node
@@ -210,7 +236,7 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
   }
   // ---- B^{n+3/2} and Bbar^{n+1}
   if (i <= g.nx - 1 && j <= g.nr - 1) {
-    const R b0 = f.bt[o];
+    const R b0 = bt0;
     const R b1 = b0 + dt * ((sm.ex[k + 1] - sm.ex[k]) * idr - (sm.er[kp] - sm.er[k]) * idx_);
     f.bt_n[o] = b1;
     f.btb[o] = (R)0.5 * (b0 + b1);
@@ -218,7 +244,7 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
   if (M1) {
     if (j <= g.nr - 1) {
       const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
-      const C b0 = f.bx1[o];
+      const C b0 = bx0;
       const C curl = cadd(cscale(csub(cscale(sm.et1[k + 1], (R)(j + 1)), cscale(sm.et1[k], (R)j)), irh),
                           cscale(cmuli(sm.er1[k]), irh));
       const C b1 = csub(b0, cscale(curl, dt));
@@ -227,12 +253,12 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
     }
     if (i <= g.nx - 1) {
       const C exr = j == 0 ? cscale(sm.ex1[k + 1], idr) : cscale(sm.ex1[k], (R)(1.0 / (j * g.dr)));
-      const C b0 = f.br1[o];
+      const C b0 = br0;
       const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(sm.et1[kp], sm.et1[k]), idx_)), dt));
       f.br1_n[o] = b1;
       f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
       if (j <= g.nr - 1) {
-        const C c0 = f.bt1[o];
+        const C c0 = btc0;
         const C c1 = cadd(c0, cscale(csub(cscale(csub(sm.ex1[k + 1], sm.ex1[k]), idr),
                                           cscale(csub(sm.er1[kp], sm.er1[k]), idx_)), dt));
         f.bt1_n[o] = c1;
