@@ -169,6 +169,15 @@ int envpic_field_step(envpic_sim* s);
 /* `nsteps` whole steps with the fused kernels (deposits inside the pushes). */
 int envpic_step_n(envpic_sim* s, int nsteps);
 
+/* Graph mode of envpic_step_n: with steps = k > 0, envpic_step_n captures
+ * its kernels from the simulation's stream in chunks of up to k steps, one
+ * HIP graph per chunk (each captured, instantiated and launched once: a
+ * step's kernel arguments depend on the step), which replaces the per-kernel
+ * launches of a chunk by one graph launch; 0 (the default) launches every
+ * kernel directly.  Results are those of direct launches.  Ignored while
+ * stage timing is on.  ENVPIC_EINVAL for k < 0. */
+int envpic_set_graph(envpic_sim* s, int steps);
+
 /* Advance `count` resident simulations by `nsteps` each, interleaving their
  * stages on `hip_stream` so that their kernels overlap on the device.  Each
  * simulation keeps its own state; results equal envpic_step_n's within the

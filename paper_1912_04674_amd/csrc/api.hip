@@ -286,7 +286,63 @@ struct envpic_sim {
     ticks.clear();
     return ENVPIC_OK;
   }
+  // graph mode: envpic_step_n records chunks of graph_steps steps into one
+  // HIP graph each and launches it on the simulation's stream; an executable
+  // graph is destroyed once the event recorded after its launch has
+  // completed.  The kernels are recorded from a private stream (the
+  // simulation's stream may be the null stream, which cannot be captured).
+  int graph_steps = 0;
+  std::vector<std::pair<hipGraphExec_t, hipEvent_t>> graphs;
+  hipStream_t cap_stream = nullptr;
+
+  void reap_graphs(bool wait) {
+    for (size_t k = 0; k < graphs.size();) {
+      if (wait) (void)hipEventSynchronize(graphs[k].second);
+      if (wait || hipEventQuery(graphs[k].second) == hipSuccess) {
+        (void)hipGraphExecDestroy(graphs[k].first);
+        (void)hipEventDestroy(graphs[k].second);
+        graphs.erase(graphs.begin() + (long)k);
+      } else {
+        ++k;
+      }
+    }
+  }
+  int step_graph(int k) {
+    reap_graphs(false);
+    int rc = ENVPIC_OK;
+    if (!cap_stream && (rc = hip_check(hipStreamCreateWithFlags(&cap_stream, hipStreamNonBlocking), "capture stream")))
+      return rc;
+    if ((rc = hip_check(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal), "begin capture"))) return rc;
+    hipStream_t own = stream;
+    stream = cap_stream;  // the stages issue their kernels on `stream`
+    for (int i = 0; i < k && !rc; ++i) rc = step();
+    stream = own;
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cap_stream, &graph);
+    if (rc || ec != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc ? rc : hip_check(ec, "end capture");
+    }
+    hipGraphExec_t exec = nullptr;
+    rc = hip_check(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0), "graph instantiate");
+    (void)hipGraphDestroy(graph);
+    if (rc) return rc;
+    hipEvent_t done = nullptr;
+    if ((rc = hip_check(hipGraphLaunch(exec, stream), "graph launch")) ||
+        (rc = hip_check(hipEventCreateWithFlags(&done, hipEventDisableTiming), "graph event")) ||
+        (rc = hip_check(hipEventRecord(done, stream), "graph event record"))) {
+      (void)hipStreamSynchronize(stream);
+      (void)hipGraphExecDestroy(exec);
+      if (done) (void)hipEventDestroy(done);
+      return rc;
+    }
+    graphs.emplace_back(exec, done);
+    return ENVPIC_OK;
+  }
+
   virtual ~envpic_sim() {
+    reap_graphs(true);
+    if (cap_stream) (void)hipStreamDestroy(cap_stream);
     if (!ticks.empty()) (void)hipEventSynchronize(ticks.back().b);
     for (const Tick& t : ticks) {
       (void)hipEventDestroy(t.a);
@@ -961,6 +1017,15 @@ int envpic_field_step(envpic_sim* s) { return s ? s->field() : fail(ENVPIC_EINVA
 int envpic_step_n(envpic_sim* s, int nsteps) {
   if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
   if (s->stage != 0) return fail(ENVPIC_EORDER, "step_n called in the middle of a step");
+  if (s->graph_steps > 0 && s->timing == 0) {
+    for (int done = 0; done < nsteps;) {
+      const int k = std::min(s->graph_steps, nsteps - done);
+      int rc = s->step_graph(k);
+      if (rc) return rc;
+      done += k;
+    }
+    return ENVPIC_OK;
+  }
   for (int k = 0; k < nsteps; ++k) {
     int rc = s->step();
     if (rc) return rc;
@@ -1045,6 +1110,13 @@ int envpic_set_timing(envpic_sim* s, int enable) {
     s->t_n[k] = 0;
   }
   s->timing = enable > 0 ? enable : 0;
+  return ENVPIC_OK;
+}
+
+int envpic_set_graph(envpic_sim* s, int steps) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  if (steps < 0) return fail(ENVPIC_EINVAL, "negative graph length");
+  s->graph_steps = steps;
   return ENVPIC_OK;
 }
 

@@ -167,6 +167,76 @@ template <class R, bool M1> struct MwShared {
   C ex1[M1 ? HN : 1], er1[M1 ? HN : 1], et1[M1 ? HN : 1];
 };
 
+// B^{n+1/2} of one node
+template <class R, bool M1> struct MwB {
+  using C = typename cplx_of<R>::type;
+  R bt;
+  C bx1, br1, bt1;
+};
+
+// One owned node (i, j) of a Maxwell tile, LDS index k (E^{n+1} of the tile
+// and its +1 column / row in sm), grid offset o, B^{n+1/2} in bo: the new E
+// stored, B^{n+3/2} and Bbar^{n+1}, the next deposits cleared.
+template <class R, bool M1>
+__device__ inline void tile_node(const Geo& g, const Grids<R>& f, const DepositBufs<R>& dnext, int i, int j, int k,
+                                 size_t o, const MwB<R, M1>& bo, bool left_edge_zero, const MwShared<R, M1>& sm) {
+  using C = typename cplx_of<R>::type;
+  constexpr int HJ = MwShared<R, M1>::HJ;
+  const int kp = k + HJ;  // (i+1, j); k + 1 is (i, j+1)
+  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  const bool ez = left_edge_zero && i == 1;
+  // the new E of the owned node
+  if (j <= g.nr - 1) f.er_n[o] = ez ? (R)0 : sm.er[k];
+  if (i <= g.nx - 1) f.ex_n[o] = sm.ex[k];
+  if (M1) {
+    const C z = mk<C>((R)0, (R)0);
+    if (i <= g.nx - 1) f.ex1_n[o] = sm.ex1[k];
+    if (j <= g.nr - 1) f.er1_n[o] = ez ? z : sm.er1[k];
+    f.et1_n[o] = ez ? z : sm.et1[k];
+  }
+  // ---- B^{n+3/2} and Bbar^{n+1}
+  if (i <= g.nx - 1 && j <= g.nr - 1) {
+    const R b0 = bo.bt;
+    const R b1 = b0 + dt * ((sm.ex[k + 1] - sm.ex[k]) * idr - (sm.er[kp] - sm.er[k]) * idx_);
+    f.bt_n[o] = b1;
+    f.btb[o] = (R)0.5 * (b0 + b1);
+  }
+  if (M1) {
+    if (j <= g.nr - 1) {
+      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+      const C b0 = bo.bx1;
+      const C curl = cadd(cscale(csub(cscale(sm.et1[k + 1], (R)(j + 1)), cscale(sm.et1[k], (R)j)), irh),
+                          cscale(cmuli(sm.er1[k]), irh));
+      const C b1 = csub(b0, cscale(curl, dt));
+      f.bx1_n[o] = b1;
+      f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
+    }
+    if (i <= g.nx - 1) {
+      const C exr = j == 0 ? cscale(sm.ex1[k + 1], idr) : cscale(sm.ex1[k], (R)(1.0 / (j * g.dr)));
+      const C b0 = bo.br1;
+      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(sm.et1[kp], sm.et1[k]), idx_)), dt));
+      f.br1_n[o] = b1;
+      f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
+      if (j <= g.nr - 1) {
+        const C c0 = bo.bt1;
+        const C c1 = cadd(c0, cscale(csub(cscale(csub(sm.ex1[k + 1], sm.ex1[k]), idr),
+                                          cscale(csub(sm.er1[kp], sm.er1[k]), idx_)), dt));
+        f.bt1_n[o] = c1;
+        f.btb1[o] = cscale(cadd(c0, c1), (R)0.5);
+      }
+    }
+  }
+  dnext.chi[o] = 0;
+  dnext.jx[o] = 0;
+  dnext.jr[o] = 0;
+  if (M1) {
+    const C z = mk<C>((R)0, (R)0);
+    dnext.jx1[o] = z;
+    dnext.jr1[o] = z;
+    dnext.jt1[o] = z;
+  }
+}
+
 // The Maxwell tile (i0, j0): E^{n+1} on the tile and its +1 column / +1 row
 // into LDS, then the owned nodes' E^{n+1}, B^{n+3/2}, Bbar^{n+1} and the
 // cleared next deposits.  left_edge_zero: the window moves after this step
@@ -213,67 +283,28 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
   const bool own = i <= g.nx && j <= g.nr;
   const size_t o = (size_t)phys_col(g, own ? i : 0) * g.pitch + (own ? j : 0);
   // B^{n+1/2} of the owned node, loaded before the barrier
-  const R bt0 = f.bt[o];
-  C bx0{}, br0{}, btc0{};
+  MwB<R, M1> bo;
+  bo.bt = f.bt[o];
   if (M1) {
-    bx0 = f.bx1[o];
-    br0 = f.br1[o];
-    btc0 = f.bt1[o];
+    bo.bx1 = f.bx1[o];
+    bo.br1 = f.br1[o];
+    bo.bt1 = f.bt1[o];
   }
   __syncthreads();
-  if (!own) return;
-  const int k = a * HJ + b, kp = k + HJ;  // (i, j), (i+1, j)
-  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
-  const bool ez = left_edge_zero && i == 1;
-  // the new E of the owned node
-  if (j <= g.nr - 1) f.er_n[o] = ez ? (R)0 : sm.er[k];
-  if (i <= g.nx - 1) f.ex_n[o] = sm.ex[k];
-  if (M1) {
-    const C z = mk<C>((R)0, (R)0);
-    if (i <= g.nx - 1) f.ex1_n[o] = sm.ex1[k];
-    if (j <= g.nr - 1) f.er1_n[o] = ez ? z : sm.er1[k];
-    f.et1_n[o] = ez ? z : sm.et1[k];
-  }
-  // ---- B^{n+3/2} and Bbar^{n+1}
-  if (i <= g.nx - 1 && j <= g.nr - 1) {
-    const R b0 = bt0;
-    const R b1 = b0 + dt * ((sm.ex[k + 1] - sm.ex[k]) * idr - (sm.er[kp] - sm.er[k]) * idx_);
-    f.bt_n[o] = b1;
-    f.btb[o] = (R)0.5 * (b0 + b1);
-  }
-  if (M1) {
-    if (j <= g.nr - 1) {
-      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
-      const C b0 = bx0;
-      const C curl = cadd(cscale(csub(cscale(sm.et1[k + 1], (R)(j + 1)), cscale(sm.et1[k], (R)j)), irh),
-                          cscale(cmuli(sm.er1[k]), irh));
-      const C b1 = csub(b0, cscale(curl, dt));
-      f.bx1_n[o] = b1;
-      f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
+  if (own) tile_node<R, M1>(g, f, dnext, i, j, a * HJ + b, o, bo, left_edge_zero, sm);
+  // the last row tile of a grid with nr a multiple of the tile height also
+  // owns row nr (its +1 halo row): one more node for the first MW_TI threads
+  if (j0 + MW_TJ == g.nr && threadIdx.x < MW_TI && i0 + (int)threadIdx.x <= g.nx) {
+    const int ie = i0 + threadIdx.x;
+    const size_t oe = (size_t)phys_col(g, ie) * g.pitch + g.nr;
+    MwB<R, M1> be;
+    be.bt = f.bt[oe];
+    if (M1) {
+      be.bx1 = f.bx1[oe];
+      be.br1 = f.br1[oe];
+      be.bt1 = f.bt1[oe];
     }
-    if (i <= g.nx - 1) {
-      const C exr = j == 0 ? cscale(sm.ex1[k + 1], idr) : cscale(sm.ex1[k], (R)(1.0 / (j * g.dr)));
-      const C b0 = br0;
-      const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(sm.et1[kp], sm.et1[k]), idx_)), dt));
-      f.br1_n[o] = b1;
-      f.brb1[o] = cscale(cadd(b0, b1), (R)0.5);
-      if (j <= g.nr - 1) {
-        const C c0 = btc0;
-        const C c1 = cadd(c0, cscale(csub(cscale(csub(sm.ex1[k + 1], sm.ex1[k]), idr),
-                                          cscale(csub(sm.er1[kp], sm.er1[k]), idx_)), dt));
-        f.bt1_n[o] = c1;
-        f.btb1[o] = cscale(cadd(c0, c1), (R)0.5);
-      }
-    }
-  }
-  dnext.chi[o] = 0;
-  dnext.jx[o] = 0;
-  dnext.jr[o] = 0;
-  if (M1) {
-    const C z = mk<C>((R)0, (R)0);
-    dnext.jx1[o] = z;
-    dnext.jr1[o] = z;
-    dnext.jt1[o] = z;
+    tile_node<R, M1>(g, f, dnext, ie, g.nr, (int)threadIdx.x * HJ + MW_TJ, oe, be, left_edge_zero, sm);
   }
 }
 
@@ -415,7 +446,9 @@ void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_row
 template <class R>
 void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
                   const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st) {
-  fa.nbx_mw = (g.nr + 1 + MW_TJ - 1) / MW_TJ;
+  // row tiles: rows 0..nr; when nr is a multiple of the tile height, the
+  // last tile owns row nr as well (its halo row)
+  fa.nbx_mw = g.nr % MW_TJ == 0 ? g.nr / MW_TJ : (g.nr + 1 + MW_TJ - 1) / MW_TJ;
   fa.nb_mw = fa.nbx_mw * ((g.nx + 1 + MW_TI - 1) / MW_TI);
   fa.nb_win = fa.shifting ? (g.nr + 1 + MW_T - 1) / MW_T : 0;
   const int nb_cs = fa.presort ? (g.ntiles + 1) / 2 : 0;

@@ -62,7 +62,7 @@ EXPORTS = [
     "envpic_batch_step", "envpic_get_field", "envpic_set_field", "envpic_state",
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
-    "envpic_set_timing", "envpic_get_timing",
+    "envpic_set_timing", "envpic_get_timing", "envpic_set_graph",
 ]
 
 
@@ -95,6 +95,7 @@ def lib():
     L.envpic_set_particles.argtypes = [vp, ctypes.c_int64] + [dp] * 7 + [up]
     L.envpic_diagnostics.argtypes = [vp, dp]
     L.envpic_set_timing.argtypes = [vp, ctypes.c_int]
+    L.envpic_set_graph.argtypes = [vp, ctypes.c_int]
     L.envpic_get_timing.argtypes = [vp, dp, i64p]
     L.envpic_save.argtypes = [vp, vp, ctypes.POINTER(ctypes.c_size_t)]
     L.envpic_load.argtypes = [vp, vp, ctypes.c_size_t]
@@ -251,6 +252,10 @@ class Sim:
         ids = np.ascontiguousarray(parts["id"], dtype=np.uint32)
         _check(lib().envpic_set_particles(self._h, n, *(_dptr(a) for a in arrs),
                                           ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+
+    def set_graph(self, steps):
+        """step() issues chunks of up to `steps` steps as one HIP graph each (0: off)."""
+        _check(lib().envpic_set_graph(self._h, int(steps)))
 
     def set_timing(self, enable=True, every=1):
         """Record stage events on every `every`-th step (off if not enable)."""

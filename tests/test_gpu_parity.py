@@ -235,6 +235,26 @@ def test_ragged_grid_parity(E, oracle_mod, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+ROWS64 = dict(name="rows64", nx=120, nr=64, dx=0.8, dr=1.5, dt=0.6, n_modes=2, ppc=(2, 2, 2),
+              profile="ramp", n0=0.003, ramp_len=30.0, a0=2.0, w0=25.0, tau=12.0,
+              x_c=120 * 0.8 - 30.0, x_f=120 * 0.8 - 30.0, moving_window=1, seed=191204678)
+
+
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_rows_multiple_of_64_parity(E, oracle_mod, prec, tf, tp):
+    """nr a multiple of the field update's 64-row tile (the outermost row
+    nr is then updated by the last tile as its extra row), window and modes
+    0-1."""
+    say("nr = 64", prec)
+    g = E.Sim(ROWS64, _prec(E, prec))
+    r = oracle_mod.OracleSim(ROWS64)
+    g.step(50)
+    r.step(50)
+    assert g.state() == r.state()
+    compare_fields(g, r, tf, modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_vacuum_run_has_no_particles(E, oracle_mod, prec):
     """No plasma: zero particles through every stage; the envelope and the
@@ -414,6 +434,32 @@ def test_batch_equals_alone(E):
         alone.step(30)
         compare_fields(m, alone, 1e-4, names=("env", "ex", "er", "bt"))
         compare_particles(m.get_particles(), alone.get_particles(), 1e-3, 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_graph_mode_matches_direct_launches(E, prec):
+    """step_n in graph mode (chunks of up to 7 steps captured into HIP graphs
+    and launched once each) against direct launches, checked after each of
+    several calls, with eager work and synchronisation between them; the
+    window, injection and sorts run inside the captured chunks."""
+    say("graph mode", prec)
+    P = _prec(E, prec)
+    a = E.Sim(C2_SMALL, P)
+    b = E.Sim(C2_SMALL, P)
+    a.set_graph(7)
+    tol_f, tol_p = (1e-10, 1e-10) if prec == "fp64" else (1e-4, 1e-3)
+    for n in (10, 7, 13):
+        a.step(n)
+        b.step(n)
+        assert a.state() == b.state()
+        compare_fields(a, b, tol_f, names=("env", "chi", "ex", "er", "bt"), modes=2)
+        da, db = a.diagnostics(), b.diagnostics()  # eager work between the graphs
+        assert da["count"] == db["count"]
+    compare_particles(a.get_particles(), b.get_particles(), tol_p, 1e-8 if prec == "fp64" else 1e-3)
+    a.set_graph(0)
+    a.step(3)
+    b.step(3)
+    compare_fields(a, b, tol_f, names=("env", "ex"), modes=1)
 
 
 # ------------------------------------------------ full-size sampled check --
