@@ -292,20 +292,6 @@ __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const Depos
   }
   __syncthreads();
   if (own) tile_node<R, M1>(g, f, dnext, i, j, a * HJ + b, o, bo, left_edge_zero, sm);
-  // the last row tile of a grid with nr a multiple of the tile height also
-  // owns row nr (its +1 halo row): one more node for the first MW_TI threads
-  if (j0 + MW_TJ == g.nr && threadIdx.x < MW_TI && i0 + (int)threadIdx.x <= g.nx) {
-    const int ie = i0 + threadIdx.x;
-    const size_t oe = (size_t)phys_col(g, ie) * g.pitch + g.nr;
-    MwB<R, M1> be;
-    be.bt = f.bt[oe];
-    if (M1) {
-      be.bx1 = f.bx1[oe];
-      be.br1 = f.br1[oe];
-      be.bt1 = f.bt1[oe];
-    }
-    tile_node<R, M1>(g, f, dnext, ie, g.nr, (int)threadIdx.x * HJ + MW_TJ, oe, be, left_edge_zero, sm);
-  }
 }
 
 // ----------------------------------------------------- window shift --
@@ -446,9 +432,7 @@ void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_row
 template <class R>
 void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
                   const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st) {
-  // row tiles: rows 0..nr; when nr is a multiple of the tile height, the
-  // last tile owns row nr as well (its halo row)
-  fa.nbx_mw = g.nr % MW_TJ == 0 ? g.nr / MW_TJ : (g.nr + 1 + MW_TJ - 1) / MW_TJ;
+  fa.nbx_mw = (g.nr + 1 + MW_TJ - 1) / MW_TJ;
   fa.nb_mw = fa.nbx_mw * ((g.nx + 1 + MW_TI - 1) / MW_TI);
   fa.nb_win = fa.shifting ? (g.nr + 1 + MW_T - 1) / MW_T : 0;
   const int nb_cs = fa.presort ? (g.ntiles + 1) / 2 : 0;

@@ -88,9 +88,14 @@ class Job:
 
 class GpuBackend:
     """Jobs as libenvpic simulations inside one pre-allocated device arena,
-    each on a pooled HIP stream (default priority)."""
+    each on a pooled HIP stream (default priority).
 
-    def __init__(self, budget_bytes, precision=0, lineout=True, full=False):
+    With `graph_min_jobs` or more jobs resident, a job's chunk of steps is
+    issued as one HIP graph (envpic_set_graph): issuing small jobs' kernels
+    one by one then keeps the host busier than the device.  With fewer jobs
+    the kernels are launched directly, which runs a lone job faster."""
+
+    def __init__(self, budget_bytes, precision=0, lineout=True, full=False, graph_min_jobs=4):
         import torch
         from . import envpic as E
         self.E, self.torch = E, torch
@@ -99,7 +104,9 @@ class GpuBackend:
         self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
         self.budget = int(budget_bytes)
         self.lineout, self.full = lineout, full
+        self.graph_min_jobs = graph_min_jobs
         self._streams = []
+        self._live = 0
 
     def footprint(self, cfg):
         return self.E.footprint(cfg, self.precision)
@@ -109,10 +116,15 @@ class GpuBackend:
         st = self._streams.pop() if self._streams else torch.cuda.Stream()
         view = self.arena[offset:offset + job.footprint]
         sim = self.E.Sim(job.cfg, self.precision, arena=view, stream=st)
-        return {"sim": sim, "stream": st, "view": view}
+        self._live += 1
+        return {"sim": sim, "stream": st, "view": view, "graph": 0}
 
     def issue(self, h, k):
         """Queue k steps on the job's stream; returns a completion token."""
+        g = k if self.graph_min_jobs and self._live >= self.graph_min_jobs else 0
+        if g != h["graph"]:
+            h["sim"].set_graph(g)
+            h["graph"] = g
         h["sim"].step(k)
         ev = self.torch.cuda.Event()
         ev.record(h["stream"])
@@ -134,6 +146,7 @@ class GpuBackend:
     def release(self, h):
         h["stream"].synchronize()
         h["sim"].close()
+        self._live -= 1
         self._streams.append(h["stream"])
 
 

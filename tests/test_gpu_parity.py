@@ -242,9 +242,8 @@ ROWS64 = dict(name="rows64", nx=120, nr=64, dx=0.8, dr=1.5, dt=0.6, n_modes=2, p
 
 @pytest.mark.parametrize("prec,tf,tp", PRECS)
 def test_rows_multiple_of_64_parity(E, oracle_mod, prec, tf, tp):
-    """nr a multiple of the field update's 64-row tile (the outermost row
-    nr is then updated by the last tile as its extra row), window and modes
-    0-1."""
+    """nr a multiple of the field update's 64-row tile (row nr alone in the
+    last row tile), window and modes 0-1."""
     say("nr = 64", prec)
     g = E.Sim(ROWS64, _prec(E, prec))
     r = oracle_mod.OracleSim(ROWS64)
