@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define ENVPIC_PARAMS_VERSION 1
+#define ENVPIC_PARAMS_VERSION 2
 
 enum envpic_status {
   ENVPIC_OK = 0,
@@ -89,7 +89,11 @@ typedef struct envpic_params {
   double a0, w0, tau, x_c, x_f;
   double n0, ramp_len, perturb, bump_x, bump_w;
   int64_t capacity;        /* particle slots per buffer (0: derived) */
+  int32_t filter_passes;   /* passes of the 1-2-1 binomial filter on J (0: none, at most
+                              ENVPIC_FILTER_MAX); each pass smooths along x, then r */
+  int32_t reserved;        /* 0 */
 } envpic_params;
+#define ENVPIC_FILTER_MAX 8
 
 /* grid identifiers for envpic_get_field / envpic_set_field */
 enum envpic_field {

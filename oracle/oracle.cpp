@@ -35,6 +35,11 @@
  *   R17 loading regular in x and r, one random angle per cell, equally spaced
  *       angles inside the cell, weights proportional to r
  *   R21 Bbar^n = (B^{n-1/2} + B^{n+1/2}) / 2
+ *   R24 optional binomial current filter (Sec. 4, nonlinear benchmark: an
+ *       uncompensated binomial filter of 7 passes): N passes of 1-2-1 in
+ *       index space, each along x then along r, on J^{n+1/2} of both modes
+ *       before the field update; zero current outside the window and beyond
+ *       r_max, ghost rows below the axis by the component's parity (R23)
  */
 #include "oracle.h"
 
@@ -498,6 +503,45 @@ void position_J(Sim& s) {
   s.id.resize(m);
 }
 
+/* --------------------------------------- binomial current filter (R24) --
+ * One pass on a component f valid for 0 <= i <= imax, 0 <= j <= jmax:
+ * f <- (f_{i-1} + 2 f_i + f_{i+1})/4 along x, then the same along r.  Zero
+ * beyond the valid ranges; the row below the axis is the mirror of row 1
+ * (primal in r: J(-1) = parity J(1)) or of row 0 (half-integer in r:
+ * J(-1/2) = parity J(1/2)).                                                */
+template <class T>
+void binomial_pass(const Sim& s, std::vector<T>& f, int imax, int jmax, bool half_r, double parity) {
+  std::vector<T> g(f.size(), T(0));
+  for (int i = 0; i <= imax; ++i)
+    for (int j = 0; j <= jmax; ++j) {
+      const T lo = i > 0 ? f[s.at(i - 1, j)] : T(0);
+      const T hi = i < imax ? f[s.at(i + 1, j)] : T(0);
+      g[s.at(i, j)] = 0.25 * lo + 0.5 * f[s.at(i, j)] + 0.25 * hi;
+    }
+  for (int i = 0; i <= imax; ++i)
+    for (int j = 0; j <= jmax; ++j) {
+      const T lo = j > 0 ? g[s.at(i, j - 1)] : parity * g[s.at(i, half_r ? 0 : std::min(1, jmax))];
+      const T hi = j < jmax ? g[s.at(i, j + 1)] : T(0);
+      f[s.at(i, j)] = 0.25 * lo + 0.5 * g[s.at(i, j)] + 0.25 * hi;
+    }
+}
+
+/* R24 on J^{n+1/2}: mode 0 J_x (axial, even; i+1/2, j) and J_r (radial,
+ * odd; i, j+1/2); mode 1 J_x (axial, odd), J_r (radial, even; i, j+1/2)
+ * and J_t (azimuthal, even; i, j).                                        */
+void filter_J(Sim& s) {
+  const int Nx = s.Nx, Nr = s.Nr;
+  for (int k = 0; k < s.p.filter_passes; ++k) {
+    binomial_pass(s, s.Jx, Nx - 1, Nr, false, +1.0);
+    binomial_pass(s, s.Jr, Nx, Nr - 1, true, -1.0);
+    if (s.m1()) {
+      binomial_pass(s, s.Jx1, Nx - 1, Nr, false, -1.0);
+      binomial_pass(s, s.Jr1, Nx, Nr - 1, true, +1.0);
+      binomial_pass(s, s.Jt1, Nx, Nr, false, +1.0);
+    }
+  }
+}
+
 /* ---------------------------------------------- Maxwell (Sec. 2, 3) --
  * Yee leap-frog of Eq. MaxwellEqsCylindrical with dt/2 staggering:
  * E^{n+1} from B^{n+1/2} and J^{n+1/2}, then B^{n+3/2} from E^{n+1};
@@ -675,6 +719,7 @@ bool check_params(const oracle_params* p) {
   /* one cell at most per step along each axis (the current deposit needs it) */
   if (!(p->dt < p->dx && p->dt < p->dr)) return false;
   if (p->start_col < 0) return false;
+  if (p->filter_passes < 0 || p->filter_passes > 64) return false;
   return true;
 }
 
@@ -725,9 +770,14 @@ int oracle_position_J(void* h) {
 }
 int oracle_field_step(void* h) {
   Sim& s = *as_sim(h);
+  if (s.p.filter_passes > 0) filter_J(s);
   maxwell(s);
   window(s);
   s.n += 1;
+  return ORACLE_OK;
+}
+int oracle_filter_J(void* h) {
+  filter_J(*as_sim(h));
   return ORACLE_OK;
 }
 int oracle_step(void* h, int nsteps) {

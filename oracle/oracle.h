@@ -44,6 +44,10 @@
  *                          of one particle.  Beyond these the mode-1 fields
  *                          and currents are PARITY UNPINNED (derived
  *                          equations only, no closed form for a general state).
+ *   binomial J filter      transfer factor cos^2(k/2)^N of an interior
+ *   (R24)                  Fourier mode; linear and constant radial profiles
+ *                          of each parity preserved through the axis ghost;
+ *                          one pass at the x ends and at r_max (3/4)
  *   step order, gbar and   documented choices with no value printed in the
  *   Phi centring (R6-R8)   paper: PARITY UNPINNED beyond the convergence
  *                          order the luminal test fixes.
@@ -58,7 +62,7 @@
 extern "C" {
 #endif
 
-#define ORACLE_PARAMS_VERSION 1
+#define ORACLE_PARAMS_VERSION 2
 
 enum {
   ORACLE_OK = 0,
@@ -90,6 +94,8 @@ typedef struct oracle_params {
   double n0, ramp_len, perturb, bump_x, bump_w;
   int64_t start_col;     /* lab column of the window's left edge at n = 0 (a slab
                             of a larger run: same positions, angles and ids) */
+  int32_t filter_passes; /* passes of the 1-2-1 binomial filter on J (0: none) */
+  int32_t reserved;
 } oracle_params;
 
 /* grid identifiers (window-relative (nx+1) x (nr+1) arrays) */
@@ -139,7 +145,8 @@ void oracle_destroy(void* sim);
 int oracle_momentum_chi(void* sim); /* p^{n-1/2} -> p^{n+1/2}, deposit chi^n      */
 int oracle_envelope(void* sim);     /* A^{n+1} from A^n, A^{n-1}, chi^n           */
 int oracle_position_J(void* sim);   /* x^n -> x^{n+1}, deposit J^{n+1/2}         */
-int oracle_field_step(void* sim);   /* E^{n+1}, B^{n+3/2}, Bbar^{n+1}, window; n+1 */
+int oracle_field_step(void* sim);   /* [filter J], E^{n+1}, B^{n+3/2}, Bbar^{n+1}, window; n+1 */
+int oracle_filter_J(void* sim);     /* the binomial passes of R24 alone (filter_passes of them) */
 int oracle_step(void* sim, int nsteps);
 
 int oracle_state(void* sim, int64_t* n, int64_t* shift, int64_t* n_particles);

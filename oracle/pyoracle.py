@@ -14,7 +14,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 
-PARAMS_VERSION = 1
+PARAMS_VERSION = 2
 
 PROFILES = {"none": 0, "uniform": 1, "ramp": 2, "perturb": 3, "bump": 4}
 
@@ -46,6 +46,7 @@ class OracleParams(ctypes.Structure):
         ("perturb", ctypes.c_double), ("bump_x", ctypes.c_double),
         ("bump_w", ctypes.c_double),
         ("start_col", ctypes.c_int64),
+        ("filter_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -76,7 +77,7 @@ def lib():
         L.oracle_destroy.argtypes = [vp]
         L.oracle_destroy.restype = None
         for name in ("oracle_momentum_chi", "oracle_envelope", "oracle_position_J",
-                     "oracle_field_step"):
+                     "oracle_field_step", "oracle_filter_J"):
             getattr(L, name).argtypes = [vp]
         L.oracle_step.argtypes = [vp, ctypes.c_int]
         L.oracle_state.argtypes = [vp, i64p, i64p, i64p]
@@ -119,6 +120,7 @@ def make_params(cfg):
     p.bump_x = float(cfg.get("bump_x", 0.0))
     p.bump_w = float(cfg.get("bump_w", 1.0))
     p.start_col = int(cfg.get("start_col", 0))
+    p.filter_passes = int(cfg.get("filter_passes", 0))
     return p
 
 
@@ -158,6 +160,9 @@ class OracleSim:
 
     def field_step(self):
         lib().oracle_field_step(self._h)
+
+    def filter_J(self):
+        lib().oracle_filter_J(self._h)
 
     def step(self, n=1):
         lib().oracle_step(self._h, int(n))

@@ -52,6 +52,7 @@ class Params(ctypes.Structure):
         ("n0", ctypes.c_double), ("ramp_len", ctypes.c_double), ("perturb", ctypes.c_double),
         ("bump_x", ctypes.c_double), ("bump_w", ctypes.c_double),
         ("capacity", ctypes.c_int64),
+        ("filter_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -142,6 +143,7 @@ def make_params(cfg):
     p.bump_x = float(cfg.get("bump_x", 0.0))
     p.bump_w = float(cfg.get("bump_w", 1.0))
     p.capacity = int(cfg.get("capacity", 0))
+    p.filter_passes = int(cfg.get("filter_passes", 0))
     return p
 
 
