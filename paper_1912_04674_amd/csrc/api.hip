@@ -117,6 +117,7 @@ template <class R> struct State {
   Parts<R> parts[2], scr;
   Grids<R> grids;
   DepositBufs<R> dep[2];
+  DepositBufs<R> jf;  // filtered currents (chi unused) when the binomial filter is on
   Layout lay[2];
   int* hist;    // particles per tile at the next sort
   int* ccount;  // particles per cell at the next sort ([phys col][row], as the grids)
@@ -188,6 +189,16 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
     d.jr1 = cv.take<C>(n1);
     d.jt1 = cv.take<C>(n1);
   }
+  {
+    const bool filt = p.filter_passes > 0;
+    DepositBufs<R>& d = S.jf;
+    d.chi = nullptr;
+    d.jx = cv.take<R>(filt ? ng : 0);
+    d.jr = cv.take<R>(filt ? ng : 0);
+    d.jx1 = cv.take<C>(filt ? n1 : 0);
+    d.jr1 = cv.take<C>(filt ? n1 : 0);
+    d.jt1 = cv.take<C>(filt ? n1 : 0);
+  }
   f.chi = nullptr;
   f.jx = nullptr;
   f.jr = nullptr;
@@ -235,6 +246,7 @@ struct envpic_sim {
   int64_t n_sorts = 0;    // sorts so far (selects tile or cell order)
   bool deferred = false, deposit_done = true;
   int chi_last = 0;  // deposit buffer of the last momentum stage
+  bool jf_valid = false;  // the filtered copy holds the current of the last field stage
   // stage timing (events on the simulation's stream)
   struct Tick {
     int stage;
@@ -594,6 +606,7 @@ template <class R> struct SimT : envpic_sim {
 
   int position(bool defer) override {
     if (stage != 2) return fail(ENVPIC_EORDER, "position stage out of order");
+    jf_valid = false;
     const Geo g = geo();
     const bool shifting = shift_due();
     // the plasma of the column entering the window at this step's shift is
@@ -639,7 +652,18 @@ template <class R> struct SimT : envpic_sim {
     fa.bump_fill = S.lay[cur].fill;
     fa.pending = S.pending;
     fa.err = S.err;
-    launch_field<R>(g, S.grids, S.dep[n & 1], S.dep[(n + 1) & 1], S.dep[0], S.dep[1], fa, stream);
+    DepositBufs<R> din = S.dep[n & 1];
+    if (p.filter_passes > 0) {
+      // the field update reads the filtered current
+      launch_filter<R>(g, din, S.jf, p.filter_passes, stream);
+      din.jx = S.jf.jx;
+      din.jr = S.jf.jr;
+      din.jx1 = S.jf.jx1;
+      din.jr1 = S.jf.jr1;
+      din.jt1 = S.jf.jt1;
+      jf_valid = true;
+    }
+    launch_field<R>(g, S.grids, din, S.dep[(n + 1) & 1], S.dep[0], S.dep[1], fa, stream);
     {
       Grids<R>& G = S.grids;  // the new E, B become the current ones
       std::swap(G.ex, G.ex_n);
@@ -675,8 +699,8 @@ template <class R> struct SimT : envpic_sim {
       case ENVPIC_F_ER: r = {G.er, false, false, true}; return 0;
       case ENVPIC_F_BT: r = {G.bt, false, true, true}; return 0;
       case ENVPIC_F_BT_BAR: r = {G.btb, false, true, true}; return 0;
-      case ENVPIC_F_JX: r = {S.dep[chi_last].jx, false, true, false}; return 0;
-      case ENVPIC_F_JR: r = {S.dep[chi_last].jr, false, false, true}; return 0;
+      case ENVPIC_F_JX: r = {(jf_valid ? S.jf : S.dep[chi_last]).jx, false, true, false}; return 0;
+      case ENVPIC_F_JR: r = {(jf_valid ? S.jf : S.dep[chi_last]).jr, false, false, true}; return 0;
       default: break;
     }
     if (!m1 || f < ENVPIC_F_EX1 || f >= ENVPIC_NFIELDS) return fail(ENVPIC_EINVAL, "unknown field (or mode 1 not enabled)");
@@ -690,9 +714,9 @@ template <class R> struct SimT : envpic_sim {
       case ENVPIC_F_BX1_BAR: r = {G.bxb1, true, false, true}; return 0;
       case ENVPIC_F_BR1_BAR: r = {G.brb1, true, true, false}; return 0;
       case ENVPIC_F_BT1_BAR: r = {G.btb1, true, true, true}; return 0;
-      case ENVPIC_F_JX1: r = {S.dep[chi_last].jx1, true, true, false}; return 0;
-      case ENVPIC_F_JR1: r = {S.dep[chi_last].jr1, true, false, true}; return 0;
-      case ENVPIC_F_JT1: r = {S.dep[chi_last].jt1, true, false, false}; return 0;
+      case ENVPIC_F_JX1: r = {(jf_valid ? S.jf : S.dep[chi_last]).jx1, true, true, false}; return 0;
+      case ENVPIC_F_JR1: r = {(jf_valid ? S.jf : S.dep[chi_last]).jr1, true, false, true}; return 0;
+      case ENVPIC_F_JT1: r = {(jf_valid ? S.jf : S.dep[chi_last]).jt1, true, false, false}; return 0;
     }
     return fail(ENVPIC_EINVAL, "unknown field");
   }
@@ -1219,6 +1243,7 @@ int envpic_load(envpic_sim* s, const void* blob, size_t bytes) {
   s->n = h.n;
   s->shift = h.shift;
   s->chi_last = (int)((h.n + 1) & 1);
+  s->jf_valid = false;
   int rc;
   if ((rc = s->clear_deposits())) return rc;
   for (int k = 0; k < h.nfields; ++k) {

@@ -7,6 +7,7 @@
 // One thread per window node (i, j), radius fastest, so a wavefront reads a
 // contiguous run of one column; columns live in a ring indexed by lab column
 // mod nxa.  All kernels are bound by HBM bandwidth (a few flops per byte).
+#include "envpic.h"
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
@@ -444,6 +445,121 @@ void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, co
   if (fa.presort) hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(SCAN_T), 0, st, fa);
 }
 
+// ------------------------------------------------- binomial J filter --
+// The uncompensated binomial filter of the paper's nonlinear benchmark
+// (Sec. 4), read as N passes of 1-2-1 in index space, each along x then
+// along r, on J^{n+1/2} of both modes before the field update: zero current
+// outside the window and beyond r_max, rows below the axis mirrored with the
+// component's parity (axial components (-1)^m, radial and azimuthal
+// (-1)^{m+1}).  A work group owns a FT x FT tile and holds it with a halo of
+// ENVPIC_FILTER_MAX nodes in LDS (one node of halo is consumed per pass and
+// direction), runs every pass there and writes the owned nodes to the
+// filtered copy that the field update reads.
+constexpr int FT = 32;                // owned nodes per tile side
+constexpr int FH = ENVPIC_FILTER_MAX;  // halo
+constexpr int FR = FT + 2 * FH;        // LDS region side
+constexpr int FTH = 256;               // threads of a filter work group
+
+__device__ inline float lin3(float a, float b, float c) { return 0.25f * a + 0.5f * b + 0.25f * c; }
+__device__ inline double lin3(double a, double b, double c) { return 0.25 * a + 0.5 * b + 0.25 * c; }
+__device__ inline float2 lin3(float2 a, float2 b, float2 c) {
+  return make_float2(lin3(a.x, b.x, c.x), lin3(a.y, b.y, c.y));
+}
+__device__ inline double2 lin3(double2 a, double2 b, double2 c) {
+  return make_double2(lin3(a.x, b.x, c.x), lin3(a.y, b.y, c.y));
+}
+__device__ inline float vscale(float a, float s) { return a * s; }
+__device__ inline double vscale(double a, double s) { return a * s; }
+__device__ inline float2 vscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
+__device__ inline double2 vscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+
+// One component of the tile (i0, j0): valid for 0 <= i <= imax, 0 <= j <=
+// jmax; half_r: staggered by half a cell in r (the row below the axis
+// mirrors row 0, else row 1).  A, B: two LDS buffers of FR x FR values.
+template <class V, class R>
+__device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __restrict__ dst, int imax, int jmax,
+                                 bool half_r, R parity, int passes, int i0, int j0, V* A, V* B) {
+  const V zero = vscale(V{}, (R)0);
+  const bool ghosts = j0 - FH < 0;  // the tile touches the axis
+  // zero outside the valid ranges; rows below the axis from their mirrors
+  auto rules = [&](V* X) {
+    for (int k = threadIdx.x; k < FR * FR; k += FTH) {
+      const int a = k / FR, b = k - (k / FR) * FR;
+      const int i = i0 - FH + a, j = j0 - FH + b;
+      if (i < 0 || i > imax || j > jmax) X[k] = zero;
+    }
+    if (!ghosts) return;
+    __syncthreads();
+    for (int k = threadIdx.x; k < FR * FR; k += FTH) {
+      const int a = k / FR, b = k - (k / FR) * FR;
+      const int i = i0 - FH + a, j = j0 - FH + b;
+      if (j >= 0 || i < 0 || i > imax) continue;
+      const int jm = half_r ? -1 - j : -j;  // mirror row, 0 <= jm <= FH
+      X[k] = jm <= jmax ? vscale(X[a * FR + (jm - (j0 - FH))], parity) : zero;
+    }
+  };
+  for (int k = threadIdx.x; k < FR * FR; k += FTH) {
+    const int a = k / FR, b = k - (k / FR) * FR;
+    const int i = i0 - FH + a, j = j0 - FH + b;
+    A[k] = (i >= 0 && i <= imax && j >= 0 && j <= jmax) ? src[(size_t)phys_col(g, i) * g.pitch + j] : zero;
+  }
+  __syncthreads();
+  rules(A);
+  __syncthreads();
+  for (int p = 0; p < passes; ++p) {
+    for (int k = threadIdx.x; k < FR * FR; k += FTH) {  // along x (the outer ring only goes stale)
+      const int a = k / FR;
+      B[k] = (a == 0 || a == FR - 1) ? A[k] : lin3(A[k - FR], A[k], A[k + FR]);
+    }
+    __syncthreads();
+    rules(B);
+    __syncthreads();
+    for (int k = threadIdx.x; k < FR * FR; k += FTH) {  // along r
+      const int b = k - (k / FR) * FR;
+      A[k] = (b == 0 || b == FR - 1) ? B[k] : lin3(B[k - 1], B[k], B[k + 1]);
+    }
+    __syncthreads();
+    rules(A);
+    __syncthreads();
+  }
+  for (int k = threadIdx.x; k < FT * FT; k += FTH) {
+    const int a = k / FT, b = k - (k / FT) * FT;
+    const int i = i0 + a, j = j0 + b;
+    if (i > g.nx || j > g.nr) continue;
+    dst[(size_t)phys_col(g, i) * g.pitch + j] = (i <= imax && j <= jmax) ? A[(a + FH) * FR + b + FH] : zero;
+  }
+  __syncthreads();  // the buffers are reused by the next component
+}
+
+template <class R, bool M1>
+__global__ __launch_bounds__(FTH) void k_filter(Geo g, DepositBufs<R> din, DepositBufs<R> dout, int passes) {
+  using C = typename cplx_of<R>::type;
+  __shared__ C buf[2 * FR * FR];
+  const int ntr = (g.nr + 1 + FT - 1) / FT;
+  const int i0 = (blockIdx.x / ntr) * FT, j0 = (blockIdx.x % ntr) * FT;
+  R* ra = reinterpret_cast<R*>(buf);
+  R* rb = ra + FR * FR;
+  filter_component<R, R>(g, din.jx, dout.jx, g.nx - 1, g.nr, false, (R)1, passes, i0, j0, ra, rb);
+  filter_component<R, R>(g, din.jr, dout.jr, g.nx, g.nr - 1, true, (R)-1, passes, i0, j0, ra, rb);
+  if (M1) {
+    C* ca = buf;
+    C* cb = buf + FR * FR;
+    filter_component<C, R>(g, din.jx1, dout.jx1, g.nx - 1, g.nr, false, (R)-1, passes, i0, j0, ca, cb);
+    filter_component<C, R>(g, din.jr1, dout.jr1, g.nx, g.nr - 1, true, (R)1, passes, i0, j0, ca, cb);
+    filter_component<C, R>(g, din.jt1, dout.jt1, g.nx, g.nr, false, (R)1, passes, i0, j0, ca, cb);
+  }
+}
+
+template <class R>
+void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st) {
+  if (passes <= 0) return;
+  const int grid = ((g.nx + 1 + FT - 1) / FT) * ((g.nr + 1 + FT - 1) / FT);
+  if (g.modes >= 2)
+    hipLaunchKernelGGL((k_filter<R, true>), dim3(grid), dim3(FTH), 0, st, g, din, dout, passes);
+  else
+    hipLaunchKernelGGL((k_filter<R, false>), dim3(grid), dim3(FTH), 0, st, g, din, dout, passes);
+}
+
 template <class R>
 void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st) {
   hipLaunchKernelGGL((k_init_envelope<R>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, L, fp64_rows);
@@ -453,7 +569,8 @@ void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int f
   template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, hipStream_t);                \
   template void launch_field<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&,   \
                                 const DepositBufs<R>&, const DepositBufs<R>&, FieldArgs, hipStream_t);      \
-  template void launch_init_envelope<R>(const Geo&, const Grids<R>&, const Laser&, int, hipStream_t);
+  template void launch_init_envelope<R>(const Geo&, const Grids<R>&, const Laser&, int, hipStream_t);        \
+  template void launch_filter<R>(const Geo&, const DepositBufs<R>&, const DepositBufs<R>&, int, hipStream_t);
 ENVPIC_INST(float)
 ENVPIC_INST(double)
 #undef ENVPIC_INST

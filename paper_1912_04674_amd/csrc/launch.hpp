@@ -46,6 +46,10 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
 
 template <class R>
 void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st);
+// `passes` passes of the binomial filter on the currents of din into dout
+// (chi is not touched)
+template <class R>
+void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st);
 // arguments of the field-stage kernel besides the grids and deposits
 struct FieldArgs {
   Geo gn;                      // geometry after the window shift (as before it when there is none)

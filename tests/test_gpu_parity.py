@@ -254,6 +254,61 @@ def test_rows_multiple_of_64_parity(E, oracle_mod, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("passes", [1, 7])
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_binomial_filter_kernel(E, oracle_mod, prec, passes):
+    """The current filter alone: random currents of both modes on a grid whose
+    sizes fill no filter tile (70 x 45) go through the field stage of a
+    vacuum run; the filtered currents it keeps equal the oracle's filter of
+    the same input (axis ghosts, window ends and r_max included)."""
+    say("binomial filter", prec, passes)
+    cfg = scaled(C1, nx=70, nr=45, n_modes=2, profile="none", a0=0.0, filter_passes=passes,
+                 x_c=28.0, x_f=28.0)
+    g = E.Sim(cfg, _prec(E, prec))
+    r = oracle_mod.OracleSim(cfg)
+    rng = np.random.default_rng(11 + passes)
+    shape = (cfg["nx"] + 1, cfg["nr"] + 1)
+    valid = {"jx": (cfg["nx"] - 1, cfg["nr"]), "jr": (cfg["nx"], cfg["nr"] - 1), "jx1": (cfg["nx"] - 1, cfg["nr"]),
+             "jr1": (cfg["nx"], cfg["nr"] - 1), "jt1": (cfg["nx"], cfg["nr"])}
+    inputs = {}
+    for name, (imax, jmax) in valid.items():
+        f = rng.standard_normal(shape)
+        if name.endswith("1"):
+            f = f + 1j * rng.standard_normal(shape)
+        f[imax + 1:, :] = 0
+        f[:, jmax + 1:] = 0
+        inputs[name] = f
+    g.gather_push(E.MOMENTUM)
+    g.envelope_step()
+    g.gather_push(E.POSITION)
+    for name, f in inputs.items():
+        g.set_field(name, f)
+        r.set_field(name, f)
+    g.field_step()
+    r.filter_J()
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    for name in inputs:
+        want = r.get_field(name)
+        err = np.abs(g.get_field(name) - want).max() / np.abs(want).max()
+        say(name, f"{err:.2e}")
+        assert err <= tol, (name, err)
+
+
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_filtered_window_run_parity(E, oracle_mod, prec, tf, tp):
+    """The paper's nonlinear-benchmark filter (7 passes) in a moving-window run
+    with injection, modes 0 and 1: 60 steps against the oracle."""
+    say("filtered run", prec)
+    cfg = scaled(C2_SMALL, filter_passes=7, name="c2_small_filtered")
+    g = E.Sim(cfg, _prec(E, prec))
+    r = oracle_mod.OracleSim(cfg)
+    g.step(60)
+    r.step(60)
+    assert g.state() == r.state()
+    compare_fields(g, r, tf, names=("env", "chi", "ex", "er", "bt", "jx", "jr"), modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_vacuum_run_has_no_particles(E, oracle_mod, prec):
     """No plasma: zero particles through every stage; the envelope and the
