@@ -39,7 +39,8 @@
  *       uncompensated binomial filter of 7 passes): N passes of 1-2-1 in
  *       index space, each along x then along r, on J^{n+1/2} of both modes
  *       before the field update; zero current outside the window and beyond
- *       r_max, ghost rows below the axis by the component's parity (R23)
+ *       r_max, ghost rows below the axis by the component's parity (R23);
+ *       a component odd on the primal axis row (mode-1 J_x) is zero there
  */
 #include "oracle.h"
 
@@ -528,9 +529,13 @@ void binomial_pass(const Sim& s, std::vector<T>& f, int imax, int jmax, bool hal
 
 /* R24 on J^{n+1/2}: mode 0 J_x (axial, even; i+1/2, j) and J_r (radial,
  * odd; i, j+1/2); mode 1 J_x (axial, odd), J_r (radial, even; i, j+1/2)
- * and J_t (azimuthal, even; i, j).                                        */
+ * and J_t (azimuthal, even; i, j).  The odd mode-1 J_x vanishes on the axis
+ * (R23), so its axis row is zeroed first (the field update never reads it):
+ * the passes then act on an odd function.                                 */
 void filter_J(Sim& s) {
   const int Nx = s.Nx, Nr = s.Nr;
+  if (s.m1() && s.p.filter_passes > 0)
+    for (int i = 0; i <= Nx; ++i) s.Jx1[s.at(i, 0)] = 0.0;
   for (int k = 0; k < s.p.filter_passes; ++k) {
     binomial_pass(s, s.Jx, Nx - 1, Nr, false, +1.0);
     binomial_pass(s, s.Jr, Nx, Nr - 1, true, -1.0);

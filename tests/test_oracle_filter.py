@@ -75,6 +75,17 @@ def test_one_pass_at_the_zero_boundaries(oracle_mod):
     assert np.all(out[NX:, :] == 0)
 
 
+def test_odd_axial_current_vanishes_on_the_axis(oracle_mod):
+    """Mode-1 J_x is odd about the axis: a current on the axis row alone is
+    not a current at all, and filters to zero everywhere."""
+    s = _sim(oracle_mod, 4)
+    f = np.zeros((NX + 1, NR + 1), complex)
+    f[: NX, 0] = 1.0 - 2.0j
+    s.set_field("jx1", f)
+    s.filter_J()
+    assert np.abs(s.get_field("jx1")).max() == 0.0
+
+
 def test_no_filter_is_identity(oracle_mod):
     s = _sim(oracle_mod, 0)
     rng = np.random.default_rng(3)
