@@ -90,7 +90,8 @@ typedef struct envpic_params {
   double n0, ramp_len, perturb, bump_x, bump_w;
   int64_t capacity;        /* particle slots per buffer (0: derived) */
   int32_t filter_passes;   /* passes of the 1-2-1 binomial filter on J (0: none, at most
-                              ENVPIC_FILTER_MAX); each pass smooths along x, then r */
+                              ENVPIC_FILTER_MAX, below nx/2 and nr/2); each pass
+                              smooths along x, then r */
   int32_t reserved;        /* 0 */
 } envpic_params;
 #define ENVPIC_FILTER_MAX 8

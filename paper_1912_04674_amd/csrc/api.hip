@@ -89,6 +89,8 @@ int validate(const envpic_params* p) {
   if (p->profile < 0 || p->profile > 4) return fail(ENVPIC_EINVAL, "unknown plasma profile");
   if (p->filter_passes < 0 || p->filter_passes > ENVPIC_FILTER_MAX)
     return fail(ENVPIC_EINVAL, "filter_passes must be in [0, ENVPIC_FILTER_MAX]");
+  if (p->filter_passes > 0 && (p->nx <= 2 * p->filter_passes || p->nr <= 2 * p->filter_passes))
+    return fail(ENVPIC_EINVAL, "the binomial filter needs nx and nr above twice its passes");
   if (p->n0 < 0) return fail(ENVPIC_EINVAL, "n0 must be >= 0");
   if (p->profile == ENVPIC_PROFILE_RAMP && !(p->ramp_len > 0)) return fail(ENVPIC_EINVAL, "ramp_len must be > 0");
   if (p->profile == ENVPIC_PROFILE_BUMP && !(p->bump_w > 0)) return fail(ENVPIC_EINVAL, "bump_w must be > 0");

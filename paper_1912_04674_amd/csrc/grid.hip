@@ -451,102 +451,106 @@ void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, co
 // along r, on J^{n+1/2} of both modes before the field update: zero current
 // outside the window and beyond r_max, rows below the axis mirrored with the
 // component's parity (axial components (-1)^m, radial and azimuthal
-// (-1)^{m+1}).  A work group owns a FT x FT tile and holds it with a halo of
-// ENVPIC_FILTER_MAX nodes in LDS (one node of halo is consumed per pass and
-// direction), runs every pass there and writes the owned nodes to the
-// filtered copy that the field update reads.
-constexpr int FT = 32;                // owned nodes per tile side
-constexpr int FH = ENVPIC_FILTER_MAX;  // halo
-constexpr int FR = FT + 2 * FH;        // LDS region side
+// (-1)^{m+1}); the odd mode-1 J_x is zero on the axis row (it vanishes
+// there, and the field update never reads it).
+// Zeroing the node beyond an end before every pass is the same as filtering
+// the signal extended oddly about that node, and the axis rule is the same
+// as filtering its parity extension; 1-2-1 keeps both symmetries, and the x
+// and r passes commute (with each other and with those extensions).  So the
+// N passes are, exactly, one (2N+1)-tap convolution with the binomial
+// weights C(2N, N+m)/4^N along x and one along r, of the extended signal.
+// A work group owns a FT x FT tile, loads it with an N-node halo (the
+// extension applied at the load) into LDS, convolves along x, then along r,
+// and writes the owned nodes to the filtered copy the field update reads.
+// The grid must be at least N + 1 nodes wide in each direction.
+constexpr int FT = 32;                 // owned nodes per tile side
+constexpr int FH = ENVPIC_FILTER_MAX;  // largest halo
+constexpr int FR = FT + 2 * FH;        // LDS region side (at most)
 constexpr int FTH = 256;               // threads of a filter work group
 
-__device__ inline float lin3(float a, float b, float c) { return 0.25f * a + 0.5f * b + 0.25f * c; }
-__device__ inline double lin3(double a, double b, double c) { return 0.25 * a + 0.5 * b + 0.25 * c; }
-__device__ inline float2 lin3(float2 a, float2 b, float2 c) {
-  return make_float2(lin3(a.x, b.x, c.x), lin3(a.y, b.y, c.y));
-}
-__device__ inline double2 lin3(double2 a, double2 b, double2 c) {
-  return make_double2(lin3(a.x, b.x, c.x), lin3(a.y, b.y, c.y));
-}
 __device__ inline float vscale(float a, float s) { return a * s; }
 __device__ inline double vscale(double a, double s) { return a * s; }
 __device__ inline float2 vscale(float2 a, float s) { return make_float2(a.x * s, a.y * s); }
 __device__ inline double2 vscale(double2 a, double s) { return make_double2(a.x * s, a.y * s); }
+__device__ inline float vfma(float w, float a, float acc) { return fmaf(w, a, acc); }
+__device__ inline double vfma(double w, double a, double acc) { return fma(w, a, acc); }
+__device__ inline float2 vfma(float w, float2 a, float2 acc) { return make_float2(fmaf(w, a.x, acc.x), fmaf(w, a.y, acc.y)); }
+__device__ inline double2 vfma(double w, double2 a, double2 acc) { return make_double2(fma(w, a.x, acc.x), fma(w, a.y, acc.y)); }
+
+// index of the extended signal's node i in the valid range [0, m] and its
+// sign: odd reflection about -1 and about m + 1 (the zeroed neighbours);
+// returns -1 where the extension is zero
+__device__ inline int reflect_end(int i, int m, float& sign) {
+  if (i >= 0 && i <= m) return i;
+  if (i == -1 || i == m + 1) return -1;
+  sign = -sign;
+  return i < 0 ? -2 - i : 2 * (m + 1) - i;
+}
 
 // One component of the tile (i0, j0): valid for 0 <= i <= imax, 0 <= j <=
-// jmax; half_r: staggered by half a cell in r (the row below the axis
-// mirrors row 0, else row 1).  A, B: two LDS buffers of FR x FR values.
+// jmax; half_r: staggered by half a cell in r (the mirror of row j < 0 is
+// -1 - j, else -j).  A: (FT + 2N) x (FT + 2N) values, B: FT x (FT + 2N).
 template <class V, class R>
 __device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __restrict__ dst, int imax, int jmax,
-                                 bool half_r, R parity, int passes, int i0, int j0, V* A, V* B) {
+                                 bool half_r, R parity, int N, const R* cw, int i0, int j0, V* A, V* B) {
   const V zero = vscale(V{}, (R)0);
-  const bool ghosts = j0 - FH < 0;  // the tile touches the axis
-  // zero outside the valid ranges; rows below the axis from their mirrors
-  auto rules = [&](V* X) {
-    for (int k = threadIdx.x; k < FR * FR; k += FTH) {
-      const int a = k / FR, b = k - (k / FR) * FR;
-      const int i = i0 - FH + a, j = j0 - FH + b;
-      if (i < 0 || i > imax || j > jmax) X[k] = zero;
+  const int S = FT + 2 * N;  // region side
+  for (int k = threadIdx.x; k < S * S; k += FTH) {
+    const int a = k / S, b = k - (k / S) * S;
+    float sx = 1.0f, sr = 1.0f;
+    const int i = reflect_end(i0 - N + a, imax, sx);
+    int j = j0 - N + b;
+    if (j < 0) {  // below the axis: the parity mirror
+      j = half_r ? -1 - j : -j;
+      sr = (float)parity;
     }
-    if (!ghosts) return;
-    __syncthreads();
-    for (int k = threadIdx.x; k < FR * FR; k += FTH) {
-      const int a = k / FR, b = k - (k / FR) * FR;
-      const int i = i0 - FH + a, j = j0 - FH + b;
-      if (j >= 0 || i < 0 || i > imax) continue;
-      const int jm = half_r ? -1 - j : -j;  // mirror row, 0 <= jm <= FH
-      X[k] = jm <= jmax ? vscale(X[a * FR + (jm - (j0 - FH))], parity) : zero;
-    }
-  };
-  for (int k = threadIdx.x; k < FR * FR; k += FTH) {
-    const int a = k / FR, b = k - (k / FR) * FR;
-    const int i = i0 - FH + a, j = j0 - FH + b;
-    A[k] = (i >= 0 && i <= imax && j >= 0 && j <= jmax) ? src[(size_t)phys_col(g, i) * g.pitch + j] : zero;
+    j = reflect_end(j, jmax, sr);
+    const bool odd_axis = !half_r && parity < (R)0 && j == 0;  // an odd function's axis value
+    A[k] = (i < 0 || j < 0 || odd_axis) ? zero : vscale(src[(size_t)phys_col(g, i) * g.pitch + j], (R)(sx * sr));
   }
   __syncthreads();
-  rules(A);
-  __syncthreads();
-  for (int p = 0; p < passes; ++p) {
-    for (int k = threadIdx.x; k < FR * FR; k += FTH) {  // along x (the outer ring only goes stale)
-      const int a = k / FR;
-      B[k] = (a == 0 || a == FR - 1) ? A[k] : lin3(A[k - FR], A[k], A[k + FR]);
-    }
-    __syncthreads();
-    rules(B);
-    __syncthreads();
-    for (int k = threadIdx.x; k < FR * FR; k += FTH) {  // along r
-      const int b = k - (k / FR) * FR;
-      A[k] = (b == 0 || b == FR - 1) ? B[k] : lin3(B[k - 1], B[k], B[k + 1]);
-    }
-    __syncthreads();
-    rules(A);
-    __syncthreads();
+  // along x: owned columns, every row of the region
+  for (int k = threadIdx.x; k < FT * S; k += FTH) {
+    const int a = k / S, b = k - (k / S) * S;
+    V acc = zero;
+    for (int m = 0; m <= 2 * N; ++m) acc = vfma(cw[m], A[(a + m) * S + b], acc);
+    B[k] = acc;
   }
+  __syncthreads();
+  // along r: owned nodes
   for (int k = threadIdx.x; k < FT * FT; k += FTH) {
     const int a = k / FT, b = k - (k / FT) * FT;
     const int i = i0 + a, j = j0 + b;
     if (i > g.nx || j > g.nr) continue;
-    dst[(size_t)phys_col(g, i) * g.pitch + j] = (i <= imax && j <= jmax) ? A[(a + FH) * FR + b + FH] : zero;
+    V acc = zero;
+    for (int m = 0; m <= 2 * N; ++m) acc = vfma(cw[m], B[a * S + b + m], acc);
+    dst[(size_t)phys_col(g, i) * g.pitch + j] = (i <= imax && j <= jmax) ? acc : zero;
   }
   __syncthreads();  // the buffers are reused by the next component
 }
 
 template <class R, bool M1>
-__global__ __launch_bounds__(FTH) void k_filter(Geo g, DepositBufs<R> din, DepositBufs<R> dout, int passes) {
+__global__ __launch_bounds__(FTH) void k_filter(Geo g, DepositBufs<R> din, DepositBufs<R> dout, int N) {
   using C = typename cplx_of<R>::type;
-  __shared__ C buf[2 * FR * FR];
+  __shared__ C a_buf[FR * FR];
+  __shared__ C b_buf[FT * FR];
+  __shared__ R cw[2 * FH + 1];
   const int ntr = (g.nr + 1 + FT - 1) / FT;
   const int i0 = (blockIdx.x / ntr) * FT, j0 = (blockIdx.x % ntr) * FT;
-  R* ra = reinterpret_cast<R*>(buf);
-  R* rb = ra + FR * FR;
-  filter_component<R, R>(g, din.jx, dout.jx, g.nx - 1, g.nr, false, (R)1, passes, i0, j0, ra, rb);
-  filter_component<R, R>(g, din.jr, dout.jr, g.nx, g.nr - 1, true, (R)-1, passes, i0, j0, ra, rb);
+  if (threadIdx.x <= 2 * N) {  // binomial weights C(2N, m) / 4^N (exact)
+    double c = 1.0;
+    for (int q = 0; q < (int)threadIdx.x; ++q) c = c * (2 * N - q) / (q + 1);
+    cw[threadIdx.x] = (R)std::ldexp(c, -2 * N);
+  }
+  __syncthreads();
+  R* ra = reinterpret_cast<R*>(a_buf);
+  R* rb = reinterpret_cast<R*>(b_buf);
+  filter_component<R, R>(g, din.jx, dout.jx, g.nx - 1, g.nr, false, (R)1, N, cw, i0, j0, ra, rb);
+  filter_component<R, R>(g, din.jr, dout.jr, g.nx, g.nr - 1, true, (R)-1, N, cw, i0, j0, ra, rb);
   if (M1) {
-    C* ca = buf;
-    C* cb = buf + FR * FR;
-    filter_component<C, R>(g, din.jx1, dout.jx1, g.nx - 1, g.nr, false, (R)-1, passes, i0, j0, ca, cb);
-    filter_component<C, R>(g, din.jr1, dout.jr1, g.nx, g.nr - 1, true, (R)1, passes, i0, j0, ca, cb);
-    filter_component<C, R>(g, din.jt1, dout.jt1, g.nx, g.nr, false, (R)1, passes, i0, j0, ca, cb);
+    filter_component<C, R>(g, din.jx1, dout.jx1, g.nx - 1, g.nr, false, (R)-1, N, cw, i0, j0, a_buf, b_buf);
+    filter_component<C, R>(g, din.jr1, dout.jr1, g.nx, g.nr - 1, true, (R)1, N, cw, i0, j0, a_buf, b_buf);
+    filter_component<C, R>(g, din.jt1, dout.jt1, g.nx, g.nr, false, (R)1, N, cw, i0, j0, a_buf, b_buf);
   }
 }
 
