@@ -170,6 +170,8 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-serving", action="store_true", help="skip the scan-serving trace")
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
+    ap.add_argument("--filter-passes", type=int, default=0,
+                    help="binomial current filter passes (the paper's nonlinear benchmark uses 7)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB, 10 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -197,6 +199,8 @@ def main():
     import paper_1912_04674_amd as E
     from inputs import C2, C3, C5
     cfg = {"c2": C2, "c3": C3, "c5": C5}[args.workload]
+    if args.filter_passes:
+        cfg = dict(cfg, filter_passes=args.filter_passes, name=f"{cfg['name']}_filter{args.filter_passes}")
     E.lib()
     torch.cuda.set_device(0)
 
@@ -235,6 +239,7 @@ def main():
         "ms_per_step": 1e3 * r32["wall_s"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["nx"], cfg["nr"]], "modes": cfg["n_modes"],
+                   "filter_passes": int(cfg.get("filter_passes", 0)),
                    "ppc": list(cfg["ppc"]), "particles": int(r32["particles"]),
                    "moving_window": bool(cfg["moving_window"]), "precision": "fp32-bulk (fp64 axis rows)"},
         "roofline": roofline,

@@ -459,9 +459,10 @@ void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, co
 // and r passes commute (with each other and with those extensions).  So the
 // N passes are, exactly, one (2N+1)-tap convolution with the binomial
 // weights C(2N, N+m)/4^N along x and one along r, of the extended signal.
-// A work group owns a FT x FT tile, loads it with an N-node halo (the
-// extension applied at the load) into LDS, convolves along x, then along r,
-// and writes the owned nodes to the filtered copy the field update reads.
+// A work group owns one component of a FT x FT tile, loads it with an
+// N-node halo (the extension applied at the load) into LDS, convolves along
+// x, then along r, and writes the owned nodes to the filtered copy the field
+// update reads.
 // The grid must be at least N + 1 nodes wide in each direction.
 constexpr int FT = 32;                 // owned nodes per tile side
 constexpr int FH = ENVPIC_FILTER_MAX;  // largest halo
@@ -489,17 +490,19 @@ __device__ inline int reflect_end(int i, int m, float& sign) {
 
 // One component of the tile (i0, j0): valid for 0 <= i <= imax, 0 <= j <=
 // jmax; half_r: staggered by half a cell in r (the mirror of row j < 0 is
-// -1 - j, else -j).  A: (FT + 2N) x (FT + 2N) values, B: FT x (FT + 2N).
+// -1 - j, else -j).  A: FR x FR values (the tile and a halo of FH >= N
+// nodes; the outer FH - N rings are not needed), B: FT x FR.
 template <class V, class R>
 __device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __restrict__ dst, int imax, int jmax,
                                  bool half_r, R parity, int N, const R* cw, int i0, int j0, V* A, V* B) {
   const V zero = vscale(V{}, (R)0);
-  const int S = FT + 2 * N;  // region side
-  for (int k = threadIdx.x; k < S * S; k += FTH) {
-    const int a = k / S, b = k - (k / S) * S;
+  const int lo = FH - N, hi = FH + FT + N;  // the region rows and columns used
+  for (int k = threadIdx.x; k < FR * FR; k += FTH) {
+    const int a = k / FR, b = k - (k / FR) * FR;
+    if (a < lo || a >= hi || b < lo || b >= hi) continue;
     float sx = 1.0f, sr = 1.0f;
-    const int i = reflect_end(i0 - N + a, imax, sx);
-    int j = j0 - N + b;
+    const int i = reflect_end(i0 - FH + a, imax, sx);
+    int j = j0 - FH + b;
     if (j < 0) {  // below the axis: the parity mirror
       j = half_r ? -1 - j : -j;
       sr = (float)parity;
@@ -509,11 +512,12 @@ __device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __r
     A[k] = (i < 0 || j < 0 || odd_axis) ? zero : vscale(src[(size_t)phys_col(g, i) * g.pitch + j], (R)(sx * sr));
   }
   __syncthreads();
-  // along x: owned columns, every row of the region
-  for (int k = threadIdx.x; k < FT * S; k += FTH) {
-    const int a = k / S, b = k - (k / S) * S;
+  // along x: owned columns, the rows used
+  for (int k = threadIdx.x; k < FT * FR; k += FTH) {
+    const int a = k / FR, b = k - (k / FR) * FR;
+    if (b < lo || b >= hi) continue;
     V acc = zero;
-    for (int m = 0; m <= 2 * N; ++m) acc = vfma(cw[m], A[(a + m) * S + b], acc);
+    for (int m = 0; m <= 2 * N; ++m) acc = vfma(cw[m], A[(a + lo + m) * FR + b], acc);
     B[k] = acc;
   }
   __syncthreads();
@@ -523,20 +527,22 @@ __device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __r
     const int i = i0 + a, j = j0 + b;
     if (i > g.nx || j > g.nr) continue;
     V acc = zero;
-    for (int m = 0; m <= 2 * N; ++m) acc = vfma(cw[m], B[a * S + b + m], acc);
+    for (int m = 0; m <= 2 * N; ++m) acc = vfma(cw[m], B[a * FR + b + lo + m], acc);
     dst[(size_t)phys_col(g, i) * g.pitch + j] = (i <= imax && j <= jmax) ? acc : zero;
   }
-  __syncthreads();  // the buffers are reused by the next component
 }
 
+// work group: tile blockIdx.x / ncomp, component blockIdx.x % ncomp
 template <class R, bool M1>
 __global__ __launch_bounds__(FTH) void k_filter(Geo g, DepositBufs<R> din, DepositBufs<R> dout, int N) {
   using C = typename cplx_of<R>::type;
+  constexpr int ncomp = M1 ? 5 : 2;
   __shared__ C a_buf[FR * FR];
   __shared__ C b_buf[FT * FR];
   __shared__ R cw[2 * FH + 1];
+  const int tile = blockIdx.x / ncomp, comp = blockIdx.x % ncomp;
   const int ntr = (g.nr + 1 + FT - 1) / FT;
-  const int i0 = (blockIdx.x / ntr) * FT, j0 = (blockIdx.x % ntr) * FT;
+  const int i0 = (tile / ntr) * FT, j0 = (tile % ntr) * FT;
   if (threadIdx.x <= 2 * N) {  // binomial weights C(2N, m) / 4^N (exact)
     double c = 1.0;
     for (int q = 0; q < (int)threadIdx.x; ++q) c = c * (2 * N - q) / (q + 1);
@@ -545,19 +551,20 @@ __global__ __launch_bounds__(FTH) void k_filter(Geo g, DepositBufs<R> din, Depos
   __syncthreads();
   R* ra = reinterpret_cast<R*>(a_buf);
   R* rb = reinterpret_cast<R*>(b_buf);
-  filter_component<R, R>(g, din.jx, dout.jx, g.nx - 1, g.nr, false, (R)1, N, cw, i0, j0, ra, rb);
-  filter_component<R, R>(g, din.jr, dout.jr, g.nx, g.nr - 1, true, (R)-1, N, cw, i0, j0, ra, rb);
-  if (M1) {
-    filter_component<C, R>(g, din.jx1, dout.jx1, g.nx - 1, g.nr, false, (R)-1, N, cw, i0, j0, a_buf, b_buf);
-    filter_component<C, R>(g, din.jr1, dout.jr1, g.nx, g.nr - 1, true, (R)1, N, cw, i0, j0, a_buf, b_buf);
-    filter_component<C, R>(g, din.jt1, dout.jt1, g.nx, g.nr, false, (R)1, N, cw, i0, j0, a_buf, b_buf);
+  switch (comp) {
+    case 0: filter_component<R, R>(g, din.jx, dout.jx, g.nx - 1, g.nr, false, (R)1, N, cw, i0, j0, ra, rb); break;
+    case 1: filter_component<R, R>(g, din.jr, dout.jr, g.nx, g.nr - 1, true, (R)-1, N, cw, i0, j0, ra, rb); break;
+    case 2: filter_component<C, R>(g, din.jx1, dout.jx1, g.nx - 1, g.nr, false, (R)-1, N, cw, i0, j0, a_buf, b_buf); break;
+    case 3: filter_component<C, R>(g, din.jr1, dout.jr1, g.nx, g.nr - 1, true, (R)1, N, cw, i0, j0, a_buf, b_buf); break;
+    default: filter_component<C, R>(g, din.jt1, dout.jt1, g.nx, g.nr, false, (R)1, N, cw, i0, j0, a_buf, b_buf); break;
   }
 }
 
 template <class R>
 void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st) {
   if (passes <= 0) return;
-  const int grid = ((g.nx + 1 + FT - 1) / FT) * ((g.nr + 1 + FT - 1) / FT);
+  const int tiles = ((g.nx + 1 + FT - 1) / FT) * ((g.nr + 1 + FT - 1) / FT);
+  const int grid = tiles * (g.modes >= 2 ? 5 : 2);
   if (g.modes >= 2)
     hipLaunchKernelGGL((k_filter<R, true>), dim3(grid), dim3(FTH), 0, st, g, din, dout, passes);
   else
