@@ -76,7 +76,25 @@ def traffic_record(kernel, workload):
 TIMING_EVERY = 7
 
 
-def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True):
+# beam parameters of the final state (Table BeamParams): electrons above
+# 1e-3 m_e c^2 of kinetic energy, 512 bins up to 20 m_e c^2
+BEAM_QUERY = (1e-3, 20.0, 512)
+
+
+def time_beam(sim, torch, reps=20):
+    """Average wall time of the synchronous beam-parameter call (histogram,
+    peak and two moment passes over every particle, read back to the host)."""
+    out = sim.beam(*BEAM_QUERY)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        sim.beam(*BEAM_QUERY)
+    dt = (time.perf_counter() - t0) / reps
+    return {"ms": 1e3 * dt, "query": list(BEAM_QUERY), "count": out["count"], "e_peak": out["e_peak"],
+            "charge": out["charge"], "rel_spread": out["rel_spread"], "emit_y": out["emit_y"]}
+
+
+def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True, beam=False):
     """Warm up, then time `steps` steps issued by the library's own loop
     (envpic_step_n) on the simulation's stream.  With `per_kernel`, the
     library records HIP events around each stage's kernels on that same
@@ -108,6 +126,8 @@ def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True):
         timed = sum(1 for k in range(step0, step0 + steps) if k % TIMING_EVERY == 0)
         assert t["momentum"][1] == timed and t["position"][1] == timed, (t, timed)
         out["timed_launches"] = timed
+    if beam:
+        out["beam"] = time_beam(sim, torch)
     sim.close()
     del sim
     torch.cuda.empty_cache()
@@ -204,7 +224,7 @@ def main():
     E.lib()
     torch.cuda.set_device(0)
 
-    r32 = run_gpu(E, torch, cfg, E.FP32_BULK, args.steps, args.warmup)
+    r32 = run_gpu(E, torch, cfg, E.FP32_BULK, args.steps, args.warmup, beam=True)
     pushes = r32["particles"] * args.steps
     value = pushes / r32["wall_s"]
     cells = cfg["nx"] * cfg["nr"]
@@ -227,6 +247,12 @@ def main():
              "stage_avg_ms": r32["stage_ms"],
              "stage_timed_steps": r32["timed_launches"], "stage_timing_every": TIMING_EVERY,
              "particles_start_end": [r32["n0"], r32["n1"]]}
+    # the beam pass reads cell, momentum and weight of every particle three
+    # times (histogram, means, centred moments): 60 B per particle
+    bm = r32["beam"]
+    bm["alg_bytes"] = 3 * (4 + 3 * 4 + 4) * r32["n1"]
+    bm["GBps_alg_incl_host_sync"] = bm["alg_bytes"] / (bm["ms"] * 1e-3) / 1e9
+    extra["beam_diag"] = bm
     if not args.no_fp64:
         s64 = max(10, args.steps // 5)
         r64 = run_gpu(E, torch, cfg, E.FP64, s64, min(args.warmup, 5), per_kernel=False)

@@ -142,6 +142,24 @@ enum envpic_diag {
   ENVPIC_NDIAG = 9
 };
 
+/* injected-beam parameters (envpic_beam_diagnostics), FP64 */
+enum envpic_beam {
+  ENVPIC_B_PEAK = 0,    /* energy of the spectrum peak, gamma - 1 (m_e c^2) */
+  ENVPIC_B_FWHM = 1,    /* full width at half maximum of the peak (m_e c^2) */
+  ENVPIC_B_CHARGE = 2,  /* sum q w over the window (q = -1) */
+  ENVPIC_B_EMEAN = 3,   /* weighted mean energy over the window */
+  ENVPIC_B_ERMS = 4,    /* weighted rms energy spread over the window */
+  ENVPIC_B_SPREAD = 5,  /* ERMS / PEAK */
+  ENVPIC_B_EMIT_Y = 6,  /* normalized emittance of (y, p_y), c/w0 */
+  ENVPIC_B_EMIT_Z = 7,  /* normalized emittance of (z, p_z), c/w0 */
+  ENVPIC_B_COUNT = 8,   /* macro-particles in the window */
+  ENVPIC_B_QSPEC = 9,   /* sum q w over the whole spectrum range */
+  ENVPIC_B_WIN_LO = 10, /* window [WIN_LO, WIN_HI] in energy */
+  ENVPIC_B_WIN_HI = 11,
+  ENVPIC_NBEAM = 12
+};
+#define ENVPIC_BEAM_MAX_BINS 4096
+
 typedef struct envpic_sim envpic_sim;
 
 /* Fill `p` with a preset: 0 custom (small vacuum defaults); 1..5 the
@@ -221,6 +239,26 @@ int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts);
 
 /* FP64 device reductions of the current state into out[ENVPIC_NDIAG]. */
 int envpic_diagnostics(const envpic_sim* s, double* out);
+
+/* Injected-beam parameters of the current particles (Sec. 4, Table
+ * BeamParams: spectrum peak energy, beam charge, relative energy spread and
+ * normalized transverse emittance sqrt(s_uu s_pp - s_up^2), all over the
+ * particles within two FWHM widths in energy around the spectrum peak),
+ * as FP64 device reductions into out[ENVPIC_NBEAM].
+ *   energy     gamma - 1 with gamma = sqrt(1 + |p|^2);
+ *   spectrum   charge histogram sum |q| w over `nbins` equal bins of
+ *              [e_lo, e_hi) (e_lo leaves out the bulk plasma), copied to
+ *              `hist` (nbins doubles, caller-owned; NULL to skip);
+ *   peak       centre of the fullest bin (the lowest on a tie);
+ *   FWHM       half-maximum crossings interpolated between bin centres, the
+ *              range edge where a side stays above half maximum;
+ *   window     [peak - FWHM, peak + FWHM] within [e_lo, e_hi);
+ *   moments    weighted by w and centred; y = r cos(theta), z = r sin(theta).
+ * An empty spectrum gives all zeros.  Synchronous; only between steps
+ * (ENVPIC_EORDER otherwise).  ENVPIC_EINVAL unless e_lo < e_hi (finite)
+ * and 1 <= nbins <= ENVPIC_BEAM_MAX_BINS. */
+int envpic_beam_diagnostics(const envpic_sim* s, double e_lo, double e_hi, int nbins, double* out,
+                            double* hist);
 
 /* Checkpoint: with host_blob == NULL, *bytes receives the size needed; else
  * the full state (step, shift, both envelope levels, E, B, Bbar, particles,

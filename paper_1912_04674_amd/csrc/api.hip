@@ -128,6 +128,7 @@ template <class R> struct State {
   int* pending;  // [items, slots] appended by the last injection, not yet counted
   double* diag_scratch;
   double* diag_out;
+  BeamScratch beam;
 };
 
 template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64_rows, char* base, State<R>* st) {
@@ -223,6 +224,11 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   g.nr = p.nr;
   S.diag_scratch = cv.take<double>((size_t)diag_scratch_doubles(s.max_items, g));
   S.diag_out = cv.take<double>(ENVPIC_NDIAG);
+  S.beam.hist = cv.take<unsigned long long>(BEAM_MAX_BINS);
+  S.beam.hist_f = cv.take<double>(BEAM_MAX_BINS);
+  S.beam.part = cv.take<double>((size_t)s.max_items * BEAM_PARTS);
+  S.beam.st = cv.take<double>(BEAM_STATE);
+  S.beam.out = cv.take<double>(ENVPIC_NBEAM);
   if (st) *st = S;
   return align_up(cv.off, 256);
 }
@@ -378,6 +384,7 @@ struct envpic_sim {
   virtual int get_particles(std::vector<double>* cols, std::vector<uint32_t>* ids) = 0;
   virtual int set_particles(int64_t n, const double* const* cols, const uint32_t* id) = 0;
   virtual int diagnostics(double* out) = 0;
+  virtual int beam(double e_lo, double e_hi, int nbins, double* out, double* hist) = 0;
   virtual int poison(int f) = 0;
   virtual int check_err() = 0;
   virtual int clear_deposits() = 0;
@@ -920,6 +927,24 @@ template <class R> struct SimT : envpic_sim {
     return check_err();
   }
 
+  int beam(double e_lo, double e_hi, int nbins, double* out, double* hist) override {
+    BeamArgs a{};
+    a.e_lo = e_lo;
+    a.e_hi = e_hi;
+    a.nbins = nbins;
+    a.de = (e_hi - e_lo) / nbins;
+    // fixed-point histogram: a power of two with capacity * w_max * scale <= 2^61
+    const double wb = std::max(wmax, 1e-300) * (double)sz.capacity;
+    a.scale = std::ldexp(1.0, std::min(1000, (int)std::floor(std::log2(std::ldexp(1.0, 61) / wb))));
+    launch_beam<R>(geo(), S.parts[cur], S.lay[cur], sz.max_items, a, S.beam, stream);
+    int rc = launched("beam diagnostics");
+    if (rc) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(out, S.beam.out, ENVPIC_NBEAM * sizeof(double), hipMemcpyDeviceToHost, stream), "beam read"))) return rc;
+    if (hist && (rc = hip_check(hipMemcpyAsync(hist, S.beam.hist_f, nbins * sizeof(double), hipMemcpyDeviceToHost, stream), "beam hist"))) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "beam sync"))) return rc;
+    return check_err();
+  }
+
   int poison(int f) override {
     std::vector<double> buf;
     FieldRef r;
@@ -1162,6 +1187,17 @@ int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts) {
 int envpic_diagnostics(const envpic_sim* s, double* out) {
   if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
   return const_cast<envpic_sim*>(s)->diagnostics(out);
+}
+
+int envpic_beam_diagnostics(const envpic_sim* cs, double e_lo, double e_hi, int nbins, double* out, double* hist) {
+  static_assert(ENVPIC_BEAM_MAX_BINS == envpic::BEAM_MAX_BINS, "beam histogram bound");
+  envpic_sim* s = const_cast<envpic_sim*>(cs);
+  if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
+  if (!(std::isfinite(e_lo) && std::isfinite(e_hi) && e_hi > e_lo))
+    return fail(ENVPIC_EINVAL, "beam diagnostics need finite e_lo < e_hi");
+  if (nbins < 1 || nbins > ENVPIC_BEAM_MAX_BINS) return fail(ENVPIC_EINVAL, "nbins outside [1, ENVPIC_BEAM_MAX_BINS]");
+  if (s->stage != 0) return fail(ENVPIC_EORDER, "beam diagnostics only between steps");
+  return s->beam(e_lo, e_hi, nbins, out, hist);
 }
 
 // checkpoint blob: header, the persistent grids (FP64, window-relative),

@@ -81,4 +81,28 @@ template <class R>
 void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, int max_items, const Grids<R>& f, const R* chi,
                  int fp64_rows, double* scratch, double* out, hipStream_t st);
 
+// injected-beam parameters (beam.hip)
+constexpr int BEAM_MAX_BINS = 4096;
+constexpr int BEAM_PARTS = 8;  // partial sums per work item in each moment pass
+struct BeamArgs {
+  double e_lo, e_hi, de;  // spectrum range (gamma - 1) and bin width (e_hi - e_lo) / nbins
+  double scale;           // fixed-point scale of the histogram: sum |w| scale < 2^62
+  int nbins;
+};
+// slots of the small state vector the beam kernels pass on to each other
+enum {
+  BS_NONEMPTY = 0, BS_PEAK, BS_FWHM, BS_LO, BS_HI, BS_W, BS_COUNT, BS_QSPEC,
+  BS_EMEAN, BS_YMEAN, BS_ZMEAN, BS_PYMEAN, BS_PZMEAN, BEAM_STATE = 16
+};
+struct BeamScratch {
+  unsigned long long* hist;  // [BEAM_MAX_BINS] fixed-point charge per bin
+  double* hist_f;            // [BEAM_MAX_BINS] the same as FP64 (charge units)
+  double* part;              // [max_items][BEAM_PARTS] per-item partial sums
+  double* st;                // [BEAM_STATE]
+  double* out;               // [ENVPIC_NBEAM]
+};
+template <class R>
+void launch_beam(const Geo& g, const Parts<R>& P, const Layout& L, int max_items, const BeamArgs& a,
+                 const BeamScratch& b, hipStream_t st);
+
 }  // namespace envpic

@@ -29,6 +29,9 @@ FIELDS = {
 COMPLEX_FIELDS = {"env", "env_prev", "ex1", "er1", "et1", "bx1", "br1", "bt1",
                   "bx1_bar", "br1_bar", "bt1_bar", "jx1", "jr1", "jt1"}
 DIAG_NAMES = ["count", "charge", "chi_v", "kin", "uem", "env2_v", "lx", "px", "nonfinite"]
+BEAM_NAMES = ["e_peak", "fwhm", "charge", "e_mean", "e_rms", "rel_spread", "emit_y", "emit_z", "count",
+              "charge_spectrum", "win_lo", "win_hi"]
+BEAM_MAX_BINS = 4096
 ERRORS = {-1: "EINVAL", -2: "ENOMEM", -3: "EORDER", -4: "EDEVICE", -5: "ENUMERIC"}
 
 
@@ -63,7 +66,7 @@ EXPORTS = [
     "envpic_batch_step", "envpic_get_field", "envpic_set_field", "envpic_state",
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
-    "envpic_set_timing", "envpic_get_timing", "envpic_set_graph",
+    "envpic_set_timing", "envpic_get_timing", "envpic_set_graph", "envpic_beam_diagnostics",
 ]
 
 
@@ -95,6 +98,7 @@ def lib():
     L.envpic_get_particles.argtypes = [vp] + [dp] * 7 + [up]
     L.envpic_set_particles.argtypes = [vp, ctypes.c_int64] + [dp] * 7 + [up]
     L.envpic_diagnostics.argtypes = [vp, dp]
+    L.envpic_beam_diagnostics.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
     L.envpic_set_timing.argtypes = [vp, ctypes.c_int]
     L.envpic_set_graph.argtypes = [vp, ctypes.c_int]
     L.envpic_get_timing.argtypes = [vp, dp, i64p]
@@ -276,6 +280,16 @@ class Sim:
         out = np.zeros(len(DIAG_NAMES))
         _check(lib().envpic_diagnostics(self._h, _dptr(out)))
         return dict(zip(DIAG_NAMES, out))
+
+    def beam(self, e_lo, e_hi, nbins, with_hist=False):
+        """Injected-beam parameters (dict of BEAM_NAMES), and the charge
+        spectrum over [e_lo, e_hi) when with_hist."""
+        out = np.zeros(len(BEAM_NAMES))
+        hist = np.zeros(max(int(nbins), 1)) if with_hist else None
+        _check(lib().envpic_beam_diagnostics(self._h, float(e_lo), float(e_hi), int(nbins), _dptr(out),
+                                             _dptr(hist) if with_hist else None))
+        res = dict(zip(BEAM_NAMES, out))
+        return (res, hist) if with_hist else res
 
     def save(self):
         n = ctypes.c_size_t()

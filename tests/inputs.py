@@ -117,3 +117,27 @@ def random_grid(cfg, seed, amp=1.0, complex_=False):
         a = rng.normal() + (1j * rng.normal() if complex_ else 0.0)
         out = out + a * np.cos(2 * np.pi * kx * i + ph[0]) * np.cos(2 * np.pi * kr * j + ph[1])
     return amp * out / 4.0
+
+
+def beam_particles(cfg, n_bulk, n_beam, seed, p_beam=400.0, dp_beam=8.0, sig_r=2.0):
+    """A cold bulk plasma near rest plus an accelerated electron bunch, as
+    after self-injection: the bunch has p_x ~ N(p_beam, dp_beam), transverse
+    positions ~ N(0, sig_r) and transverse momenta correlated with them, and
+    a low-energy tail (a fifth of the bunch with p_x ~ U[20, p_beam]).
+    Lab-frame Cartesian FP64 arrays plus ids; all inside the window."""
+    rng = np.random.default_rng(seed)
+    dx, dr = cfg["dx"], cfg["dr"]
+    nx, nr = cfg["nx"], cfg["nr"]
+    bulk = random_particles(cfg, n_bulk, seed + 1, margin=4.0, pmax=0.05)
+    x = rng.uniform(0.3 * nx * dx, 0.5 * nx * dx, n_beam)
+    y = np.clip(rng.normal(0.0, sig_r, n_beam), -0.3 * nr * dr, 0.3 * nr * dr)
+    z = np.clip(rng.normal(0.0, sig_r, n_beam), -0.3 * nr * dr, 0.3 * nr * dr)
+    px = rng.normal(p_beam, dp_beam, n_beam)
+    tail = rng.uniform(0.0, 1.0, n_beam) < 0.2
+    px[tail] = rng.uniform(20.0, p_beam, int(tail.sum()))
+    py = 0.5 * y + rng.normal(0.0, 1.0, n_beam)
+    pz = -0.3 * z + rng.normal(0.0, 0.7, n_beam)
+    w = rng.uniform(0.2, 1.0, n_beam) * 1e-3
+    ids = np.arange(n_bulk, n_bulk + n_beam, dtype=np.uint32)
+    return {k: np.concatenate([bulk[k], v]) for k, v in
+            dict(x=x, y=y, z=z, px=px, py=py, pz=pz, w=w, id=ids).items()}

@@ -80,3 +80,13 @@ def test_stability_guard_matches_oracle_growth(oracle_mod):
         ok.envelope()
     assert np.abs(bad.get_field("env")).max() > 1e3
     assert np.abs(ok.get_field("env")).max() < 1.5
+
+
+def test_beam_diagnostics_null_sim_rejected(E):
+    """Argument checks of the beam diagnostics run on the host before any
+    device work: a NULL simulation or output is ENVPIC_EINVAL."""
+    import ctypes
+    out = np.zeros(len(E.envpic.BEAM_NAMES))
+    dp = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    assert E.lib().envpic_beam_diagnostics(None, 0.0, 1.0, 8, dp, None) == -1
+    assert len(E.envpic.BEAM_NAMES) == 12
