@@ -95,7 +95,8 @@ class GpuBackend:
     one by one then keeps the host busier than the device.  With fewer jobs
     the kernels are launched directly, which runs a lone job faster."""
 
-    def __init__(self, budget_bytes, precision=0, lineout=True, full=False, graph_min_jobs=4):
+    def __init__(self, budget_bytes, precision=0, lineout=True, full=False, graph_min_jobs=4,
+                 beam_query=(1e-3, 20.0, 256)):
         import torch
         from . import envpic as E
         self.E, self.torch = E, torch
@@ -104,6 +105,9 @@ class GpuBackend:
         self.arena = torch.empty(int(budget_bytes), dtype=torch.uint8, device="cuda")
         self.budget = int(budget_bytes)
         self.lineout, self.full = lineout, full
+        # (e_lo, e_hi, nbins) of the injected-beam parameters returned with
+        # each result (a job's cfg may give its own as "beam_query"); None: off
+        self.beam_query = beam_query
         self.graph_min_jobs = graph_min_jobs
         self._streams = []
         self._live = 0
@@ -117,7 +121,8 @@ class GpuBackend:
         view = self.arena[offset:offset + job.footprint]
         sim = self.E.Sim(job.cfg, self.precision, arena=view, stream=st)
         self._live += 1
-        return {"sim": sim, "stream": st, "view": view, "graph": 0}
+        return {"sim": sim, "stream": st, "view": view, "graph": 0,
+                "beam_query": job.cfg.get("beam_query", self.beam_query)}
 
     def issue(self, h, k):
         """Queue k steps on the job's stream; returns a completion token."""
@@ -136,6 +141,8 @@ class GpuBackend:
     def result(self, h):
         sim = h["sim"]
         out = {"diag": sim.diagnostics()}
+        if h["beam_query"] is not None:
+            out["beam"] = sim.beam(*h["beam_query"])
         if self.lineout:
             out["ex_axis"] = sim.get_field("ex")[:, 0].copy()
         if self.full:  # the whole final state (for checks)

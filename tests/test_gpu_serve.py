@@ -40,11 +40,13 @@ def _small_jobs(n):
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
 def test_jobs_same_alone_and_in_the_mix(E, prec):
+    from oracle import beam
     from paper_1912_04674_amd.serve import GpuBackend, ScanServer, DONE
     P = E.FP32_BULK if prec == "fp32" else E.FP64
     cfgs = _small_jobs(6)
     need = sum(E.footprint(c, P) for c in cfgs)
-    be = GpuBackend(budget_bytes=need // 2 + (1 << 20), precision=P, full=True)  # not all fit at once
+    be = GpuBackend(budget_bytes=need // 2 + (1 << 20), precision=P, full=True,  # not all fit at once
+                    beam_query=(0.0, 0.05, 64))
     srv = ScanServer(be, chunk=7, depth=2)
     say("serving", prec, [c["name"] for c in cfgs])
     jobs = srv.run_trace(cfgs, [0.0, 0.0, 0.001, 0.002, 0.003, 0.004], steps=40, timeout=120)
@@ -65,5 +67,11 @@ def test_jobs_same_alone_and_in_the_mix(E, prec):
         pm = max(np.abs(a[k]).max() for k in ("px", "py", "pz")) or 1.0
         for k in ("px", "py", "pz"):
             assert np.abs(a[k][oa] - b[k][ob]).max() / pm <= tol_p, (c["name"], k)
+        # the beam parameters returned with the job are those of its final particles
+        ref, _ = beam.beam_parameters(b, *be.beam_query)
+        assert ref["count"] > 0
+        for k, v in ref.items():
+            got = j.result["beam"][k]
+            assert got == v if k == "count" else abs(got - v) <= 1e-9 * abs(v), (c["name"], k, got, v)
         alone.close()
     say("ok", prec)
