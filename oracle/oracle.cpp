@@ -163,47 +163,68 @@ cplx pulse(const Sim& s, double xl, double r, double t) {
   return p.a0 * std::exp(-r * r / (p.w0 * p.w0 * q)) / q * std::exp(-xi * xi / (sig * sig));
 }
 
-/* ------------------------------------------------------------- shapes -- */
+/* ------------------------------------------------------------- shapes --
+ * Order 1 (R9, cloud in cell): nodes floor(u), floor(u)+1 with weights
+ * 1-f, f.  Order 2 (R26, quadratic B-spline): around the nearest node
+ * m = floor(u + 1/2), d = u - m in [-1/2, 1/2), nodes m-1, m, m+1 with
+ * weights (1/2 - d)^2/2, 3/4 - d^2, (1/2 + d)^2/2.  u is in node units
+ * (cell units for the primal nodes, shifted by 1/2 for the dual ones).   */
 struct Sh {
   int i;       /* first node */
-  double a, b; /* weights of nodes i and i+1 */
+  int n;       /* number of nodes (order + 1) */
+  double w[3]; /* weights of nodes i .. i+n-1 */
 };
-Sh primal(double u) {
-  double f = std::floor(u);
-  return Sh{(int)f, 1.0 - (u - f), u - f};
+Sh shape(double u, int order) {
+  Sh r{};
+  if (order == 2) {
+    double m = std::floor(u + 0.5), d = u - m;
+    r.i = (int)m - 1;
+    r.n = 3;
+    r.w[0] = 0.5 * (0.5 - d) * (0.5 - d);
+    r.w[1] = 0.75 - d * d;
+    r.w[2] = 0.5 * (0.5 + d) * (0.5 + d);
+  } else {
+    double f = std::floor(u);
+    r.i = (int)f;
+    r.n = 2;
+    r.w[0] = 1.0 - (u - f);
+    r.w[1] = u - f;
+  }
+  return r;
 }
-Sh dual(double u) { return primal(u - 0.5); }
+int order_of(const Sim& s) { return s.p.shape_order == 2 ? 2 : 1; }
+Sh primal(const Sim& s, double u) { return shape(u, order_of(s)); }
+Sh dual(const Sim& s, double u) { return shape(u - 0.5, order_of(s)); }
 
-/* value of a real grid at (i, j); (imax, jmax) is the last stored index of
- * this staggering, row j = -1 is the mirror of row 0 with sign `par`
- * (parity across the axis), anything else outside is zero.              */
-double val(const Sim& s, const std::vector<double>& f, int i, int j, int imax, int jmax,
-           double par) {
-  if (i < 0 || i > imax) return 0.0;
-  if (j == -1) return par * f[s.at(i, 0)];
-  if (j < 0 || j > jmax) return 0.0;
+/* Radial staggering of a grid: primal rows sit at r = j dr, half rows at
+ * r = (j + 1/2) dr.  Below the axis a grid continues by its parity (R23):
+ * primal row -j mirrors row j, half row -1-j mirrors row j.              */
+enum Stag { PRIMAL_R = 0, HALF_R = 1 };
+int mirror_row(int j, Stag st) { return st == HALF_R ? -1 - j : -j; }
+
+/* value of a grid at (i, j); (imax, jmax) is the last stored index of this
+ * staggering; rows below the axis mirror with sign `par`; anything else
+ * outside is zero.                                                        */
+template <class T>
+T val(const Sim& s, const std::vector<T>& f, int i, int j, int imax, int jmax, Stag st, double par) {
+  if (i < 0 || i > imax) return T(0.0);
+  if (j < 0) {
+    int m = mirror_row(j, st);
+    if (m > jmax) return T(0.0);
+    return par * f[s.at(i, m)];
+  }
+  if (j > jmax) return T(0.0);
   return f[s.at(i, j)];
 }
-cplx valc(const Sim& s, const std::vector<cplx>& f, int i, int j, int imax, int jmax,
-          double par) {
-  if (i < 0 || i > imax) return 0.0;
-  if (j == -1) return par * f[s.at(i, 0)];
-  if (j < 0 || j > jmax) return 0.0;
-  return f[s.at(i, j)];
-}
-double interp(const Sim& s, const std::vector<double>& f, Sh sx, Sh sr, int imax, int jmax,
-              double par) {
-  return sx.a * (sr.a * val(s, f, sx.i, sr.i, imax, jmax, par) +
-                 sr.b * val(s, f, sx.i, sr.i + 1, imax, jmax, par)) +
-         sx.b * (sr.a * val(s, f, sx.i + 1, sr.i, imax, jmax, par) +
-                 sr.b * val(s, f, sx.i + 1, sr.i + 1, imax, jmax, par));
-}
-cplx interpc(const Sim& s, const std::vector<cplx>& f, Sh sx, Sh sr, int imax, int jmax,
-             double par) {
-  return sx.a * (sr.a * valc(s, f, sx.i, sr.i, imax, jmax, par) +
-                 sr.b * valc(s, f, sx.i, sr.i + 1, imax, jmax, par)) +
-         sx.b * (sr.a * valc(s, f, sx.i + 1, sr.i, imax, jmax, par) +
-                 sr.b * valc(s, f, sx.i + 1, sr.i + 1, imax, jmax, par));
+template <class T>
+T interp(const Sim& s, const std::vector<T>& f, Sh sx, Sh sr, int imax, int jmax, Stag st, double par) {
+  T acc(0.0);
+  for (int a = 0; a < sx.n; ++a) {
+    T col(0.0);
+    for (int b = 0; b < sr.n; ++b) col += sr.w[b] * val(s, f, sx.i + a, sr.i + b, imax, jmax, st, par);
+    acc += sx.w[a] * col;
+  }
+  return acc;
 }
 
 /* mode-1 contribution at azimuth (c, s) = (cos, sin): Re[F e^{-i theta}] */
@@ -261,26 +282,29 @@ void momentum_chi(Sim& s) {
     double ux = s.x[k] / dx - (double)s.shift;
     double r = std::sqrt(s.y[k] * s.y[k] + s.z[k] * s.z[k]);
     double ur = r / dr;
-    Sh Px = primal(ux), Dx = dual(ux), Pr = primal(ur), Dr = dual(ur);
+    Sh Px = primal(s, ux), Dx = dual(s, ux), Pr = primal(s, ur), Dr = dual(s, ur);
     double c = 1.0, sn = 0.0;
     if (r > 0.0) {
       c = s.y[k] / r;
       sn = s.z[k] / r;
     }
-    double ex = interp(s, s.Ex, Dx, Pr, Nx - 1, Nr, 1.0);
-    double er = interp(s, s.Er, Px, Dr, Nx, Nr - 1, -1.0);
-    double bt = interp(s, s.Btb, Dx, Dr, Nx - 1, Nr - 1, -1.0);
+    /* parities across the axis (R23): axial components (-1)^m, radial and
+     * azimuthal ones (-1)^(m+1); Phi and its x-derivative even, its
+     * r-derivative odd */
+    double ex = interp(s, s.Ex, Dx, Pr, Nx - 1, Nr, PRIMAL_R, 1.0);
+    double er = interp(s, s.Er, Px, Dr, Nx, Nr - 1, HALF_R, -1.0);
+    double bt = interp(s, s.Btb, Dx, Dr, Nx - 1, Nr - 1, HALF_R, -1.0);
     double et = 0.0, bx = 0.0, br = 0.0;
-    double ph = interp(s, phi, Px, Pr, Nx, Nr, 1.0);
-    double gxp = interp(s, gx, Px, Pr, Nx, Nr, 1.0);
-    double grp = interp(s, gr, Px, Pr, Nx, Nr, 1.0);
+    double ph = interp(s, phi, Px, Pr, Nx, Nr, PRIMAL_R, 1.0);
+    double gxp = interp(s, gx, Px, Pr, Nx, Nr, PRIMAL_R, 1.0);
+    double grp = interp(s, gr, Px, Pr, Nx, Nr, PRIMAL_R, -1.0);
     if (s.m1()) {
-      ex += mode1(interpc(s, s.Ex1, Dx, Pr, Nx - 1, Nr, -1.0), c, sn);
-      er += mode1(interpc(s, s.Er1, Px, Dr, Nx, Nr - 1, 1.0), c, sn);
-      et += mode1(interpc(s, s.Et1, Px, Pr, Nx, Nr, -1.0), c, sn);
-      bx += mode1(interpc(s, s.Bxb1, Px, Dr, Nx, Nr - 1, -1.0), c, sn);
-      br += mode1(interpc(s, s.Brb1, Dx, Pr, Nx - 1, Nr, 1.0), c, sn);
-      bt += mode1(interpc(s, s.Btb1, Dx, Dr, Nx - 1, Nr - 1, 1.0), c, sn);
+      ex += mode1(interp(s, s.Ex1, Dx, Pr, Nx - 1, Nr, PRIMAL_R, -1.0), c, sn);
+      er += mode1(interp(s, s.Er1, Px, Dr, Nx, Nr - 1, HALF_R, 1.0), c, sn);
+      et += mode1(interp(s, s.Et1, Px, Pr, Nx, Nr, PRIMAL_R, 1.0), c, sn);
+      bx += mode1(interp(s, s.Bxb1, Px, Dr, Nx, Nr - 1, HALF_R, -1.0), c, sn);
+      br += mode1(interp(s, s.Brb1, Dx, Pr, Nx - 1, Nr, PRIMAL_R, 1.0), c, sn);
+      bt += mode1(interp(s, s.Btb1, Dx, Dr, Nx - 1, Nr - 1, HALF_R, 1.0), c, sn);
     }
     /* rotate (x, r, theta) components to Cartesian */
     double E[3] = {ex, er * c - et * sn, er * sn + et * c};
@@ -306,13 +330,14 @@ void momentum_chi(Sim& s) {
     s.py[k] = pl[1] + 0.5 * dt * F[1];
     s.pz[k] = pl[2] + 0.5 * dt * F[2];
     s.gbar[k] = gb;
-    /* chi^n deposit at the primal nodes around x^n */
-    double ws[2] = {Px.a, Px.b}, wr[2] = {Pr.a, Pr.b};
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) {
+    /* chi^n deposit at the primal nodes around x^n (even across the
+     * axis); the volume is that of the row the contribution lands on */
+    for (int a = 0; a < Px.n; ++a)
+      for (int b = 0; b < Pr.n; ++b) {
         int i = Px.i + a, j = Pr.i + b;
+        if (j < 0) j = mirror_row(j, PRIMAL_R);
         if (i < 0 || i > Nx || j < 0 || j > Nr) continue;
-        s.chi[s.at(i, j)] += s.w[k] * ws[a] * wr[b] / (gb * vol_node(s, j));
+        s.chi[s.at(i, j)] += s.w[k] * Px.w[a] * Pr.w[b] / (gb * vol_node(s, j));
       }
   }
 }
@@ -364,33 +389,43 @@ void envelope(Sim& s) {
 void deposit_J_mode0(Sim& s, double w, double ux0, double ur0, double ux1, double ur1) {
   const int Nx = s.Nx, Nr = s.Nr;
   const double q = -1.0;
-  Sh a0 = primal(ux0), a1 = primal(ux1), b0 = primal(ur0), b1 = primal(ur1);
+  Sh a0 = primal(s, ux0), a1 = primal(s, ux1), b0 = primal(s, ur0), b1 = primal(s, ur1);
+  /* the two stencils, on the union of their nodes (one node more than a
+   * stencil, since a particle moves less than a cell per step) */
+  const int K = a0.n + 1;
   int imin = std::min(a0.i, a1.i), jmin = std::min(b0.i, b1.i);
-  double S0x[3] = {0, 0, 0}, S1x[3] = {0, 0, 0}, S0r[3] = {0, 0, 0}, S1r[3] = {0, 0, 0};
-  S0x[a0.i - imin] += a0.a;
-  S0x[a0.i - imin + 1] += a0.b;
-  S1x[a1.i - imin] += a1.a;
-  S1x[a1.i - imin + 1] += a1.b;
-  S0r[b0.i - jmin] += b0.a;
-  S0r[b0.i - jmin + 1] += b0.b;
-  S1r[b1.i - jmin] += b1.a;
-  S1r[b1.i - jmin + 1] += b1.b;
-  for (int b = 0; b < 3; ++b) {
+  double S0x[4] = {0, 0, 0, 0}, S1x[4] = {0, 0, 0, 0}, S0r[4] = {0, 0, 0, 0}, S1r[4] = {0, 0, 0, 0};
+  for (int m = 0; m < a0.n; ++m) {
+    S0x[a0.i - imin + m] += a0.w[m];
+    S1x[a1.i - imin + m] += a1.w[m];
+    S0r[b0.i - jmin + m] += b0.w[m];
+    S1r[b1.i - jmin + m] += b1.w[m];
+  }
+  /* J_x on row j: even across the axis (a row below folds onto its mirror) */
+  for (int b = 0; b < K; ++b) {
     double acc = 0.0;
-    for (int a = 0; a < 3; ++a) {
+    for (int a = 0; a < K; ++a) {
       acc += (S1x[a] - S0x[a]) * (S0r[b] + S1r[b]) * 0.5;
       int i = imin + a, j = jmin + b;
+      if (j < 0) j = mirror_row(j, PRIMAL_R);
       if (i < 0 || i > Nx - 1 || j < 0 || j > Nr) continue;
       s.Jx[s.at(i, j)] += -q * w * acc / (area_x(s, j) * s.dt);
     }
   }
-  for (int a = 0; a < 3; ++a) {
+  /* J_r at the face j + 1/2: odd across the axis (the face at -1/2 folds
+   * onto +1/2 with the opposite sign) */
+  for (int a = 0; a < K; ++a) {
     double acc = 0.0;
-    for (int b = 0; b < 3; ++b) {
+    for (int b = 0; b < K; ++b) {
       acc += (S1r[b] - S0r[b]) * (S0x[a] + S1x[a]) * 0.5;
       int i = imin + a, j = jmin + b;
+      double sg = 1.0;
+      if (j < 0) {
+        j = mirror_row(j, HALF_R);
+        sg = -1.0;
+      }
       if (i < 0 || i > Nx || j < 0 || j > Nr - 1) continue;
-      s.Jr[s.at(i, j)] += -q * w * acc / (area_r(s, j) * s.dt);
+      s.Jr[s.at(i, j)] += sg * -q * w * acc / (area_r(s, j) * s.dt);
     }
   }
 }
@@ -404,32 +439,34 @@ void deposit_J_mode1(Sim& s, double w, double ux, double ur, double c, double sn
   const double q = -1.0;
   double vr = v[1] * c + v[2] * sn, vt = -v[1] * sn + v[2] * c;
   cplx e(c, sn);
-  Sh Px = primal(ux), Dx = dual(ux), Pr = primal(ur), Dr = dual(ur);
-  double wx[2], wr[2];
-  /* J_x1 at (i+1/2, j) */
-  wx[0] = Dx.a; wx[1] = Dx.b; wr[0] = Pr.a; wr[1] = Pr.b;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
+  Sh Px = primal(s, ux), Dx = dual(s, ux), Pr = primal(s, ur), Dr = dual(s, ur);
+  /* J_x1 at (i+1/2, j): odd across the axis for mode 1 */
+  for (int a = 0; a < Dx.n; ++a)
+    for (int b = 0; b < Pr.n; ++b) {
       int i = Dx.i + a, j = Pr.i + b;
+      double sg = 1.0;
+      if (j < 0) {
+        j = mirror_row(j, PRIMAL_R);
+        sg = -1.0;
+      }
       if (i < 0 || i > Nx - 1 || j < 0 || j > Nr) continue;
-      s.Jx1[s.at(i, j)] += 2.0 * q * w * v[0] * wx[a] * wr[b] * e / vol_node(s, j);
+      s.Jx1[s.at(i, j)] += sg * 2.0 * q * w * v[0] * Dx.w[a] * Pr.w[b] * e / vol_node(s, j);
     }
-  /* J_r1 at (i, j+1/2); row -1/2 folds onto +1/2 (even for mode 1) */
-  wx[0] = Px.a; wx[1] = Px.b; wr[0] = Dr.a; wr[1] = Dr.b;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
+  /* J_r1 at (i, j+1/2): even for mode 1 (row -1/2 folds onto +1/2) */
+  for (int a = 0; a < Px.n; ++a)
+    for (int b = 0; b < Dr.n; ++b) {
       int i = Px.i + a, j = Dr.i + b;
-      if (j == -1) j = 0;
+      if (j < 0) j = mirror_row(j, HALF_R);
       if (i < 0 || i > Nx || j < 0 || j > Nr - 1) continue;
-      s.Jr1[s.at(i, j)] += 2.0 * q * w * vr * wx[a] * wr[b] * e / vol_half(s, j);
+      s.Jr1[s.at(i, j)] += 2.0 * q * w * vr * Px.w[a] * Dr.w[b] * e / vol_half(s, j);
     }
-  /* J_t1 at (i, j) */
-  wx[0] = Px.a; wx[1] = Px.b; wr[0] = Pr.a; wr[1] = Pr.b;
-  for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) {
+  /* J_t1 at (i, j): even for mode 1 */
+  for (int a = 0; a < Px.n; ++a)
+    for (int b = 0; b < Pr.n; ++b) {
       int i = Px.i + a, j = Pr.i + b;
+      if (j < 0) j = mirror_row(j, PRIMAL_R);
       if (i < 0 || i > Nx || j < 0 || j > Nr) continue;
-      s.Jt1[s.at(i, j)] += 2.0 * q * w * vt * wx[a] * wr[b] * e / vol_node(s, j);
+      s.Jt1[s.at(i, j)] += 2.0 * q * w * vt * Px.w[a] * Pr.w[b] * e / vol_node(s, j);
     }
 }
 
@@ -457,7 +494,7 @@ void position_J(Sim& s) {
   for (size_t k = 0; k < np; ++k) {
     double ux = s.x[k] / dx - (double)s.shift;
     double r = std::sqrt(s.y[k] * s.y[k] + s.z[k] * s.z[k]);
-    double ph = interp(s, phh, primal(ux), primal(r / dr), Nx, Nr, 1.0);
+    double ph = interp(s, phh, primal(s, ux), primal(s, r / dr), Nx, Nr, PRIMAL_R, 1.0);
     double p[3] = {s.px[k], s.py[k], s.pz[k]};
     double g = std::sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + ph);
     double v[3] = {p[0] / g, p[1] / g, p[2] / g};
@@ -725,6 +762,7 @@ bool check_params(const oracle_params* p) {
   if (!(p->dt < p->dx && p->dt < p->dr)) return false;
   if (p->start_col < 0) return false;
   if (p->filter_passes < 0 || p->filter_passes > 64) return false;
+  if (p->shape_order < 0 || p->shape_order > 2) return false;
   return true;
 }
 

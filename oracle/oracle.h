@@ -48,6 +48,14 @@
  *   (R24)                  Fourier mode; linear and constant radial profiles
  *                          of each parity preserved through the axis ghost;
  *                          one pass at the x ends and at r_max (3/4)
+ *   quadratic shapes (R26) moments of the B-spline (1, u, u^2 + 1/4) on
+ *                          primal and half rows and along x; parity ghosts
+ *                          below the axis exact for fields linear or even-
+ *                          quadratic through it (mode 0 and 1); ponderomotive
+ *                          kick in Phi ~ r^2; chi sum rule with the axis
+ *                          fold; discrete Gauss law and continuity of the
+ *                          order-2 Esirkepov current with axis folds; mode-1
+ *                          J fold parity; moving window = static run
  *   step order, gbar and   documented choices with no value printed in the
  *   Phi centring (R6-R8)   paper: PARITY UNPINNED beyond the convergence
  *                          order the luminal test fixes.
@@ -95,7 +103,8 @@ typedef struct oracle_params {
   int64_t start_col;     /* lab column of the window's left edge at n = 0 (a slab
                             of a larger run: same positions, angles and ids) */
   int32_t filter_passes; /* passes of the 1-2-1 binomial filter on J (0: none) */
-  int32_t reserved;
+  int32_t shape_order;   /* particle shape for gather and deposit: 0 or 1 linear,
+                            2 quadratic (R26) */
 } oracle_params;
 
 /* grid identifiers (window-relative (nx+1) x (nr+1) arrays) */

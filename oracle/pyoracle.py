@@ -46,7 +46,7 @@ class OracleParams(ctypes.Structure):
         ("perturb", ctypes.c_double), ("bump_x", ctypes.c_double),
         ("bump_w", ctypes.c_double),
         ("start_col", ctypes.c_int64),
-        ("filter_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("filter_passes", ctypes.c_int32), ("shape_order", ctypes.c_int32),
     ]
 
 
@@ -121,6 +121,7 @@ def make_params(cfg):
     p.bump_w = float(cfg.get("bump_w", 1.0))
     p.start_col = int(cfg.get("start_col", 0))
     p.filter_passes = int(cfg.get("filter_passes", 0))
+    p.shape_order = int(cfg.get("shape_order", 1))
     return p
 
 

@@ -194,12 +194,14 @@ def test_mode1_deposit_phase_matches_gather(oracle_mod):
     assert np.abs(s.get_field("jt1")).max() < 1e-15 * np.abs(jr1).max()
 
 
-def test_moving_window_equals_static_longer_box(oracle_mod):
+@pytest.mark.parametrize("order", [1, 2])
+def test_moving_window_equals_static_longer_box(oracle_mod, order):
     """A run whose window follows the pulse equals a static run in a box that
     is longer by the number of shifts, on the columns both hold (away from the
-    left edge, where particles leave, and the leading edge)."""
+    left edge, where particles leave, and the leading edge); both shape
+    orders."""
     base = dict(nr=12, profile="uniform", n0=0.004, ppc=(2, 2, 2), a0=1.2, w0=8.0,
-                tau=6.0, x_c=25.6, x_f=25.6)
+                tau=6.0, x_c=25.6, x_f=25.6, shape_order=order)
     nsteps = 40
     A = oracle_mod.OracleSim(_cfg(nx=64, moving_window=1, **base))
     A.step(nsteps)
