@@ -192,6 +192,8 @@ def main():
     ap.add_argument("--serving-budget-gib", type=float, default=4.0)
     ap.add_argument("--filter-passes", type=int, default=0,
                     help="binomial current filter passes (the paper's nonlinear benchmark uses 7)")
+    ap.add_argument("--shape-order", type=int, default=1, choices=[1, 2],
+                    help="particle shape order of gather and deposit (2: quadratic B-spline)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB, 10 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -221,6 +223,8 @@ def main():
     cfg = {"c2": C2, "c3": C3, "c5": C5}[args.workload]
     if args.filter_passes:
         cfg = dict(cfg, filter_passes=args.filter_passes, name=f"{cfg['name']}_filter{args.filter_passes}")
+    if args.shape_order == 2:
+        cfg = dict(cfg, shape_order=2, name=f"{cfg['name']}_order2")
     E.lib()
     torch.cuda.set_device(0)
 
@@ -266,6 +270,7 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": cfg["name"], "grid": [cfg["nx"], cfg["nr"]], "modes": cfg["n_modes"],
                    "filter_passes": int(cfg.get("filter_passes", 0)),
+                   "shape_order": int(cfg.get("shape_order", 1)),
                    "ppc": list(cfg["ppc"]), "particles": int(r32["particles"]),
                    "moving_window": bool(cfg["moving_window"]), "precision": "fp32-bulk (fp64 axis rows)"},
         "roofline": roofline,

@@ -92,7 +92,10 @@ typedef struct envpic_params {
   int32_t filter_passes;   /* passes of the 1-2-1 binomial filter on J (0: none, at most
                               ENVPIC_FILTER_MAX, below nx/2 and nr/2); each pass
                               smooths along x, then r */
-  int32_t reserved;        /* 0 */
+  int32_t shape_order;     /* particle shape of gather and deposit: 0 or 1 linear
+                              (cloud in cell), 2 quadratic B-spline (Sec. 4's
+                              nonlinear benchmark configuration); order 2 re-sorts
+                              every second step and has no deferred deposits */
 } envpic_params;
 #define ENVPIC_FILTER_MAX 8
 

@@ -91,6 +91,7 @@ int validate(const envpic_params* p) {
     return fail(ENVPIC_EINVAL, "filter_passes must be in [0, ENVPIC_FILTER_MAX]");
   if (p->filter_passes > 0 && (p->nx <= 2 * p->filter_passes || p->nr <= 2 * p->filter_passes))
     return fail(ENVPIC_EINVAL, "the binomial filter needs nx and nr above twice its passes");
+  if (p->shape_order < 0 || p->shape_order > 2) return fail(ENVPIC_EINVAL, "shape_order must be 0, 1 (linear) or 2 (quadratic)");
   if (p->n0 < 0) return fail(ENVPIC_EINVAL, "n0 must be >= 0");
   if (p->profile == ENVPIC_PROFILE_RAMP && !(p->ramp_len > 0)) return fail(ENVPIC_EINVAL, "ramp_len must be > 0");
   if (p->profile == ENVPIC_PROFILE_BUMP && !(p->bump_w > 0)) return fail(ENVPIC_EINVAL, "bump_w must be > 0");
@@ -390,7 +391,11 @@ struct envpic_sim {
   virtual int clear_deposits() = 0;
 
   // the momentum stage of the next step re-sorts the particles
-  bool presort() const { return n + 1 - sorted_at >= SORT_EVERY; }
+  // Steps between sorts: particles drift at most one cell per step, and the
+  // LDS halo holds SORT_EVERY cells of drift plus the linear stencil, or
+  // SORT_EVERY - 1 cells plus the wider quadratic one.
+  int sort_every() const { return p.shape_order == 2 ? SORT_EVERY - 1 : SORT_EVERY; }
+  bool presort() const { return n + 1 - sorted_at >= sort_every(); }
   bool shift_due() const {
     return p.moving_window && (double)(n + 1) * p.dt >= (double)(shift + 1) * p.dx;
   }
@@ -450,6 +455,7 @@ template <class R> struct SimT : envpic_sim {
     g.dr = p.dr;
     g.dt = p.dt;
     g.chunk = sz.chunk;
+    g.order = p.shape_order == 2 ? 2 : 1;
     // fixed-point scale of the mode-1 current sums: 2^49 over the largest
     // |2 q w v S / V| = 2 w_max / V_0, V_0 = pi dr^2 dx / 4
     const double cmax = 2.0 * wmax * 4.0 / (3.14159265358979323846 * p.dr * p.dr * p.dx);
@@ -564,9 +570,9 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 0) return fail(ENVPIC_EORDER, "momentum stage out of order");
     const Geo g = geo();
     const int d = (int)(n & 1);
-    // re-sort when the particles have had SORT_EVERY steps to drift from
+    // re-sort when the particles have had sort_every() steps to drift from
     // their tiles; in between, p is updated in place
-    const bool scatter = n - sorted_at >= SORT_EVERY;
+    const bool scatter = n - sorted_at >= sort_every();
     // every CELL_SORT_EVERY-th sort orders the tiles by cell again
     const int mode = !scatter ? SCAT_NONE : (n_sorts % CELL_SORT_EVERY == 0 ? SCAT_CELL : SCAT_TILE);
     tick_begin();
@@ -1058,6 +1064,8 @@ int envpic_gather_push(envpic_sim* s, int stage) {
   if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
   const bool defer = (stage & ENVPIC_DEFER_DEPOSIT) != 0;
   stage &= ~ENVPIC_DEFER_DEPOSIT;
+  if (defer && s->p.shape_order == 2)
+    return fail(ENVPIC_EINVAL, "deferred deposits are built for linear shapes only");
   if (stage == ENVPIC_MOMENTUM) return s->momentum(defer);
   if (stage == ENVPIC_POSITION) return s->position(defer);
   return fail(ENVPIC_EINVAL, "stage must be ENVPIC_MOMENTUM or ENVPIC_POSITION");

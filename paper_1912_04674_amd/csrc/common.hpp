@@ -76,6 +76,7 @@ struct Geo {
   float fix0;        // fixed-point scale of the FP32 path's chi and mode-0 current sums
   double unfix0;     // 1 / fix0
   int chunk;         // particles per work item at most (<= CHUNK, a multiple of WG)
+  int order;         // particle shape order: 1 linear, 2 quadratic
 };
 
 template <class R> struct Parts {

@@ -50,6 +50,43 @@ template <class C, class R> __device__ inline C interp2c(const C* a, Lin<R> sx, 
                w00 * v00.y + w01 * v01.y + w10 * v10.y + w11 * v11.y);
 }
 
+// Quadratic B-spline (order 2) on three nodes i, i+1, i+2 around the nearest
+// node m = i + 1, d = u - m in [-1/2, 1/2): (1/2 - d)^2/2, 3/4 - d^2,
+// (1/2 + d)^2/2.  Primal nodes sit at the cell corners (nearest node a or
+// a + 1), dual nodes at the cell centres (nearest node always a).
+template <class R> struct Quad {
+  int i;
+  R w[3];
+};
+template <class R> __device__ inline Quad<R> quad_of(int i, R d) {
+  const R l = (R)0.5 - d, h = (R)0.5 + d;
+  return Quad<R>{i, {(R)0.5 * l * l, (R)0.75 - d * d, (R)0.5 * h * h}};
+}
+template <class R> __device__ inline Quad<R> quad_primal(int c, R f) {
+  return f < (R)0.5 ? quad_of<R>(c - 1, f) : quad_of<R>(c, f - (R)1);
+}
+template <class R> __device__ inline Quad<R> quad_dual(int c, R f) { return quad_of<R>(c - 1, f - (R)0.5); }
+
+template <class R> __device__ inline R interp3(const R* a, const Quad<R>& sx, const Quad<R>& sr) {
+  R acc = 0;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const R* col = a + (sx.i + u) * LR + sr.i;
+    acc += sx.w[u] * (sr.w[0] * col[0] + sr.w[1] * col[1] + sr.w[2] * col[2]);
+  }
+  return acc;
+}
+template <class C, class R> __device__ inline C interp3c(const C* a, const Quad<R>& sx, const Quad<R>& sr) {
+  R re = 0, im = 0;
+#pragma unroll
+  for (int u = 0; u < 3; ++u) {
+    const C* col = a + (sx.i + u) * LR + sr.i;
+    re += sx.w[u] * (sr.w[0] * col[0].x + sr.w[1] * col[1].x + sr.w[2] * col[2].x);
+    im += sx.w[u] * (sr.w[0] * col[0].y + sr.w[1] * col[1].y + sr.w[2] * col[2].y);
+  }
+  return mk<C>(re, im);
+}
+
 __device__ inline int clampi(int v, int lo, int hi, bool& bad) {
   if (v < lo) { bad = true; return lo; }
   if (v > hi) { bad = true; return hi; }
@@ -267,7 +304,9 @@ __device__ inline int item_of(int b, int n) {
 // tile by cell and places every work item as at loading, so that the lanes
 // of a wavefront hold particles of distinct cells again (the deposits'
 // LDS atomics do not collide), at the price of strided writes.
-template <class R, bool M1, bool DEFER, int SCAT>
+// O: particle shape order (1 linear, 2 quadratic; order 2 re-sorts every
+// second step, so its wider stencil stays inside the same halo).
+template <class R, bool M1, bool DEFER, int SCAT, int O>
 __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restrict__ chi_out,
                                                  Parts<R> src, Parts<R> dst, Layout Ls, Layout Ld,
                                                  int* __restrict__ ccur, R* __restrict__ gscr, int* err) {
@@ -285,32 +324,36 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   // value is selected afterwards; outside the grid the value is zero, and on
   // the ghost row j = -1 the radial-staggered values mirror row 1/2 with the
   // parity of the component (odd for mode-0 E_r and Bbar_t and mode-1 B_x).
+  // The quadratic stencil also reaches the primal ghost row j = -1, which
+  // mirrors row 1 (odd: mode-1 E_x; even: the others).
   for (int k = threadIdx.x; k < LN; k += WG) {
     const int a = k / LR, b = k - (k / LR) * LR;
     const int rel = q.relX0 + a, j = q.R0 + b;
     const bool px = rel >= 0 && rel <= g.nx, dxok = rel >= 0 && rel <= g.nx - 1;
     const size_t o = (px || dxok) ? (size_t)phys_col(g, rel) * g.pitch : 0;
     const bool pr = j >= 0 && j <= g.nr, drok = j >= 0 && j <= g.nr - 1, ghost = j == -1;
-    const size_t in = pr ? o + j : o;                  // primal row (clamped)
+    const bool pg = O == 2 && ghost && g.nr >= 1;      // primal ghost row (order 2)
+    const bool pv = pr || pg;
+    const size_t in = pr ? o + j : (pg ? o + 1 : o);   // primal row (clamped), ghost -> row 1
     const size_t ih = drok ? o + j : o;                // half row, ghost -> row 1/2
     const R hs = drok ? (R)1 : (ghost ? (R)-1 : (R)0); // odd parity on the ghost row
     const R hp = drok ? (R)1 : (ghost ? (R)1 : (R)0);  // even parity on the ghost row
     const R vex = f.ex[in], ver = f.er[ih], vbt = f.btb[ih];
     const C venv = f.env[in];
-    sm.ex[k] = (dxok && pr) ? vex : (R)0;
+    sm.ex[k] = (dxok && pv) ? vex : (R)0;
     sm.er[k] = px ? hs * ver : (R)0;
     sm.bt[k] = dxok ? hs * vbt : (R)0;
-    sm.phi[k] = (px && pr) ? (R)0.5 * cnorm(venv) : (R)0;
+    sm.phi[k] = (px && pv) ? (R)0.5 * cnorm(venv) : (R)0;
     sm.chi[k] = 0;
     if (M1) {
       const C z = mk<C>((R)0, (R)0);
       const C e1 = f.ex1[in], r1 = f.er1[ih], t1 = f.et1[in];
       const C bx = f.bxb1[ih], br = f.brb1[in], bt = f.btb1[ih];
-      sm.ex1[k] = (dxok && pr) ? e1 : z;
+      sm.ex1[k] = (dxok && pv) ? (pg ? cscale(e1, (R)-1) : e1) : z;
       sm.er1[k] = px ? cscale(r1, hp) : z;
-      sm.et1[k] = (px && pr) ? t1 : z;
+      sm.et1[k] = (px && pv) ? t1 : z;
       sm.bx1[k] = px ? cscale(bx, hs) : z;
-      sm.br1[k] = (dxok && pr) ? br : z;
+      sm.br1[k] = (dxok && pv) ? br : z;
       sm.bt1[k] = dxok ? cscale(bt, hp) : z;
     }
   }
@@ -330,7 +373,10 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
       R vx = 0, vr = 0;
       if (a >= 1 && a <= LX - 2 && b >= 1 && b <= LR - 2) {
         vx = (sm.phi[k + LR] - sm.phi[k - LR]) * i2dx;
-        if (q.R0 + b != 0) vr = (sm.phi[k + 1] - sm.phi[k - 1]) * i2dr;
+        if (O == 2 && q.R0 + b == -1)  // odd below the axis: minus the value on row 1
+          vr = -((sm.phi[k + 3] - sm.phi[k + 1]) * i2dr);
+        else if (q.R0 + b != 0)
+          vr = (sm.phi[k + 1] - sm.phi[k - 1]) * i2dr;
       }
       sm.gx[k] = vx;
       sm.gr[k] = vr;
@@ -425,26 +471,52 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     }
     const R fx = src.fx[p], fr = src.fr[p], th = src.th[p], w = src.w[p];
     R pv[3] = {src.px[p], src.py[p], src.pz[p]};
-    const int a = clampi(cell_ix(cw) - q.X0, 1, LX - 3, bad);
-    const int b = clampi(cell_jr(cw) - q.R0, 1, LR - 3, bad);
-    const Lin<R> Px = primal_w<R>(a, fx), Dx = dual_w<R>(a, fx);
-    const Lin<R> Pr = primal_w<R>(b, fr), Dr = dual_w<R>(b, fr);
+    // the cell relative to the region: [1, LX - 3] for the linear stencils;
+    // order 2 (two steps of drift at most) keeps [2, LX - 4], the range its
+    // position pass needs for the current stencil of the old and new cells
+    const int a = O == 2 ? clampi(cell_ix(cw) - q.X0, 2, LX - 4, bad) : clampi(cell_ix(cw) - q.X0, 1, LX - 3, bad);
+    const int b = O == 2 ? clampi(cell_jr(cw) - q.R0, 2, LR - 4, bad) : clampi(cell_jr(cw) - q.R0, 1, LR - 3, bad);
     R s, c;
     sincos_r(th, &s, &c);
-    R ex = interp2<R>(sm.ex, Dx, Pr);
-    R er = interp2<R>(sm.er, Px, Dr);
-    R bt = interp2<R>(sm.bt, Dx, Dr);
-    R et = 0, bx = 0, br = 0;
-    const R ph = interp2<R>(sm.phi, Px, Pr);
-    const R gx = interp2<R>(sm.gx, Px, Pr);
-    const R gr = interp2<R>(sm.gr, Px, Pr);
-    if (M1) {
-      ex += mode1_at<C, R>(interp2c<C, R>(sm.ex1, Dx, Pr), c, s);
-      er += mode1_at<C, R>(interp2c<C, R>(sm.er1, Px, Dr), c, s);
-      et = mode1_at<C, R>(interp2c<C, R>(sm.et1, Px, Pr), c, s);
-      bx = mode1_at<C, R>(interp2c<C, R>(sm.bx1, Px, Dr), c, s);
-      br = mode1_at<C, R>(interp2c<C, R>(sm.br1, Dx, Pr), c, s);
-      bt += mode1_at<C, R>(interp2c<C, R>(sm.bt1, Dx, Dr), c, s);
+    R ex, er, bt, et = 0, bx = 0, br = 0, ph, gx, gr;
+    Lin<R> Px, Pr;
+    Quad<R> Qx, Qr;
+    if constexpr (O == 2) {
+      Qx = quad_primal<R>(a, fx);
+      Qr = quad_primal<R>(b, fr);
+      const Quad<R> Ux = quad_dual<R>(a, fx), Ur = quad_dual<R>(b, fr);
+      ex = interp3<R>(sm.ex, Ux, Qr);
+      er = interp3<R>(sm.er, Qx, Ur);
+      bt = interp3<R>(sm.bt, Ux, Ur);
+      ph = interp3<R>(sm.phi, Qx, Qr);
+      gx = interp3<R>(sm.gx, Qx, Qr);
+      gr = interp3<R>(sm.gr, Qx, Qr);
+      if (M1) {
+        ex += mode1_at<C, R>(interp3c<C, R>(sm.ex1, Ux, Qr), c, s);
+        er += mode1_at<C, R>(interp3c<C, R>(sm.er1, Qx, Ur), c, s);
+        et = mode1_at<C, R>(interp3c<C, R>(sm.et1, Qx, Qr), c, s);
+        bx = mode1_at<C, R>(interp3c<C, R>(sm.bx1, Qx, Ur), c, s);
+        br = mode1_at<C, R>(interp3c<C, R>(sm.br1, Ux, Qr), c, s);
+        bt += mode1_at<C, R>(interp3c<C, R>(sm.bt1, Ux, Ur), c, s);
+      }
+    } else {
+      Px = primal_w<R>(a, fx);
+      Pr = primal_w<R>(b, fr);
+      const Lin<R> Dx = dual_w<R>(a, fx), Dr = dual_w<R>(b, fr);
+      ex = interp2<R>(sm.ex, Dx, Pr);
+      er = interp2<R>(sm.er, Px, Dr);
+      bt = interp2<R>(sm.bt, Dx, Dr);
+      ph = interp2<R>(sm.phi, Px, Pr);
+      gx = interp2<R>(sm.gx, Px, Pr);
+      gr = interp2<R>(sm.gr, Px, Pr);
+      if (M1) {
+        ex += mode1_at<C, R>(interp2c<C, R>(sm.ex1, Dx, Pr), c, s);
+        er += mode1_at<C, R>(interp2c<C, R>(sm.er1, Px, Dr), c, s);
+        et = mode1_at<C, R>(interp2c<C, R>(sm.et1, Px, Pr), c, s);
+        bx = mode1_at<C, R>(interp2c<C, R>(sm.bx1, Px, Dr), c, s);
+        br = mode1_at<C, R>(interp2c<C, R>(sm.br1, Dx, Pr), c, s);
+        bt += mode1_at<C, R>(interp2c<C, R>(sm.bt1, Dx, Dr), c, s);
+      }
     }
     // (x, r, theta) -> Cartesian, r-hat = (0, c, s), theta-hat = (0, -s, c)
     const R E[3] = {ex, er * c - et * s, er * s + et * c};
@@ -471,6 +543,16 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     pv[2] = pm[2] + pp[0] * sv[1] - pp[1] * sv[0] + hdt * F[2];
     if (DEFER) {
       gscr[d] = (R)1 / igb;
+    } else if constexpr (O == 2) {
+      // rows below the axis are folded onto their mirrors at the flush
+      const R wg = w * igb * (R)Acc0<R>::scale(g);
+#pragma unroll
+      for (int aa = 0; aa < 3; ++aa) {
+        const double wa = (double)(wg * Qx.w[aa]);
+#pragma unroll
+        for (int bb = 0; bb < 3; ++bb)
+          Acc0<R>::add_prod(&sm.chi[(Qx.i + aa) * LR + Qr.i + bb], wa, (double)Qr.w[bb]);
+      }
     } else {
       const R wg = w * igb * (R)Acc0<R>::scale(g);
 #pragma unroll
@@ -501,11 +583,14 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   if (DEFER) return;
   __syncthreads();
   for (int k = threadIdx.x; k < LN; k += WG) {
-    if (sm.chi[k] == 0) continue;
     const int a = k / LR, b = k - (k / LR) * LR;
     const int rel = q.relX0 + a, j = q.R0 + b;
+    typename Acc0<R>::T v = sm.chi[k];
+    // order 2: the row below the axis (two LDS rows down) belongs to row 1
+    if (O == 2 && j == 1 && b >= 2) v += sm.chi[k - 2];
+    if (v == 0) continue;
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
-    atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], (R)(Acc0<R>::val(sm.chi[k], g) * sm.ivol[b]));
+    atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], (R)(Acc0<R>::val(v, g) * sm.ivol[b]));
   }
 }
 
@@ -698,6 +783,139 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
   }
 }
 
+// Order-2 currents: the Esirkepov decomposition of the change between the
+// old and new quadratic stencils on their 4-node union (mode 0), and the
+// quadratic mid-point deposit of mode 1.  Contributions to the rows below
+// the axis stay in the LDS ghost rows and are folded at the flush, except
+// the mode-1 J_r of the half row -1/2, which lands on +1/2 directly (even).
+template <class R, bool M1>
+__device__ inline void deposit_current2(SmemPos<R, M1>& sm, const Region& q, const Geo& g, const Move<R>& mv, R w,
+                                        bool& bad) {
+  const int a0 = clampi(mv.ix0 - q.X0, 2, LX - 4, bad);
+  const int a1 = clampi(mv.ix1 - q.X0, a0 - 1, a0 + 1, bad);
+  const int b0 = clampi(mv.jr0 - q.R0, 2, LR - 4, bad);
+  const int b1 = clampi(mv.jr1 - q.R0, b0 - 1, b0 + 1, bad);
+  const Quad<R> X0 = quad_primal<R>(a0, mv.fx0), X1 = quad_primal<R>(a1, mv.fx1);
+  const Quad<R> Y0 = quad_primal<R>(b0, mv.fr0), Y1 = quad_primal<R>(b1, mv.fr1);
+  // nearest nodes move by at most one (less than a cell per step)
+  const int ax = min(X0.i, X1.i), by = min(Y0.i, Y1.i);
+  const int ox0 = clampi(X0.i - ax, 0, 1, bad), ox1 = clampi(X1.i - ax, 0, 1, bad);
+  const int or0 = clampi(Y0.i - by, 0, 1, bad), or1 = clampi(Y1.i - by, 0, 1, bad);
+  // the stencils on the union (placed without indexing register arrays)
+  auto place = [](const Quad<R>& Q, int o, R* S) {
+    S[0] = o ? (R)0 : Q.w[0];
+    S[1] = o ? Q.w[0] : Q.w[1];
+    S[2] = o ? Q.w[1] : Q.w[2];
+    S[3] = o ? Q.w[2] : (R)0;
+  };
+  R S0x[4], S1x[4], S0r[4], S1r[4];
+  place(X0, ox0, S0x);
+  place(X1, ox1, S1x);
+  place(Y0, or0, S0r);
+  place(Y1, or1, S1r);
+  // partial sums of the change from the low side (the fourth is zero)
+  R cx[3], cr[3];
+  cx[0] = S1x[0] - S0x[0];
+  cr[0] = S1r[0] - S0r[0];
+#pragma unroll
+  for (int k = 1; k < 3; ++k) {
+    cx[k] = cx[k - 1] + (S1x[k] - S0x[k]);
+    cr[k] = cr[k - 1] + (S1r[k] - S0r[k]);
+  }
+  using A0 = Acc0<R>;
+  typename A0::T* jx = &sm.jx[ax * LR + by];
+  typename A0::T* jr = &sm.jr[ax * LR + by];
+  const double hw = 0.5 * (double)w * A0::scale(g);
+#pragma unroll
+  for (int bb = 0; bb < 4; ++bb) {
+    const double sr = (double)(S0r[bb] + S1r[bb]) * hw;
+#pragma unroll
+    for (int aa = 0; aa < 3; ++aa)
+      if (cx[aa] != (R)0) A0::add_prod(&jx[aa * LR + bb], (double)cx[aa], sr);
+  }
+#pragma unroll
+  for (int aa = 0; aa < 4; ++aa) {
+    const double sx = (double)(S0x[aa] + S1x[aa]) * hw;
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb)
+      if (cr[bb] != (R)0) A0::add_prod(&jr[aa * LR + bb], (double)cr[bb], sx);
+  }
+  if (M1) {
+    // mid-point as in the linear deposit
+    const R dr = (R)g.dr;
+    const R r0 = ((R)mv.jr0 + mv.fr0) * dr;
+    int jm = mv.jr0;
+    R frm, c, s;
+    if (!mv.refl) {
+      const R u = r0 + (R)0.5 * mv.a, v = (R)0.5 * mv.b;
+      R cd, sd;
+      if (u > (R)0) {
+        const R beta = v * rcp_r(u);
+        const R qq = sqrt_r((R)1 + beta * beta);
+        frm = mv.fr0 + ((R)0.5 * mv.a + u * beta * beta * rcp_r((R)1 + qq)) * (R)(1.0 / g.dr);
+        cd = rcp_r(qq);
+        sd = beta * cd;
+      } else {
+        const R rm = sqrt_r(u * u + v * v);
+        frm = mv.fr0 + (rm - r0) / dr;
+        cd = rm > (R)0 ? u / rm : (R)1;
+        sd = rm > (R)0 ? v / rm : (R)0;
+      }
+      c = mv.c0 * cd - mv.s0 * sd;
+      s = mv.s0 * cd + mv.c0 * sd;
+    } else {
+      R s1, c1;
+      sincos_r(mv.th1, &s1, &c1);
+      const R r1 = ((R)mv.jr1 + mv.fr1) * dr;
+      const R ym = (R)0.5 * (r0 * mv.c0 + r1 * c1), zm = (R)0.5 * (r0 * mv.s0 + r1 * s1);
+      const R rm = sqrt_r(ym * ym + zm * zm);
+      jm = 0;
+      frm = rm / dr;
+      c = rm > (R)0 ? ym / rm : (R)1;
+      s = rm > (R)0 ? zm / rm : (R)0;
+    }
+    carry(jm, frm);
+    if (jm < 0) {
+      jm = 0;
+      frm = 0;
+    }
+    if (jm > g.nr - 1) {
+      frm += (R)(jm - (g.nr - 1));
+      jm = g.nr - 1;
+    }
+    const R um = (R)0.5 * ((R)a0 + mv.fx0 + (R)a1 + mv.fx1);
+    const int am = (int)floor(um);
+    const R fm = um - (R)am;
+    const int bm = clampi(jm - q.R0, 1, LR - 3, bad);
+    const int amc = clampi(am, 1, LX - 3, bad);
+    const Quad<R> Qx = quad_primal<R>(amc, fm), Ux = quad_dual<R>(amc, fm);
+    const Quad<R> Qr = quad_primal<R>(bm, frm), Ur = quad_dual<R>(bm, frm);
+    const R q2 = (R)-2 * w * Acc1<R>::scale(g);
+    const R vx = q2 * mv.vx, vr = q2 * (mv.vy * c + mv.vz * s), vt = q2 * (mv.vz * c - mv.vy * s);
+    const double xc = vx * c, xs = vx * s, rc = vr * c, rs = vr * s, tc = vt * c, ts = vt * s;
+    // radial weights times the inverse volume of the row they land on (the
+    // primal ghost row carries row 1's); the half row -1/2 is row +1/2
+    R pv[3], dv[3];
+    int dn[3];
+#pragma unroll
+    for (int bb = 0; bb < 3; ++bb) {
+      pv[bb] = Qr.w[bb] * sm.ivn[Qr.i + bb];
+      dn[bb] = (q.R0 + Ur.i + bb == -1) ? Ur.i + bb + 1 : Ur.i + bb;
+      dv[bb] = Ur.w[bb] * sm.ivh[dn[bb]];
+    }
+#pragma unroll
+    for (int aa = 0; aa < 3; ++aa) {
+#pragma unroll
+      for (int bb = 0; bb < 3; ++bb) {
+        const double ux = Ux.w[aa] * pv[bb], ur = Qx.w[aa] * dv[bb], ut = Qx.w[aa] * pv[bb];
+        Acc1<R>::add_prod(&sm.jx1[(Ux.i + aa) * LR + Qr.i + bb], ux, xc, xs);  // (i+1/2, j)
+        Acc1<R>::add_prod(&sm.jr1[(Qx.i + aa) * LR + dn[bb]], ur, rc, rs);     // (i, j+1/2)
+        Acc1<R>::add_prod(&sm.jt1[(Qx.i + aa) * LR + Qr.i + bb], ut, tc, ts);  // (i, j)
+      }
+    }
+  }
+}
+
 template <class R, bool M1>
 __device__ inline void stage_pos_constants(SmemPos<R, M1>& sm, const Region& q, const Geo& g) {
   const double pi = 3.14159265358979323846;
@@ -708,7 +926,9 @@ __device__ inline void stage_pos_constants(SmemPos<R, M1>& sm, const Region& q, 
     double ar = 2.0 * pi * (j + 0.5) * g.dr * g.dx;
     sm.iax[k] = (j >= 0 && j <= g.nr) ? (R)(1.0 / (ax * g.dt)) : (R)0;
     sm.iar[k] = (j >= 0 && j <= g.nr - 1) ? (R)(1.0 / (ar * g.dt)) : (R)0;
-    sm.ivn[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (R)0;
+    // the primal ghost row j = -1 carries the volume of row 1, onto which
+    // its (order-2) deposits are folded
+    sm.ivn[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (j == -1 ? inv_vol_node<R>(g, 1) : (R)0);
     sm.ivh[k] = (j >= 0 && j <= g.nr - 1) ? inv_vol_half<R>(g, j) : (R)0;
   }
 }
@@ -727,7 +947,18 @@ __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
   for (int k = threadIdx.x; k < CRN; k += WG) sm.ccell[k] = 0;
 }
 
-template <class R, bool M1>
+// a + sg b of two mode-1 accumulator words (exact for the fixed point)
+template <class T> __device__ inline T acc_axpy(T a, const T& b, int sg) {
+  a.x += sg * b.x;
+  a.y += sg * b.y;
+  return a;
+}
+
+// O = 2: the deposits on the rows below the axis are folded onto their
+// mirrors with the component's parity (R23): J_x row -1 onto row 1 (even for
+// mode 0, odd for mode 1), J_r face -1/2 onto +1/2 (odd for mode 0), mode-1
+// J_theta row -1 onto row 1 (even).
+template <class R, bool M1, int O>
 __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const Geo& g, R* jx_out,
                                      R* jr_out, typename cplx_of<R>::type* jx1_out,
                                      typename cplx_of<R>::type* jr1_out,
@@ -738,21 +969,30 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
     const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
     const bool dxok = rel <= g.nx - 1, drok = j <= g.nr - 1;
-    if (dxok && sm.jx[k] != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(sm.jx[k], g) * sm.iax[b]));
-    if (drok && sm.jr[k] != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(sm.jr[k], g) * sm.iar[b]));
+    const bool fold_row = O == 2 && j == 1 && b >= 2, fold_face = O == 2 && j == 0 && b >= 1;
+    typename Acc0<R>::T vjx = sm.jx[k], vjr = sm.jr[k];
+    if (fold_row) vjx += sm.jx[k - 2];
+    if (fold_face) vjr -= sm.jr[k - 1];
+    if (dxok && vjx != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(vjx, g) * sm.iax[b]));
+    if (drok && vjr != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(vjr, g) * sm.iar[b]));
     if (M1) {
       using A = Acc1<R>;
-      if (dxok && A::nonzero(sm.jx1[k])) {
-        atomicAdd(&jx1_out[o].x, (R)A::re(sm.jx1[k], g));
-        atomicAdd(&jx1_out[o].y, (R)A::im(sm.jx1[k], g));
+      typename A::T v1x = sm.jx1[k], v1t = sm.jt1[k];
+      if (fold_row) {
+        v1x = acc_axpy(v1x, sm.jx1[k - 2], -1);
+        v1t = acc_axpy(v1t, sm.jt1[k - 2], 1);
+      }
+      if (dxok && A::nonzero(v1x)) {
+        atomicAdd(&jx1_out[o].x, (R)A::re(v1x, g));
+        atomicAdd(&jx1_out[o].y, (R)A::im(v1x, g));
       }
       if (drok && A::nonzero(sm.jr1[k])) {
         atomicAdd(&jr1_out[o].x, (R)A::re(sm.jr1[k], g));
         atomicAdd(&jr1_out[o].y, (R)A::im(sm.jr1[k], g));
       }
-      if (A::nonzero(sm.jt1[k])) {
-        atomicAdd(&jt1_out[o].x, (R)A::re(sm.jt1[k], g));
-        atomicAdd(&jt1_out[o].y, (R)A::im(sm.jt1[k], g));
+      if (A::nonzero(v1t)) {
+        atomicAdd(&jt1_out[o].x, (R)A::re(v1t, g));
+        atomicAdd(&jt1_out[o].y, (R)A::im(v1t, g));
       }
     }
   }
@@ -857,7 +1097,7 @@ __device__ void inject_block(const InjectArgs& ia, Parts<R> P, const Layout& L, 
 // column is the window's first one are dropped after depositing);
 // count_cells: 1 when the particles are re-sorted at the next step (their
 // new cells are counted into ccount)
-template <class R, bool M1, bool DEFER>
+template <class R, bool M1, bool DEFER, int O>
 __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restrict__ jx_out,
                                                  R* __restrict__ jr_out,
                                                  typename cplx_of<R>::type* __restrict__ jx1_out,
@@ -879,10 +1119,12 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
   const int start = it.y, count = it.z;
   const Region q = region_of(g, it.x);
 
-  // Phi^{n+1/2} = (|A^{n+1}|^2 + |A^n|^2)/4 on the primal nodes
+  // Phi^{n+1/2} = (|A^{n+1}|^2 + |A^n|^2)/4 on the primal nodes (order 2:
+  // the ghost row j = -1 mirrors row 1, even)
   for (int k = threadIdx.x; k < LN; k += WG) {
     const int a = k / LR, b = k - (k / LR) * LR;
-    const int rel = q.relX0 + a, j = q.R0 + b;
+    const int rel = q.relX0 + a, j0 = q.R0 + b;
+    const int j = (O == 2 && j0 == -1) ? 1 : j0;
     R v = 0;
     if (rel >= 0 && rel <= g.nx && j >= 0 && j <= g.nr) {
       const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
@@ -925,9 +1167,16 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
     const R fx = cur.fx, fr = cur.fr, th = cur.th, w = cur.w;
     const R px = cur.px;
     R py = cur.py, pz = cur.pz;
-    const int a = clampi(cell_ix(cw) - q.X0, 0, LX - 2, bad);
-    const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
-    const R ph = interp2<R>(sm.phh, primal_w<R>(a, fx), primal_w<R>(b, fr));
+    R ph;
+    if constexpr (O == 2) {
+      const int a = clampi(cell_ix(cw) - q.X0, 2, LX - 4, bad);
+      const int b = clampi(cell_jr(cw) - q.R0, 2, LR - 4, bad);
+      ph = interp3<R>(sm.phh, quad_primal<R>(a, fx), quad_primal<R>(b, fr));
+    } else {
+      const int a = clampi(cell_ix(cw) - q.X0, 0, LX - 2, bad);
+      const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
+      ph = interp2<R>(sm.phh, primal_w<R>(a, fx), primal_w<R>(b, fr));
+    }
     const R ig = rsqrt_r((R)1 + px * px + py * py + pz * pz + ph);
     Move<R> mv;
     push_position<R>(g, cw, fx, fr, th, py, pz, px * ig, py * ig, pz * ig, mv);
@@ -946,6 +1195,8 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
       scr.fr[p] = fr;
       scr.th[p] = th;
       scr.w[p] = mv.refl ? -ig : ig;
+    } else if constexpr (O == 2) {
+      deposit_current2<R, M1>(sm, q, g, mv, w, bad);
     } else {
       deposit_current<R, M1>(sm, q, g, mv, w, bad);
     }
@@ -965,7 +1216,7 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
   }
   if (bad) atomicOr(err, ERR_HALO);
   __syncthreads();
-  if (!DEFER) flush_current(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
+  if (!DEFER) flush_current<R, M1, O>(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
   if (count_cells) flush_cells(sm.ccell, q, g, ccount);
 }
 
@@ -1054,7 +1305,7 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
   }
   if (bad) atomicOr(err, ERR_HALO);
   __syncthreads();
-  flush_current(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
+  flush_current<R, M1, 1>(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
 }
 
 // initial loading of window cells in tile-major order (offsets per tile
@@ -1074,36 +1325,42 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
 }
 
 // ============================================================ launchers ==
-template <class R, bool M1, bool DEFER>
+template <class R, bool M1, bool DEFER, int O>
 static void launch_momentum_sc(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                                const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
                                int scatter, hipStream_t st) {
   if (scatter == SCAT_TILE)
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_TILE>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls,
-                       Ld, ccur, gscr, err);
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_TILE, O>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst,
+                       Ls, Ld, ccur, gscr, err);
   else if (scatter == SCAT_CELL)
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_CELL>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls,
-                       Ld, ccur, gscr, err);
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_CELL, O>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst,
+                       Ls, Ld, ccur, gscr, err);
   else
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_NONE>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst, Ls,
-                       Ld, ccur, gscr, err);
+    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_NONE, O>), dim3(grid), dim3(WG), 0, st, g, f, chi, src, dst,
+                       Ls, Ld, ccur, gscr, err);
 }
 
+// order 2 has no deferred-deposit variant (the library rejects the request)
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                      const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
                      int scatter, hipStream_t st) {
   if (grid <= 0) return;
-  if (g.modes >= 2) {
-    if (defer)
-      launch_momentum_sc<R, true, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+  if (g.order == 2) {
+    if (g.modes >= 2)
+      launch_momentum_sc<R, true, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
     else
-      launch_momentum_sc<R, true, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+  } else if (g.modes >= 2) {
+    if (defer)
+      launch_momentum_sc<R, true, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+    else
+      launch_momentum_sc<R, true, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
   } else {
     if (defer)
-      launch_momentum_sc<R, false, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
     else
-      launch_momentum_sc<R, false, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
   }
 }
 
@@ -1112,22 +1369,34 @@ template <class R> int inject_blocks(const Geo& g) {
   return (n + WG - 1) / WG;
 }
 
+template <class R, bool M1, bool DEFER, int O>
+static void launch_position_k(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P,
+                              const Layout& L, int* ccount, int vacate, int count_cells, const Parts<R>& scr,
+                              int* err, int grid, const InjectArgs& inj, hipStream_t st) {
+  hipLaunchKernelGGL((k_position<R, M1, DEFER, O>), dim3(grid + inj.blocks), dim3(WG), 0, st, g, f, d.jx, d.jr,
+                     d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+}
+
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
                      int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
                      const InjectArgs& inj, hipStream_t st) {
   if (grid <= 0) return;
-  const dim3 blocks(grid + inj.blocks);
-  if (g.modes >= 2) {
-    if (defer)
-      hipLaunchKernelGGL((k_position<R, true, true>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+  if (g.order == 2) {
+    if (g.modes >= 2)
+      launch_position_k<R, true, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
     else
-      hipLaunchKernelGGL((k_position<R, true, false>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+      launch_position_k<R, false, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+  } else if (g.modes >= 2) {
+    if (defer)
+      launch_position_k<R, true, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+    else
+      launch_position_k<R, true, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
   } else {
     if (defer)
-      hipLaunchKernelGGL((k_position<R, false, true>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+      launch_position_k<R, false, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
     else
-      hipLaunchKernelGGL((k_position<R, false, false>), blocks, dim3(WG), 0, st, g, f, d.jx, d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+      launch_position_k<R, false, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
   }
 }
 

@@ -55,7 +55,7 @@ class Params(ctypes.Structure):
         ("n0", ctypes.c_double), ("ramp_len", ctypes.c_double), ("perturb", ctypes.c_double),
         ("bump_x", ctypes.c_double), ("bump_w", ctypes.c_double),
         ("capacity", ctypes.c_int64),
-        ("filter_passes", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("filter_passes", ctypes.c_int32), ("shape_order", ctypes.c_int32),
     ]
 
 
@@ -148,6 +148,7 @@ def make_params(cfg):
     p.bump_w = float(cfg.get("bump_w", 1.0))
     p.capacity = int(cfg.get("capacity", 0))
     p.filter_passes = int(cfg.get("filter_passes", 0))
+    p.shape_order = int(cfg.get("shape_order", 0))
     return p
 
 
