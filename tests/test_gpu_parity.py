@@ -517,19 +517,19 @@ def test_graph_mode_matches_direct_launches(E, prec):
 
 
 # ------------------------------------------------ full-size sampled check --
-def _full_size_slab(E, oracle_mod, cfg, c0, w, steps):
+def _full_size_slab(E, oracle_mod, cfg, c0, w, steps, reach=1):
     """Run the whole workload on the GPU in the benchmark's launch
     configuration and an oracle replica of columns [c0, c0 + w) (same lab
     positions, angles, ids and window timing); compare grids and particles
-    outside the slab boundary's domain of dependence (every stencil reaches
-    one cell per step)."""
+    outside the slab boundary's domain of dependence (`reach` cells per
+    step: one for the linear stencils)."""
     g = E.Sim(cfg, E.FP32_BULK)
     g.step(steps)
     r = oracle_mod.OracleSim(scaled(cfg, nx=w, start_col=c0))
     r.step(steps)
     (gn, gs, _), (rn, rs, _) = g.state(), r.state()
     assert gn == rn and rs == c0 + gs  # the oracle's shift counts lab columns from its slab start
-    lo, hi = steps + 4, w - steps - 4
+    lo, hi = reach * steps + 4, w - reach * steps - 4
     if c0 + w == cfg["nx"]:
         hi = w  # the slab shares the window's leading edge (same boundary, same injection)
     for n in ("env", "chi", "ex", "er", "bt", "jx", "jr") + (("ex1", "er1", "bt1", "jx1") if cfg["n_modes"] > 1 else ()):

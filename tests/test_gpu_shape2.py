@@ -8,9 +8,9 @@ FP32-bulk 1e-4 on grids and 1e-3 on momenta (2e-5 per stage).
 import numpy as np
 import pytest
 
-from inputs import random_grid, random_particles, scaled
-from test_gpu_parity import (C2_SMALL, PRECS, RAGGED, compare_fields, compare_particles, ferr, say,
-                             staggered)
+from inputs import C2, random_grid, random_particles, scaled
+from test_gpu_parity import (C2_SMALL, PRECS, RAGGED, _full_size_slab, compare_fields, compare_particles, ferr,
+                             say, staggered)
 
 pytestmark = pytest.mark.gpu
 
@@ -144,3 +144,21 @@ def test_order2_rejects_deferred_deposits(E):
         g.gather_push(E.MOMENTUM, defer=True)
     assert ei.value.code == -1
     g.step(2)  # the fused path still runs
+
+
+@pytest.mark.parametrize("order", [1, 2])
+def test_c2_full_size_window_slab_around_pulse(E, oracle_mod, order):
+    """The 2048 x 256, modes 0-1, 8.4 M-particle LWFA workload, moving window
+    and injection, 12 steps in the benchmark's launch configuration, against
+    an oracle replica of a 200-column slab around the pulse (lab positions,
+    angles, ids and window timing as in the full run), compared outside the
+    slab edges' domain of dependence (four cells per step).  The compared
+    region holds the pulse and its wake, so the fields are well above the
+    FP32 floor."""
+    say("C2 full size window slab around the pulse, order", order)
+    c0, w, steps = C2["nx"] - 300, 200, 12
+    g = _full_size_slab(E, oracle_mod, dict(C2, shape_order=order), c0, w, steps, reach=4)
+    lo, hi = 4 * steps + 4, w - 4 * steps - 4
+    ex = g.get_field("ex")[c0 + lo:c0 + hi]
+    assert np.abs(ex).max() > 1e-6  # a wake is present where the fields were compared
+    assert g.diagnostics()["nonfinite"] == 0
