@@ -141,3 +141,18 @@ def beam_particles(cfg, n_bulk, n_beam, seed, p_beam=400.0, dp_beam=8.0, sig_r=2
     ids = np.arange(n_bulk, n_bulk + n_beam, dtype=np.uint32)
     return {k: np.concatenate([bulk[k], v]) for k, v in
             dict(x=x, y=y, z=z, px=px, py=py, pz=pz, w=w, id=ids).items()}
+
+
+def bunch_particles(n, seed, x0, sig_x, sig_r, p0, w_total=1.0, id0=0, r_cut=4.0):
+    """An externally injected electron bunch: Gaussian in x (centre x0, rms
+    sig_x) and in each transverse coordinate (rms sig_r, cut at r_cut sig_r
+    from the axis), momentum p0 along x, equal weights summing to w_total.
+    Lab-frame Cartesian FP64 arrays plus ids."""
+    rng = np.random.default_rng(seed)
+    x = rng.normal(x0, sig_x, n)
+    y = rng.normal(0.0, sig_r, n)
+    z = rng.normal(0.0, sig_r, n)
+    r = np.hypot(y, z)
+    scale = np.where(r > r_cut * sig_r, r_cut * sig_r / np.maximum(r, 1e-300), 1.0)
+    return dict(x=x, y=y * scale, z=z * scale, px=np.full(n, p0), py=np.zeros(n), pz=np.zeros(n),
+                w=np.full(n, w_total / n), id=np.arange(id0, id0 + n, dtype=np.uint32))
