@@ -180,6 +180,35 @@ def cpu_baseline(cfg, cols=256, steps=20):
                       f"{int(0.5 * (n0 + n1))} particles, {steps} steps, FP64, 1 thread ({dt:.1f} s)"}
 
 
+def bunch_solve_line(workload):
+    """The field initialisation of an injected bunch (gamma = 7.09) on the
+    workload's grid: conjugate-gradient iterations, wall time of the
+    synchronous call, and the algorithmic bytes of the iterations (per
+    unknown and iteration: stencil 16 B, update 48 B, direction 24 B)."""
+    import numpy as np
+    import torch
+    import paper_1912_04674_amd as E
+    from inputs import C2, C3, C5, bunch_particles
+    base = {"c2": C2, "c3": C3, "c5": C5}[workload]
+    cfg = dict(base, capacity=base["nx"] * base["nr"] * int(np.prod(base["ppc"])) + 300_000)
+    torch.cuda.set_device(0)
+    g = E.Sim(cfg, E.FP32_BULK)
+    plasma = g.get_particles()
+    beta = 0.99
+    nb = 200_000
+    b = bunch_particles(nb, 11, x0=(cfg["nx"] - 600) * cfg["dx"], sig_x=8.0, sig_r=3.0,
+                        p0=beta / np.sqrt(1 - beta * beta), w_total=20.0, id0=1 << 26)
+    g.set_particles({k: np.concatenate([plasma[k], b[k]]) for k in plasma})
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    it, res = g.bunch_fields(1 << 26, (1 << 26) + nb, beta, tol=1e-12)
+    dt = time.perf_counter() - t0
+    n = (cfg["nx"] - 1) * cfg["nr"]
+    return {"workload": cfg["name"], "unknowns": n, "bunch_particles": nb, "beta": beta, "iterations": it,
+            "relative_residual": res, "ms": 1e3 * dt, "us_per_iteration": 1e6 * dt / max(it, 1),
+            "alg_GBps": 88.0 * n * it / dt / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -194,6 +223,9 @@ def main():
                     help="binomial current filter passes (the paper's nonlinear benchmark uses 7)")
     ap.add_argument("--shape-order", type=int, default=1, choices=[1, 2],
                     help="particle shape order of gather and deposit (2: quadratic B-spline)")
+    ap.add_argument("--bunch-solve", action="store_true",
+                    help="only time the self-consistent field solve of a 200 000-particle relativistic "
+                         "bunch added to the workload's plasma (one JSON line)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB, 10 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
@@ -211,6 +243,9 @@ def main():
         dt = (time.perf_counter() - t0) / 10
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "seconds": dt,
                           "GBps_read_plus_write": 2 * n / dt / 1e9}))
+        return
+    if args.bunch_solve:
+        print(json.dumps(bunch_solve_line(args.workload)))
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU x-slab "

@@ -263,6 +263,30 @@ int envpic_diagnostics(const envpic_sim* s, double* out);
 int envpic_beam_diagnostics(const envpic_sim* s, double e_lo, double e_hi, int nbins, double* out,
                             double* hist);
 
+/* Self-consistent initial fields of an externally injected relativistic
+ * electron bunch (Sec. 3: the field initialisation of external injection,
+ * carried over to cylindrical symmetry).  The bunch is the set of resident
+ * particles with id in [id_lo, id_hi) (load it with envpic_set_particles);
+ * it moves along x with velocity beta.  Its potential solves
+ *   (1/gamma^2) d2phi/dx2 + (1/r) d/dr (r dphi/dr) = -rho
+ * on the primal nodes, with phi = 0 on the x ends and at r_max and rho the
+ * bunch's charge deposited with the simulation's particle shape, so that
+ * the Gauss law of the field update holds exactly; then
+ *   E_x(i+1/2, j) = -(phi_{i+1,j} - phi_{i,j}) / (gamma^2 dx),
+ *   E_r(i, j+1/2) = -(phi_{i,j+1} - phi_{i,j}) / dr,
+ *   B_theta = Bbar_theta = beta (E_r(i) + E_r(i+1)) / 2 at (i+1/2, j+1/2)
+ * are ADDED to the mode-0 E^n, B^{n+1/2} and Bbar^n (mode 1 untouched: an
+ * axisymmetric bunch).  FP64 conjugate gradients (diagonal preconditioner)
+ * until the relative residual |b - K phi| / |b| is at most tol, in at most
+ * max_iter iterations; *iters and *resid (each may be NULL) receive the
+ * iterations and the final relative residual.  A range holding no charge
+ * changes nothing.  Synchronous; only between steps (ENVPIC_EORDER).
+ * ENVPIC_EINVAL unless 0 <= beta < 1, tol > 0, max_iter >= 1 and
+ * id_hi > id_lo; ENVPIC_ENUMERIC if tol is not reached (the fields are
+ * added all the same). */
+int envpic_bunch_fields(envpic_sim* s, uint32_t id_lo, uint32_t id_hi, double beta, double tol, int max_iter,
+                        int* iters, double* resid);
+
 /* Checkpoint: with host_blob == NULL, *bytes receives the size needed; else
  * the full state (step, shift, both envelope levels, E, B, Bbar, particles,
  * parameters) is written.  envpic_load restores a blob written by a

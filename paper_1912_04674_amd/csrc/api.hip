@@ -130,6 +130,7 @@ template <class R> struct State {
   double* diag_scratch;
   double* diag_out;
   BeamScratch beam;
+  CgVecs cg;
 };
 
 template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64_rows, char* base, State<R>* st) {
@@ -230,6 +231,15 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   S.beam.part = cv.take<double>((size_t)s.max_items * BEAM_PARTS);
   S.beam.st = cv.take<double>(BEAM_STATE);
   S.beam.out = cv.take<double>(ENVPIC_NBEAM);
+  {
+    const size_t nu = (size_t)cg_unknowns(p.nx, p.nr);
+    S.cg.x = cv.take<double>(nu);
+    S.cg.r = cv.take<double>(nu);
+    S.cg.p = cv.take<double>(nu);
+    S.cg.q = cv.take<double>(nu);
+    S.cg.part = cv.take<double>((size_t)cg_blocks(p.nx, p.nr) * 2);
+    S.cg.s = cv.take<double>(CG_NS);
+  }
   if (st) *st = S;
   return align_up(cv.off, 256);
 }
@@ -386,6 +396,8 @@ struct envpic_sim {
   virtual int set_particles(int64_t n, const double* const* cols, const uint32_t* id) = 0;
   virtual int diagnostics(double* out) = 0;
   virtual int beam(double e_lo, double e_hi, int nbins, double* out, double* hist) = 0;
+  virtual int bunch(uint32_t id_lo, uint32_t id_hi, double beta, double tol, int max_iter, int* iters,
+                    double* resid) = 0;
   virtual int poison(int f) = 0;
   virtual int check_err() = 0;
   virtual int clear_deposits() = 0;
@@ -951,6 +963,24 @@ template <class R> struct SimT : envpic_sim {
     return check_err();
   }
 
+  int bunch(uint32_t id_lo, uint32_t id_hi, double beta, double tol, int max_iter, int* iters,
+            double* resid) override {
+    int it = 0;
+    double res = 0.0;
+    if (bunch_solve<R>(geo(), S.parts[cur], S.lay[cur], sz.max_items, S.grids, id_lo, id_hi, beta, tol, max_iter,
+                       S.cg, stream, &it, &res)) {
+      const int rc = launched("bunch fields");
+      return rc ? rc : fail(ENVPIC_EDEVICE, "bunch fields: residual transfer failed");
+    }
+    int rc = launched("bunch fields");
+    if (rc) return rc;
+    if ((rc = hip_check(hipStreamSynchronize(stream), "bunch sync"))) return rc;
+    if (iters) *iters = it;
+    if (resid) *resid = res;
+    if (!(res <= tol)) return fail(ENVPIC_ENUMERIC, "bunch field solve did not reach the tolerance");
+    return check_err();
+  }
+
   int poison(int f) override {
     std::vector<double> buf;
     FieldRef r;
@@ -1206,6 +1236,16 @@ int envpic_beam_diagnostics(const envpic_sim* cs, double e_lo, double e_hi, int 
   if (nbins < 1 || nbins > ENVPIC_BEAM_MAX_BINS) return fail(ENVPIC_EINVAL, "nbins outside [1, ENVPIC_BEAM_MAX_BINS]");
   if (s->stage != 0) return fail(ENVPIC_EORDER, "beam diagnostics only between steps");
   return s->beam(e_lo, e_hi, nbins, out, hist);
+}
+
+int envpic_bunch_fields(envpic_sim* s, uint32_t id_lo, uint32_t id_hi, double beta, double tol, int max_iter,
+                        int* iters, double* resid) {
+  if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  if (!(beta >= 0.0 && beta < 1.0)) return fail(ENVPIC_EINVAL, "beta must be in [0, 1)");
+  if (!(tol > 0.0 && std::isfinite(tol)) || max_iter < 1) return fail(ENVPIC_EINVAL, "need tol > 0 and max_iter >= 1");
+  if (id_hi <= id_lo) return fail(ENVPIC_EINVAL, "empty id range");
+  if (s->stage != 0) return fail(ENVPIC_EORDER, "bunch fields only between steps");
+  return s->bunch(id_lo, id_hi, beta, tol, max_iter, iters, resid);
 }
 
 // checkpoint blob: header, the persistent grids (FP64, window-relative),

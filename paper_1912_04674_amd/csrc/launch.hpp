@@ -105,4 +105,20 @@ template <class R>
 void launch_beam(const Geo& g, const Parts<R>& P, const Layout& L, int max_items, const BeamArgs& a,
                  const BeamScratch& b, hipStream_t st);
 
+// self-consistent fields of an injected bunch (bunch.hip): conjugate
+// gradients on the (nx - 1) x nr interior potential nodes, FP64
+constexpr int CG_CHECK = 25;  // iterations between residual reads
+constexpr int CG_NS = 8;      // device scalars
+struct CgVecs {
+  double *x, *r, *p, *q;  // [unknowns] each
+  double* part;           // [blocks][2] partial sums
+  double* s;              // [CG_NS]
+};
+long long cg_unknowns(int nx, int nr);
+int cg_blocks(int nx, int nr);
+template <class R>
+int bunch_solve(const Geo& g, const Parts<R>& P, const Layout& L, int max_items, const Grids<R>& f,
+                unsigned id_lo, unsigned id_hi, double beta, double tol, int max_iter, const CgVecs& v,
+                hipStream_t st, int* iters, double* resid);
+
 }  // namespace envpic

@@ -67,6 +67,7 @@ EXPORTS = [
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
     "envpic_set_timing", "envpic_get_timing", "envpic_set_graph", "envpic_beam_diagnostics",
+    "envpic_bunch_fields",
 ]
 
 
@@ -99,6 +100,8 @@ def lib():
     L.envpic_set_particles.argtypes = [vp, ctypes.c_int64] + [dp] * 7 + [up]
     L.envpic_diagnostics.argtypes = [vp, dp]
     L.envpic_beam_diagnostics.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
+    L.envpic_bunch_fields.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
     L.envpic_set_timing.argtypes = [vp, ctypes.c_int]
     L.envpic_set_graph.argtypes = [vp, ctypes.c_int]
     L.envpic_get_timing.argtypes = [vp, dp, i64p]
@@ -291,6 +294,14 @@ class Sim:
                                              _dptr(hist) if with_hist else None))
         res = dict(zip(BEAM_NAMES, out))
         return (res, hist) if with_hist else res
+
+    def bunch_fields(self, id_lo, id_hi, beta, tol=1e-12, max_iter=50000):
+        """Add the self-consistent fields of the bunch of particles with id in
+        [id_lo, id_hi) moving at beta; returns (iterations, relative residual)."""
+        it, res = ctypes.c_int(), ctypes.c_double()
+        _check(lib().envpic_bunch_fields(self._h, int(id_lo), int(id_hi), float(beta), float(tol), int(max_iter),
+                                         ctypes.byref(it), ctypes.byref(res)))
+        return it.value, res.value
 
     def save(self):
         n = ctypes.c_size_t()
