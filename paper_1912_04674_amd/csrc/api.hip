@@ -236,7 +236,9 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
     S.cg.x = cv.take<double>(nu);
     S.cg.r = cv.take<double>(nu);
     S.cg.p = cv.take<double>(nu);
+    S.cg.p2 = cv.take<double>(nu);
     S.cg.q = cv.take<double>(nu);
+    S.cg.idiag = cv.take<double>((size_t)p.nr);
     S.cg.part = cv.take<double>((size_t)cg_blocks(p.nx, p.nr) * 2);
     S.cg.s = cv.take<double>(CG_NS);
   }

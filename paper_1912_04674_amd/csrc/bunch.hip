@@ -17,11 +17,13 @@
 // A_{j+1/2} = 2 pi (j + 1/2) dr dx, A_{-1/2} = 0, V_0 = pi dr^2 dx / 4.
 //
 // Solved by conjugate gradients with the diagonal as preconditioner, in
-// FP64: one stencil kernel per iteration (with the partial sums of p.Kp),
-// one update kernel (x, r and the partial sums of r.z and r.r), one
-// direction kernel, and one-group reductions in a fixed order, so a solve
-// is reproducible.  The scalars stay on the device; the host reads the
-// residual every CG_CHECK iterations.
+// FP64.  Per iteration: a stencil kernel that forms the new direction
+// p = r/diag + beta p_old on the fly for its node and the four neighbours
+// (two direction buffers, swapped by the host), applies K and sums p.Kp per
+// block; an update kernel (x, r and the partial sums of r.z and r.r); and two
+// one-group reductions in a fixed order, so a solve is reproducible.  The
+// scalars stay on the device; the host reads the residual every CG_CHECK
+// iterations.
 #include <algorithm>
 
 #include "common.hpp"
@@ -124,7 +126,13 @@ __global__ __launch_bounds__(SB) void k_cg_zero(double* __restrict__ a, long lon
   if (k < n) a[k] = 0.0;
 }
 
-// z = r / diag, p = z; partial sums of r.z, r.r
+// the preconditioner: 1 / diag of each row (the diagonal depends on j only)
+__global__ __launch_bounds__(SB) void k_cg_idiag(CgOp o, CgVecs v) {
+  const int j = blockIdx.x * SB + threadIdx.x;
+  if (j < o.nj) v.idiag[j] = 1.0 / diag_j(o, j);
+}
+
+// x = 0, p_old = 0 (so the first direction is z); partial sums of r.z, r.r
 __global__ __launch_bounds__(SB) void k_cg_start(CgOp o, CgVecs v) {
   __shared__ double red[2 * SB];
   double s[2] = {0.0, 0.0};
@@ -132,29 +140,34 @@ __global__ __launch_bounds__(SB) void k_cg_start(CgOp o, CgVecs v) {
   const long long n = (long long)o.ni * o.nj;
   if (k < n) {
     const int j = (int)(k % o.nj);
-    const double r = v.r[k], z = r / diag_j(o, j);
+    const double r = v.r[k], z = r * v.idiag[j];
     v.x[k] = 0.0;
-    v.p[k] = z;
+    v.p[k] = 0.0;
     s[0] = r * z;
     s[1] = r * r;
   }
   cg_block_sum<2>(s, red, v.part);
 }
 
-// q = K p; partial sums of p.q
-__global__ __launch_bounds__(SB) void k_cg_apply(CgOp o, CgVecs v) {
+// p_new = r / diag + beta p_old (at the node and its neighbours), q = K p_new;
+// partial sums of p_new.q
+__global__ __launch_bounds__(SB) void k_cg_apply(CgOp o, CgVecs v, const double* __restrict__ p_old,
+                                                 double* __restrict__ p_new) {
   __shared__ double red[SB];
   double s[1] = {0.0};
   const long long k = (long long)blockIdx.x * SB + threadIdx.x;
   const long long n = (long long)o.ni * o.nj;
+  const double beta = v.s[CG_BETA];
   if (k < n) {
     const int i = (int)(k / o.nj), j = (int)(k - (long long)i * o.nj);
-    const double pc = v.p[k];
+    auto dir = [&](long long m, int jj) { return v.r[m] * v.idiag[jj] + beta * p_old[m]; };
+    const double pc = dir(k, j);
     const double cx = vol_j(o, j) * o.g2 / (o.dx * o.dx);
-    const double pl = i > 0 ? v.p[k - o.nj] : 0.0, pr = i < o.ni - 1 ? v.p[k + o.nj] : 0.0;
-    const double pu = j < o.nj - 1 ? v.p[k + 1] : 0.0, pd = j > 0 ? v.p[k - 1] : 0.0;
+    const double pl = i > 0 ? dir(k - o.nj, j) : 0.0, pr = i < o.ni - 1 ? dir(k + o.nj, j) : 0.0;
+    const double pu = j < o.nj - 1 ? dir(k + 1, j + 1) : 0.0, pd = j > 0 ? dir(k - 1, j - 1) : 0.0;
     double q = cx * (2.0 * pc - pl - pr) + face_j(o, j) * (pc - pu);
     if (j > 0) q += face_j(o, j - 1) * (pc - pd);
+    p_new[k] = pc;
     v.q[k] = q;
     s[0] = pc * q;
   }
@@ -189,6 +202,7 @@ __global__ __launch_bounds__(256) void k_cg_init_scalars(int nb, CgVecs v) {
     v.s[CG_RZ] = t[0];
     v.s[CG_RR] = t[1];
     v.s[CG_BB] = t[1];
+    v.s[CG_BETA] = 0.0;
   }
 }
 
@@ -200,7 +214,7 @@ __global__ __launch_bounds__(256) void k_cg_alpha(int nb, CgVecs v) {
 }
 
 // x += alpha p, r -= alpha q; partial sums of r.z (z = r / diag) and r.r
-__global__ __launch_bounds__(SB) void k_cg_update(CgOp o, CgVecs v) {
+__global__ __launch_bounds__(SB) void k_cg_update(CgOp o, CgVecs v, const double* __restrict__ p) {
   __shared__ double red[2 * SB];
   double s[2] = {0.0, 0.0};
   const long long k = (long long)blockIdx.x * SB + threadIdx.x;
@@ -208,10 +222,10 @@ __global__ __launch_bounds__(SB) void k_cg_update(CgOp o, CgVecs v) {
   const double alpha = v.s[CG_ALPHA];
   if (k < n) {
     const int j = (int)(k % o.nj);
-    v.x[k] += alpha * v.p[k];
+    v.x[k] += alpha * p[k];
     const double r = v.r[k] - alpha * v.q[k];
     v.r[k] = r;
-    s[0] = r * (r / diag_j(o, j));
+    s[0] = r * (r * v.idiag[j]);
     s[1] = r * r;
   }
   cg_block_sum<2>(s, red, v.part);
@@ -225,17 +239,6 @@ __global__ __launch_bounds__(256) void k_cg_beta(int nb, CgVecs v) {
     v.s[CG_BETA] = v.s[CG_RZ] != 0.0 ? t[0] / v.s[CG_RZ] : 0.0;
     v.s[CG_RZ] = t[0];
     v.s[CG_RR] = t[1];
-  }
-}
-
-// p = r / diag + beta p
-__global__ __launch_bounds__(SB) void k_cg_direction(CgOp o, CgVecs v) {
-  const long long k = (long long)blockIdx.x * SB + threadIdx.x;
-  const long long n = (long long)o.ni * o.nj;
-  const double beta = v.s[CG_BETA];
-  if (k < n) {
-    const int j = (int)(k % o.nj);
-    v.p[k] = v.r[k] / diag_j(o, j) + beta * v.p[k];
   }
 }
 
@@ -283,6 +286,7 @@ int bunch_solve(const Geo& g, const Parts<R>& P, const Layout& L, int max_items,
   const long long n = cg_unknowns(g.nx, g.nr);
   const int nb = cg_blocks(g.nx, g.nr);
   hipLaunchKernelGGL(k_cg_zero, dim3(nb), dim3(SB), 0, st, v.r, n);
+  hipLaunchKernelGGL(k_cg_idiag, dim3((o.nj + SB - 1) / SB), dim3(SB), 0, st, o, v);
   hipLaunchKernelGGL((k_bunch_charge<R>), dim3(max_items), dim3(SB), 0, st, g, P, L, id_lo, id_hi, o, v.r);
   hipLaunchKernelGGL(k_cg_start, dim3(nb), dim3(SB), 0, st, o, v);
   hipLaunchKernelGGL(k_cg_init_scalars, dim3(1), dim3(256), 0, st, nb, v);
@@ -294,16 +298,18 @@ int bunch_solve(const Geo& g, const Parts<R>& P, const Layout& L, int max_items,
   *resid = 0.0;
   if (bb == 0.0) return 0;  // no charge: nothing to add (x = 0)
   const double stop = tol * tol * bb;
+  double* pa = v.p;   // direction of the previous iteration (zero at the start)
+  double* pb = v.p2;  // the new one
   int it = 0;
   double rr = bb;
   while (it < max_iter && rr > stop) {
     const int burst = std::min(CG_CHECK, max_iter - it);
     for (int k = 0; k < burst; ++k) {
-      hipLaunchKernelGGL(k_cg_apply, dim3(nb), dim3(SB), 0, st, o, v);
+      hipLaunchKernelGGL(k_cg_apply, dim3(nb), dim3(SB), 0, st, o, v, pa, pb);
       hipLaunchKernelGGL(k_cg_alpha, dim3(1), dim3(256), 0, st, nb, v);
-      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(SB), 0, st, o, v);
+      hipLaunchKernelGGL(k_cg_update, dim3(nb), dim3(SB), 0, st, o, v, pb);
       hipLaunchKernelGGL(k_cg_beta, dim3(1), dim3(256), 0, st, nb, v);
-      hipLaunchKernelGGL(k_cg_direction, dim3(nb), dim3(SB), 0, st, o, v);
+      std::swap(pa, pb);
     }
     it += burst;
     if (hipMemcpyAsync(hs, v.s, sizeof(hs), hipMemcpyDeviceToHost, st) != hipSuccess) return -1;

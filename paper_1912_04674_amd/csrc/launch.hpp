@@ -110,7 +110,8 @@ void launch_beam(const Geo& g, const Parts<R>& P, const Layout& L, int max_items
 constexpr int CG_CHECK = 25;  // iterations between residual reads
 constexpr int CG_NS = 8;      // device scalars
 struct CgVecs {
-  double *x, *r, *p, *q;  // [unknowns] each
+  double *x, *r, *p, *p2, *q;  // [unknowns] each (p, p2: two direction buffers)
+  double* idiag;          // [nr] inverse diagonal of each row
   double* part;           // [blocks][2] partial sums
   double* s;              // [CG_NS]
 };
