@@ -8,7 +8,7 @@
 //   * particles: structure of arrays, cell word (lab column, radial row),
 //     offsets in the cell along x and r, azimuth, momenta, weight (R), id
 //     (uint32); two buffers ping-pong through the counting sort by tile,
-//     which runs every third step;
+//     which runs every third step (every second with quadratic shapes);
 //   * the envelope rows j = 0, 1 additionally in FP64 (FP32 mode).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -21,7 +21,9 @@ constexpr int TR = 16;      // tile height along r (cells)
 // Particles move at most one cell per step and are re-sorted by tile every
 // SORT_EVERY steps, so a particle is at most SORT_EVERY cells outside its
 // tile at a gather (SORT_EVERY + 1 at the end of a push); one more cell of
-// margin holds the linear and half-cell-staggered stencils.
+// margin holds the linear and half-cell-staggered stencils.  Quadratic
+// stencils reach one node further and re-sort every SORT_EVERY - 1 steps,
+// which keeps them inside the same margin.
 constexpr int SORT_EVERY = 3;
 constexpr int HALO = SORT_EVERY + 1;  // LDS region margin around a tile (cells)
 constexpr int LX = TX + 2 * HALO + 1;

@@ -5,8 +5,9 @@
 // current deposit, tile histogram), loading and injection.
 //
 // Work decomposition: particles are counting-sorted by 16 x 16-cell tiles
-// every SORT_EVERY steps; a work item is (tile, contiguous range of at most
-// g.chunk particles).  A work group stages the fields of its tile plus a
+// every SORT_EVERY steps (SORT_EVERY - 1 for quadratic shapes); a work item
+// is (tile, contiguous range of at most g.chunk particles).  A work group
+// stages the fields of its tile plus a
 // HALO-cell margin in LDS, accumulates the deposits of its particles in LDS
 // and flushes them to HBM once (atomic adds, since halos overlap).
 // Particles drift at most one cell per step (dt < dx, dt < dr), so between
