@@ -209,6 +209,11 @@ def bunch_solve_line(workload):
             "alg_GBps": 88.0 * n * it / dt / 1e9}
 
 
+def progress(*a):
+    """One line on stderr as each part of the benchmark ends."""
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -264,6 +269,7 @@ def main():
     torch.cuda.set_device(0)
 
     r32 = run_gpu(E, torch, cfg, E.FP32_BULK, args.steps, args.warmup, beam=True)
+    progress(f"fp32 timed run done: {1e3 * r32['wall_s'] / args.steps:.4f} ms/step")
     pushes = r32["particles"] * args.steps
     value = pushes / r32["wall_s"]
     cells = cfg["nx"] * cfg["nr"]
@@ -298,6 +304,7 @@ def main():
         extra["fp64_pushes_per_s"] = r64["particles"] * s64 / r64["wall_s"]
         extra["fp64_steps"] = s64
         extra["fp32_over_fp64"] = value / extra["fp64_pushes_per_s"]
+        progress("fp64 run done")
     line = {
         "metric": METRIC, "value": value, "unit": "particle-pushes/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup,
@@ -315,10 +322,13 @@ def main():
         line["serving"] = {"trace": "64 jobs, Poisson 4 jobs/s, grids {512x64, 1024x128, 2048x256}, m=0, "
                                     "2x2x2 ppc, 300 steps, window on",
                            "fp32": run_serving(E, E.FP32_BULK, budget)}
+        progress("fp32 serving trace done")
         if not args.no_fp64:
             line["serving"]["fp64"] = run_serving(E, E.FP64, budget)
+            progress("fp64 serving trace done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
+        progress("cpu baseline done")
     line["extra"] = extra
     print(json.dumps(line))
 
