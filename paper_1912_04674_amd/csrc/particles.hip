@@ -970,30 +970,50 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
     const size_t o = (size_t)phys_col(g, rel) * g.pitch + j;
     const bool dxok = rel <= g.nx - 1, drok = j <= g.nr - 1;
-    const bool fold_row = O == 2 && j == 1 && b >= 2, fold_face = O == 2 && j == 0 && b >= 1;
-    typename Acc0<R>::T vjx = sm.jx[k], vjr = sm.jr[k];
-    if (fold_row) vjx += sm.jx[k - 2];
-    if (fold_face) vjr -= sm.jr[k - 1];
-    if (dxok && vjx != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(vjx, g) * sm.iax[b]));
-    if (drok && vjr != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(vjr, g) * sm.iar[b]));
-    if (M1) {
-      using A = Acc1<R>;
-      typename A::T v1x = sm.jx1[k], v1t = sm.jt1[k];
-      if (fold_row) {
-        v1x = acc_axpy(v1x, sm.jx1[k - 2], -1);
-        v1t = acc_axpy(v1t, sm.jt1[k - 2], 1);
+    if constexpr (O == 2) {
+      const bool fold_row = j == 1 && b >= 2, fold_face = j == 0 && b >= 1;
+      typename Acc0<R>::T vjx = sm.jx[k], vjr = sm.jr[k];
+      if (fold_row) vjx += sm.jx[k - 2];
+      if (fold_face) vjr -= sm.jr[k - 1];
+      if (dxok && vjx != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(vjx, g) * sm.iax[b]));
+      if (drok && vjr != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(vjr, g) * sm.iar[b]));
+      if (M1) {
+        using A = Acc1<R>;
+        typename A::T v1x = sm.jx1[k], v1t = sm.jt1[k];
+        if (fold_row) {
+          v1x = acc_axpy(v1x, sm.jx1[k - 2], -1);
+          v1t = acc_axpy(v1t, sm.jt1[k - 2], 1);
+        }
+        if (dxok && A::nonzero(v1x)) {
+          atomicAdd(&jx1_out[o].x, (R)A::re(v1x, g));
+          atomicAdd(&jx1_out[o].y, (R)A::im(v1x, g));
+        }
+        if (drok && A::nonzero(sm.jr1[k])) {
+          atomicAdd(&jr1_out[o].x, (R)A::re(sm.jr1[k], g));
+          atomicAdd(&jr1_out[o].y, (R)A::im(sm.jr1[k], g));
+        }
+        if (A::nonzero(v1t)) {
+          atomicAdd(&jt1_out[o].x, (R)A::re(v1t, g));
+          atomicAdd(&jt1_out[o].y, (R)A::im(v1t, g));
+        }
       }
-      if (dxok && A::nonzero(v1x)) {
-        atomicAdd(&jx1_out[o].x, (R)A::re(v1x, g));
-        atomicAdd(&jx1_out[o].y, (R)A::im(v1x, g));
-      }
-      if (drok && A::nonzero(sm.jr1[k])) {
-        atomicAdd(&jr1_out[o].x, (R)A::re(sm.jr1[k], g));
-        atomicAdd(&jr1_out[o].y, (R)A::im(sm.jr1[k], g));
-      }
-      if (A::nonzero(v1t)) {
-        atomicAdd(&jt1_out[o].x, (R)A::re(v1t, g));
-        atomicAdd(&jt1_out[o].y, (R)A::im(v1t, g));
+    } else {
+      if (dxok && sm.jx[k] != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(sm.jx[k], g) * sm.iax[b]));
+      if (drok && sm.jr[k] != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(sm.jr[k], g) * sm.iar[b]));
+      if (M1) {
+        using A = Acc1<R>;
+        if (dxok && A::nonzero(sm.jx1[k])) {
+          atomicAdd(&jx1_out[o].x, (R)A::re(sm.jx1[k], g));
+          atomicAdd(&jx1_out[o].y, (R)A::im(sm.jx1[k], g));
+        }
+        if (drok && A::nonzero(sm.jr1[k])) {
+          atomicAdd(&jr1_out[o].x, (R)A::re(sm.jr1[k], g));
+          atomicAdd(&jr1_out[o].y, (R)A::im(sm.jr1[k], g));
+        }
+        if (A::nonzero(sm.jt1[k])) {
+          atomicAdd(&jt1_out[o].x, (R)A::re(sm.jt1[k], g));
+          atomicAdd(&jt1_out[o].y, (R)A::im(sm.jt1[k], g));
+        }
       }
     }
   }
