@@ -162,3 +162,56 @@ def test_c2_full_size_window_slab_around_pulse(E, oracle_mod, order):
     ex = g.get_field("ex")[c0 + lo:c0 + hi]
     assert np.abs(ex).max() > 1e-6  # a wake is present where the fields were compared
     assert g.diagnostics()["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_order2_with_filter_window_parity(E, oracle_mod, prec, tf, tp):
+    """The paper's nonlinear-benchmark configuration on a small window:
+    quadratic shapes and the 7-pass binomial current filter, modes 0 and 1,
+    moving window with injection, 60 steps."""
+    cfg = dict(C2_SMALL, shape_order=2, filter_passes=7)
+    say("order-2 + filter window", prec)
+    g = E.Sim(cfg, _prec(E, prec))
+    r = oracle_mod.OracleSim(cfg)
+    g.step(60)
+    r.step(60)
+    assert g.state() == r.state()
+    compare_fields(g, r, tf, modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_order2_checkpoint_and_graph_mode(E, prec):
+    """2N steps equal N steps + save + load + N steps, and graph-mode chunks
+    equal direct launches, with the two-step sort period of order 2."""
+    cfg = dict(C2_SMALL, shape_order=2)
+    P = _prec(E, prec)
+    a = E.Sim(cfg, P)
+    a.step(15)
+    blob = a.save()
+    a.step(16)
+    b = E.Sim(cfg, P)
+    b.load(blob)
+    b.set_graph(5)
+    b.step(16)
+    assert a.state() == b.state()
+    tol_f, tol_p = (1e-10, 1e-10) if prec == "fp64" else (1e-4, 1e-3)
+    compare_fields(b, a, tol_f, names=("env", "env_prev", "chi", "ex", "er", "bt", "bt_bar"), modes=2)
+    compare_particles(b.get_particles(), a.get_particles(), tol_p, 1e-8 if prec == "fp64" else 1e-3)
+
+
+def test_beam_parameters_after_order2_run(E):
+    """The beam-parameter pass on the state of an order-2 run equals the
+    oracle's computation on the same particles."""
+    from oracle import beam
+    cfg = dict(C2_SMALL, shape_order=2, a0=3.0)
+    g = E.Sim(cfg, E.FP32_BULK)
+    g.step(50)
+    parts = g.get_particles()
+    for q in [(0.0, 0.05, 128), (1e-3, 2.0, 64)]:
+        out, hist = g.beam(*q, with_hist=True)
+        ref, rhist = beam.beam_parameters(parts, *q)
+        assert ref["count"] > 0
+        assert np.abs(hist - rhist).max() <= 1e-10 * np.abs(rhist).max()
+        for k, v in ref.items():
+            assert out[k] == v if k == "count" else abs(out[k] - v) <= 1e-9 * abs(v), (q, k, out[k], v)
