@@ -38,12 +38,17 @@
  *                          against quasi-static theory (tests/golden)
  *   moving window          equals a static run in a longer box, bitwise
  *   loading RNG            SplitMix64 published output
- *   mode-1 Maxwell/deposit vacuum energy bounded (and unstable beyond the
- *                          limit), uniform transverse field static, a
- *                          theta-symmetric ring deposits zero, deposit phase
- *                          of one particle.  Beyond these the mode-1 fields
- *                          and currents are PARITY UNPINNED (derived
- *                          equations only, no closed form for a general state).
+ *   mode-1 Maxwell         normal modes of the conducting cylinder: TM_11
+ *                          and TE_11 frequencies (second-order convergence
+ *                          of TM after the known x and time corrections),
+ *                          their radial profiles through the axis rows;
+ *                          vacuum energy bounded (and unstable beyond the
+ *                          limit); a uniform transverse field is static
+ *   mode-1 deposit         a theta-symmetric ring deposits zero, deposit
+ *                          phase of one particle, the fold of a near-axis
+ *                          particle (order 2).  Beyond these the mode-1
+ *                          currents of a general state are PARITY UNPINNED
+ *                          (no closed form).
  *   binomial J filter      transfer factor cos^2(k/2)^N of an interior
  *   (R24)                  Fourier mode; linear and constant radial profiles
  *                          of each parity preserved through the axis ghost;
