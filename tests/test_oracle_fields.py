@@ -10,8 +10,6 @@ and vacuum stability.
 import numpy as np
 import pytest
 
-from inputs import random_grid
-
 
 def _cfg(**kw):
     c = dict(dx=0.8, dr=1.5, dt=0.6, profile="none", a0=0.0)

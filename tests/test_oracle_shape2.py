@@ -238,7 +238,7 @@ def test_mode1_deposit_folds_with_parity(oracle_mod):
     direct sum of its weights: row 0 gets 2 q w v S_0 / V_0, row 1 gets
     2 q w v (S_1 - S_-1) / V_1."""
     cfg = _cfg(nx=16, nr=8, n_modes=2)
-    dx, dr, dt = cfg["dx"], cfg["dr"], cfg["dt"]
+    dx, dr = cfg["dx"], cfg["dr"]
     s = oracle_mod.OracleSim(cfg)
     th, ur, ux = 0.6, 0.3, 6.3
     px = 0.5
@@ -256,4 +256,3 @@ def test_mode1_deposit_folds_with_parity(oracle_mod):
     assert col[1].real == pytest.approx(2 * q * v * (S[2] - S[0]) / V[1], rel=1e-12)
     assert np.abs(col[2:]).max() == 0.0
     assert np.abs(col.imag).max() < 1e-15 * np.abs(col).max()
-    _ = dt
