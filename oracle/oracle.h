@@ -44,11 +44,15 @@
  *                          their radial profiles through the axis rows;
  *                          vacuum energy bounded (and unstable beyond the
  *                          limit); a uniform transverse field is static
- *   mode-1 deposit         a theta-symmetric ring deposits zero, deposit
- *                          phase of one particle, the fold of a near-axis
- *                          particle (order 2).  Beyond these the mode-1
- *                          currents of a general state are PARITY UNPINNED
- *                          (no closed form).
+ *   mode-1 deposit         closed forms of drifting quiet-start plasmas
+ *                          with linear density gradients (both shapes):
+ *                          J_r1 = q n v, J_theta1 = -i q n v for a drift
+ *                          along y; J_x1 = q n v eps e^{i theta0} for a
+ *                          drift along x of n (1 + eps cos(theta-theta0)),
+ *                          with the shape variance in the radial factor;
+ *                          one particle's phase at the mid-point azimuth;
+ *                          a theta-symmetric ring deposits zero; the fold
+ *                          of a near-axis particle (order 2)
  *   binomial J filter      transfer factor cos^2(k/2)^N of an interior
  *   (R24)                  Fourier mode; linear and constant radial profiles
  *                          of each parity preserved through the axis ghost;
