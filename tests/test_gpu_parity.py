@@ -358,6 +358,39 @@ def test_tiny_particle_sets(E, oracle_mod, n):
         compare_particles(g.get_particles(), r.get_particles(), 1e-9, 1e-9)
 
 
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_dense_clusters_parity(E, oracle_mod, prec, tf, tp):
+    """Extreme bunching: 36 000 electrons in one cell at mid radius and
+    30 000 in one cell on the axis, over a sparse background, pushed by a
+    laser pulse for 12 steps (four re-sorts, the first by cell).  Each
+    cluster's tile splits into dozens of equal work items, and the lanes of
+    a wavefront pile their deposits onto the same few LDS words."""
+    cfg = dict(nx=96, nr=32, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=1.5, w0=10.0, tau=10.0,
+               x_c=50.0, x_f=50.0, ppc=(1, 1, 1), capacity=80_000)
+    say("dense clusters", prec)
+    rng = np.random.default_rng(2024)
+    parts = random_particles(cfg, 3000, seed=77, margin=4, pmax=0.3)
+    dx, dr = cfg["dx"], cfg["dr"]
+    for n, cx, r_lo, r_hi in ((36_000, 40, 12.0, 13.0), (30_000, 60, 0.0, 0.6)):
+        x = (cx + rng.uniform(0.0, 1.0, n)) * dx
+        r = dr * np.sqrt(rng.uniform(r_lo * r_lo, r_hi * r_hi, n))
+        th = rng.uniform(0.0, 2 * np.pi, n)
+        c = dict(x=x, y=r * np.cos(th), z=r * np.sin(th), px=rng.uniform(-0.4, 0.4, n),
+                 py=rng.uniform(-0.4, 0.4, n), pz=rng.uniform(-0.4, 0.4, n), w=rng.uniform(0.5, 1.5, n) * 1e-4,
+                 id=np.arange(n, dtype=np.uint32) + len(parts["id"]))
+        parts = {k: np.concatenate([parts[k], c[k]]) for k in parts}
+    g = E.Sim(cfg, E.FP64 if prec == "fp64" else E.FP32_BULK)
+    r = oracle_mod.OracleSim(cfg)
+    g.set_particles(parts)
+    r.set_particles(parts)
+    g.step(12)
+    r.step(12)
+    assert g.state() == r.state()
+    assert g.diagnostics()["nonfinite"] == 0
+    compare_fields(g, r, tf, modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_axis_crossing_and_wall_reflection(E, oracle_mod, prec):
     """Particles aimed through the axis and at r_max: crossings of r = 0
