@@ -523,6 +523,54 @@ def test_batch_equals_alone(E):
         compare_particles(m.get_particles(), alone.get_particles(), 1e-3, 1e-3)
 
 
+def test_batch_mixed_simulations(E):
+    """One batch of twelve simulations that differ in precision, modes, shape
+    order, filter, grid and sort phase (each started a different number of
+    steps earlier): each ends where it ends alone, and steps on alone
+    afterwards."""
+    import torch
+    kinds = [(C2_SMALL, E.FP32_BULK, {}, 5), (C2_SMALL, E.FP64, {}, 0), (C2_SMALL, E.FP32_BULK, dict(n_modes=1, shape_order=2), 2),
+             (C2_SMALL, E.FP32_BULK, dict(shape_order=2, filter_passes=7), 1), (RAGGED, E.FP32_BULK, {}, 3),
+             (RAGGED, E.FP64, dict(shape_order=2), 4)]
+    kinds += [(C2_SMALL, E.FP32_BULK, dict(n_modes=1, ppc=(2, 2, 2), a0=0.8 + 0.3 * k, seed=191204710 + k), k % 3)
+              for k in range(6)]
+    say("mixed batch,", len(kinds), "simulations")
+    streams = [torch.cuda.Stream() for _ in kinds]
+    batch, alone = [], []
+    for (base, prec, over, pre), st in zip(kinds, streams):
+        cfg = dict(base, **over)
+        a, b = E.Sim(cfg, prec, stream=st), E.Sim(cfg, prec)
+        a.step(pre)
+        b.step(pre)
+        batch.append(a)
+        alone.append(b)
+    E.batch_step(batch, 23)
+    torch.cuda.synchronize()
+    for (base, prec, over, pre), a, b in zip(kinds, batch, alone):
+        b.step(23)
+        assert a.state() == b.state()
+        tf, tp = (1e-10, 1e-10) if prec == E.FP64 else (1e-4, 1e-3)
+        compare_fields(a, b, tf, names=("env", "env_prev", "chi", "ex", "er", "bt", "bt_bar"),
+                       modes=dict(base, **over)["n_modes"])
+        compare_particles(a.get_particles(), b.get_particles(), tp, 1e-8 if prec == E.FP64 else 1e-3)
+    # the simulations step on alone afterwards, on their own streams
+    batch[0].step(4)
+    alone[0].step(4)
+    compare_fields(batch[0], alone[0], 1e-4, names=("env", "ex", "er", "bt"))
+
+
+def test_batch_step_arguments(E):
+    cfg = scaled(C2_SMALL, n_modes=1)
+    a, b = E.Sim(cfg, E.FP32_BULK), E.Sim(cfg, E.FP32_BULK)
+    a.momentum()
+    with pytest.raises(E.EnvpicError) as ei:
+        E.batch_step([a, b], 2)
+    assert ei.value.code == -3
+    E.batch_step([b], 0)
+    E.batch_step([], 3)
+    assert b.state()[0] == 0
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_graph_mode_matches_direct_launches(E, prec):
     """step_n in graph mode (chunks of up to 7 steps captured into HIP graphs
