@@ -170,8 +170,9 @@ typedef struct envpic_sim envpic_sim;
 void envpic_params_default(envpic_params* p, int preset);
 
 /* Validate `p` (sizes, one-cell-per-step CFL dt < dx, dt < dr, envelope and
- * Yee stability on this grid) and report the arena bytes a simulation needs
- * at `precision`.  Returns ENVPIC_EINVAL with a message if invalid. */
+ * Yee stability on this grid, finite floating-point fields, a non-negative
+ * density and capacity) and report the arena bytes a simulation needs at
+ * `precision`.  Returns ENVPIC_EINVAL with a message if invalid. */
 int envpic_footprint(const envpic_params* p, int precision, size_t* bytes);
 
 /* Lay out and initialise a simulation inside `dev_arena` (device memory of
@@ -192,7 +193,8 @@ int envpic_envelope_step(envpic_sim* s);
 int envpic_project_chi_J(envpic_sim* s, int what);
 int envpic_field_step(envpic_sim* s);
 
-/* `nsteps` whole steps with the fused kernels (deposits inside the pushes). */
+/* `nsteps` whole steps with the fused kernels (deposits inside the pushes).
+ * ENVPIC_EINVAL for nsteps < 0; ENVPIC_EORDER inside a step. */
 int envpic_step_n(envpic_sim* s, int nsteps);
 
 /* Graph mode of envpic_step_n: with steps = k > 0, envpic_step_n captures
@@ -207,7 +209,8 @@ int envpic_set_graph(envpic_sim* s, int steps);
 /* Advance `count` resident simulations by `nsteps` each, interleaving their
  * stages on `hip_stream` so that their kernels overlap on the device.  Each
  * simulation keeps its own state; results equal envpic_step_n's within the
- * rounding of the deposit order. */
+ * rounding of the deposit order.  ENVPIC_EINVAL for count < 0, nsteps < 0,
+ * or a NULL or repeated simulation; ENVPIC_EORDER if one is inside a step. */
 int envpic_batch_step(envpic_sim* const* sims, int count, int nsteps, void* hip_stream);
 
 /* Synchronous IO (host buffers caller-owned, FP64).  `out`/`in` hold
@@ -223,7 +226,8 @@ int envpic_state(const envpic_sim* s, int64_t* n, int64_t* shift, int64_t* n_par
 int envpic_get_particles(const envpic_sim* s, double* x, double* y, double* z, double* px,
                          double* py, double* pz, double* w, uint32_t* id);
 /* Replace all particles (positions must lie inside the window and below
- * r_max); they are tile-sorted on the host before upload. */
+ * r_max, momenta and weights finite: ENVPIC_EINVAL otherwise; ENVPIC_ENOMEM
+ * beyond the capacity); they are tile-sorted on the host before upload. */
 int envpic_set_particles(envpic_sim* s, int64_t n, const double* x, const double* y,
                          const double* z, const double* px, const double* py, const double* pz,
                          const double* w, const uint32_t* id);
@@ -290,7 +294,8 @@ int envpic_bunch_fields(envpic_sim* s, uint32_t id_lo, uint32_t id_hi, double be
 /* Checkpoint: with host_blob == NULL, *bytes receives the size needed; else
  * the full state (step, shift, both envelope levels, E, B, Bbar, particles,
  * parameters) is written.  envpic_load restores a blob written by a
- * simulation with the same parameters and precision. */
+ * simulation with the same parameters and precision (ENVPIC_EINVAL for any
+ * other blob, a truncated one or one whose counts are out of range). */
 int envpic_save(const envpic_sim* s, void* host_blob, size_t* bytes);
 int envpic_load(envpic_sim* s, const void* host_blob, size_t bytes);
 

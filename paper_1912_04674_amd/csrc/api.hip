@@ -73,6 +73,10 @@ int validate(const envpic_params* p) {
     return fail(ENVPIC_EINVAL, "particles per cell must be in [1, 256]");
   if ((p->tile_x != 0 && p->tile_x != TX) || (p->tile_r != 0 && p->tile_r != TR))
     return fail(ENVPIC_EINVAL, "tile shape must be 16 x 16 (or 0 for the default)");
+  for (const double v : {p->dx, p->dr, p->dt, p->a0, p->w0, p->tau, p->x_c, p->x_f, p->n0, p->ramp_len, p->perturb,
+                         p->bump_x, p->bump_w})
+    if (!std::isfinite(v)) return fail(ENVPIC_EINVAL, "every floating-point parameter must be finite");
+  if (p->capacity < 0) return fail(ENVPIC_EINVAL, "capacity must be >= 0 (0: derived)");
   if (!(p->dx > 0 && p->dr > 0 && p->dt > 0)) return fail(ENVPIC_EINVAL, "dx, dr, dt must be positive");
   if (!(p->dt < p->dx && p->dt < p->dr))
     return fail(ENVPIC_EINVAL, "dt must be below dx and dr (particles move at most one cell per step)");
@@ -95,6 +99,8 @@ int validate(const envpic_params* p) {
   if (p->n0 < 0) return fail(ENVPIC_EINVAL, "n0 must be >= 0");
   if (p->profile == ENVPIC_PROFILE_RAMP && !(p->ramp_len > 0)) return fail(ENVPIC_EINVAL, "ramp_len must be > 0");
   if (p->profile == ENVPIC_PROFILE_BUMP && !(p->bump_w > 0)) return fail(ENVPIC_EINVAL, "bump_w must be > 0");
+  if (p->profile == ENVPIC_PROFILE_PERTURB && !(p->perturb >= 0 && p->perturb <= 1))
+    return fail(ENVPIC_EINVAL, "perturb must be in [0, 1] (a non-negative density)");
   if (p->a0 < 0 || (p->a0 > 0 && !(p->w0 > 0 && p->tau > 0))) return fail(ENVPIC_EINVAL, "bad laser parameters");
   const Sizes s = sizes_of(*p);
   if (s.capacity >= (1LL << 31) - 1) return fail(ENVPIC_EINVAL, "too many particles for int32 slots");
@@ -878,13 +884,16 @@ template <class R> struct SimT : envpic_sim {
 
   int set_particles(int64_t np, const double* const* in, const uint32_t* id) override {
     if (stage != 0) return fail(ENVPIC_EORDER, "set_particles only between steps");
-    if (np < 0 || np + (long long)p.nr * sz.ppc > sz.capacity) return fail(ENVPIC_ENOMEM, "too many particles for the capacity");
+    if (np < 0) return fail(ENVPIC_EINVAL, "negative particle count");
+    if (np + (long long)p.nr * sz.ppc > sz.capacity) return fail(ENVPIC_ENOMEM, "too many particles for the capacity");
     const Geo g = geo();
     const double rmax = p.nr * p.dr;
     std::vector<int> key(np), counts(sz.ntiles, 0);
     std::vector<int> ixv(np), jrv(np);
     std::vector<double> fxv(np), frv(np), thv(np);
     for (int64_t k = 0; k < np; ++k) {
+      if (!(std::isfinite(in[3][k]) && std::isfinite(in[4][k]) && std::isfinite(in[5][k]) && std::isfinite(in[6][k])))
+        return fail(ENVPIC_EINVAL, "non-finite particle momentum or weight");
       const double u = in[0][k] / p.dx;
       const double c = std::floor(u);
       const double r = std::sqrt(in[1][k] * in[1][k] + in[2][k] * in[2][k]);
@@ -1109,6 +1118,7 @@ int envpic_field_step(envpic_sim* s) { return s ? s->field() : fail(ENVPIC_EINVA
 
 int envpic_step_n(envpic_sim* s, int nsteps) {
   if (!s) return fail(ENVPIC_EINVAL, "NULL sim");
+  if (nsteps < 0) return fail(ENVPIC_EINVAL, "nsteps must be >= 0");
   if (s->stage != 0) return fail(ENVPIC_EORDER, "step_n called in the middle of a step");
   if (s->graph_steps > 0 && s->timing == 0) {
     for (int done = 0; done < nsteps;) {
@@ -1127,9 +1137,14 @@ int envpic_step_n(envpic_sim* s, int nsteps) {
 }
 
 int envpic_batch_step(envpic_sim* const* sims, int count, int nsteps, void* hip_stream) {
-  if (count < 0 || (count > 0 && !sims)) return fail(ENVPIC_EINVAL, "bad simulation list");
+  if (count < 0 || nsteps < 0 || (count > 0 && !sims)) return fail(ENVPIC_EINVAL, "bad simulation list or step count");
+  for (int k = 0; k < count; ++k) {
+    if (!sims[k]) return fail(ENVPIC_EINVAL, "NULL simulation in the list");
+    for (int m = 0; m < k; ++m)
+      if (sims[m] == sims[k]) return fail(ENVPIC_EINVAL, "a simulation appears twice in the list");
+  }
   for (int k = 0; k < count; ++k)
-    if (!sims[k] || sims[k]->stage != 0) return fail(ENVPIC_EORDER, "batch_step needs every simulation between steps");
+    if (sims[k]->stage != 0) return fail(ENVPIC_EORDER, "batch_step needs every simulation between steps");
   // interleave: step k of every simulation before step k+1 of any, each on
   // its own stream so that the kernels of different simulations overlap
   for (int st = 0; st < nsteps; ++st)
@@ -1322,6 +1337,13 @@ int envpic_load(envpic_sim* s, const void* blob, size_t bytes) {
   if (std::memcmp(h.magic, "ENVPIC01", 8) != 0 || h.prec != s->prec || h.nx != s->p.nx || h.nr != s->p.nr ||
       h.modes != s->p.n_modes)
     return fail(ENVPIC_EINVAL, "checkpoint does not match this simulation");
+  // the parameter block has no padding: equal parameters are equal bytes
+  static_assert(sizeof(envpic_params) == 12 * 4 + 8 + 13 * 8 + 8 + 2 * 4, "envpic_params has padding");
+  if (std::memcmp(&h.params, &s->p, sizeof(envpic_params)) != 0)
+    return fail(ENVPIC_EINVAL, "checkpoint written with other parameters");
+  if (h.nfields != n_ckpt_fields(s->p)) return fail(ENVPIC_EINVAL, "checkpoint field count does not match");
+  if (h.n < 0 || h.shift < 0 || h.nparticles < 0 || h.nparticles > s->sz.capacity)
+    return fail(ENVPIC_EINVAL, "checkpoint step, shift or particle count out of range");
   const char* q = (const char*)blob + sizeof h;
   size_t need = sizeof h;
   for (int k = 0; k < h.nfields; ++k) need += field_doubles(s->p, kCkptFields[k]) * sizeof(double);

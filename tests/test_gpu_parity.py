@@ -475,6 +475,37 @@ def test_checkpoint_resume(E, prec):
                       1e-10 if prec == "fp64" else 1e-3)
 
 
+def test_checkpoint_and_particle_upload_rejections(E):
+    """A checkpoint loads only into a simulation of the same parameters, and a
+    malformed one (field count, particle count, truncation) is refused before
+    anything is read from it; particles with non-finite momenta or weights
+    are refused."""
+    import struct
+    cfg = scaled(C2_SMALL, n_modes=1)
+    a = E.Sim(cfg, E.FP32_BULK)
+    a.step(3)
+    blob = a.save()
+    other = E.Sim(scaled(cfg, a0=cfg["a0"] * 1.1), E.FP32_BULK)
+    c = E.Sim(cfg, E.FP32_BULK)
+    bad_fields, bad_count = bytearray(blob), bytearray(blob)
+    struct.pack_into("<i", bad_fields, 28, 99)  # header: magic[8], version, prec, nx, nr, modes, nfields
+    struct.pack_into("<q", bad_count, 48, -1)   # then n, shift, nparticles
+    for sim, b in ((other, blob), (c, bytes(bad_fields)), (c, bytes(bad_count)), (c, blob[: len(blob) // 2])):
+        with pytest.raises(E.EnvpicError) as ei:
+            sim.load(b)
+        assert ei.value.code == -1
+    c.load(blob)
+    assert c.state() == a.state()
+    parts = a.get_particles()
+    for key, val in (("px", np.nan), ("w", np.inf)):
+        p2 = {k: v.copy() for k, v in parts.items()}
+        p2[key][1] = val
+        with pytest.raises(E.EnvpicError) as ei:
+            c.set_particles(p2)
+        assert ei.value.code == -1
+    assert c.state() == a.state()
+
+
 def test_stage_timing_does_not_change_results(E):
     """Stage timing records one launch per stage per step and leaves the
     result unchanged up to the deposit-order rounding of atomics."""
@@ -562,6 +593,10 @@ def test_batch_mixed_simulations(E):
 def test_batch_step_arguments(E):
     cfg = scaled(C2_SMALL, n_modes=1)
     a, b = E.Sim(cfg, E.FP32_BULK), E.Sim(cfg, E.FP32_BULK)
+    for call in (lambda: E.batch_step([a, b, a], 2), lambda: E.batch_step([a, b], -1), lambda: a.step(-1)):
+        with pytest.raises(E.EnvpicError) as ei:
+            call()
+        assert ei.value.code == -1
     a.momentum()
     with pytest.raises(E.EnvpicError) as ei:
         E.batch_step([a, b], 2)

@@ -60,6 +60,11 @@ def test_footprint_sizes(E):
     dict(n_modes=3),
     dict(ppc=(0, 2, 1)),
     dict(a0=-1.0),
+    dict(n0=float("nan")),
+    dict(x_c=float("inf")),
+    dict(a0=float("nan")),
+    dict(profile="perturb", perturb=1.5),
+    dict(capacity=-5),
 ])
 def test_validation_rejects(E, bad):
     from inputs import C1, scaled
