@@ -23,13 +23,18 @@ namespace envpic {
 // the x ends and at r_max.  A^{n+1} overwrites A^{n-1} in place.  With
 // fp64_rows the rows j = 0, 1 are advanced in FP64 from their own FP64
 // copies and rounded into the FP32 bulk array for the gathers.
+// reciprocal in the grid precision: FP64 division on the FP64 path, the
+// hardware reciprocal (about 1 ulp) on the FP32 path
+__device__ inline double recip_r(double x) { return 1.0 / x; }
+__device__ inline float recip_r(float x) { return __builtin_amdgcn_rcpf(x); }
+
 template <class R>
 __global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp64_rows) {
   using C = typename cplx_of<R>::type;
   const int nr1 = g.nr + 1;
-  const long long idx = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (long long)(g.nx + 1) * nr1) return;
-  const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
+  const int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x);  // nodes < 2^31
+  if (idx >= (g.nx + 1) * nr1) return;
+  const int i = idx / nr1, j = idx - i * nr1;
   const int pc = phys_col(g, i);
   const size_t o = (size_t)pc * g.pitch + j;
   const bool rows64 = fp64_rows && j <= 1;
@@ -70,7 +75,8 @@ __global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp6
   }
   const R rdt = (R)dt;
   const C a = f.env[o], aip = f.env[(size_t)pp * g.pitch + j], aim = f.env[(size_t)pm * g.pitch + j];
-  const R idx2 = (R)(1.0 / (g.dx * g.dx)), idr2 = (R)(1.0 / (g.dr * g.dr));
+  const R idx1 = recip_r((R)g.dx), idr1 = recip_r((R)g.dr);
+  const R idx2 = idx1 * idx1, idr2 = idr1 * idr1;
   R lx = (aip.x - (R)2 * a.x + aim.x) * idx2, ly = (aip.y - (R)2 * a.y + aim.y) * idx2;
   const C up = f.env[o + 1];
   if (j == 0) {
@@ -78,18 +84,19 @@ __global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp6
     ly += (R)4 * (up.y - a.y) * idr2;
   } else {
     const C dn = f.env[o - 1];
-    const R ir = (R)(1.0 / (2.0 * j * g.dr * g.dr));
+    const R ir = (R)0.5 * idr2 * recip_r((R)j);
     lx += (up.x - (R)2 * a.x + dn.x) * idr2 + (up.x - dn.x) * ir;
     ly += (up.y - (R)2 * a.y + dn.y) * idr2 + (up.y - dn.y) * ir;
   }
   const R ch = chi[o];
-  const R i2dx = (R)(1.0 / g.dx);
+  const R i2dx = idx1;
   const R rr = lx - ch * a.x - (aip.y - aim.y) * i2dx;
   const R ri = ly - ch * a.y + (aip.x - aim.x) * i2dx;
   const C ap = f.envp[o];
   const R br = (R)2 * a.x - (ap.x - rdt * ap.y) + rdt * rdt * rr;
   const R bi = (R)2 * a.y - (ap.y + rdt * ap.x) + rdt * rdt * ri;
-  f.envp[o] = mk<C>((R)pre_r * br - (R)pre_i * bi, (R)pre_r * bi + (R)pre_i * br);
+  const R pr = recip_r((R)1 + rdt * rdt), pim = rdt * pr;
+  f.envp[o] = mk<C>(pr * br - pim * bi, pr * bi + pim * br);
 }
 
 // ----------------------------------------------- Ampere and Faraday --
@@ -124,7 +131,7 @@ __device__ inline ENew<R, M1> ampere(const Geo& g, const Grids<R>& f, const Depo
   const int pc = phys_col(g, i);
   const size_t o = (size_t)pc * g.pitch + j;
   const size_t om = i > 0 ? (size_t)phys_col(g, i - 1) * g.pitch + j : o;
-  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  const R dt = (R)g.dt, idx_ = recip_r((R)g.dx), idr = recip_r((R)g.dr);
   const bool xin = i > 0 && i < g.nx;
   e.er = (j <= g.nr - 1 && xin) ? f.er[o] - dt * ((f.bt[o] - f.bt[om]) * idx_ + din.jr[o]) : (R)0;
   e.ex = 0;
@@ -132,7 +139,7 @@ __device__ inline ENew<R, M1> ampere(const Geo& g, const Grids<R>& f, const Depo
     if (j == 0) {
       e.ex = f.ex[o] + dt * ((R)4 * f.bt[o] * idr - din.jx[o]);
     } else if (j < g.nr) {
-      e.ex = f.ex[o] + dt * (((R)(j + 0.5) * f.bt[o] - (R)(j - 0.5) * f.bt[o - 1]) * ((R)(1.0 / j) * idr) - din.jx[o]);
+      e.ex = f.ex[o] + dt * (((R)(j + 0.5) * f.bt[o] - (R)(j - 0.5) * f.bt[o - 1]) * (recip_r((R)j) * idr) - din.jx[o]);
     }
   }
   if (M1) {
@@ -141,13 +148,13 @@ __device__ inline ENew<R, M1> ampere(const Geo& g, const Grids<R>& f, const Depo
     e.er1 = z;
     e.et1 = z;
     if (i <= g.nx - 1 && j >= 1 && j <= g.nr - 1) {
-      const R irj = (R)(1.0 / (j * g.dr));
+      const R irj = recip_r((R)j) * idr;
       const C curl = cadd(cscale(csub(cscale(f.bt1[o], (R)(j + 0.5)), cscale(f.bt1[o - 1], (R)(j - 0.5))), irj),
                           cscale(cmuli(f.br1[o]), irj));
       e.ex1 = cadd(f.ex1[o], cscale(csub(curl, din.jx1[o]), dt));
     }
     if (j <= g.nr - 1 && xin) {
-      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+      const R irh = recip_r((R)(j + 0.5)) * idr;
       const C curl = csub(cscale(cmuli(f.bx1[o]), -irh), cscale(csub(f.bt1[o], f.bt1[om]), idx_));
       e.er1 = cadd(f.er1[o], cscale(csub(curl, din.jr1[o]), dt));
       const C dbr = cscale(csub(f.br1[o], f.br1[om]), idx_);
@@ -184,7 +191,7 @@ __device__ inline void tile_node(const Geo& g, const Grids<R>& f, const DepositB
   using C = typename cplx_of<R>::type;
   constexpr int HJ = MwShared<R, M1>::HJ;
   const int kp = k + HJ;  // (i+1, j); k + 1 is (i, j+1)
-  const R dt = (R)g.dt, idx_ = (R)(1.0 / g.dx), idr = (R)(1.0 / g.dr);
+  const R dt = (R)g.dt, idx_ = recip_r((R)g.dx), idr = recip_r((R)g.dr);
   const bool ez = left_edge_zero && i == 1;
   // the new E of the owned node
   if (j <= g.nr - 1) f.er_n[o] = ez ? (R)0 : sm.er[k];
@@ -204,7 +211,7 @@ __device__ inline void tile_node(const Geo& g, const Grids<R>& f, const DepositB
   }
   if (M1) {
     if (j <= g.nr - 1) {
-      const R irh = (R)(1.0 / ((j + 0.5) * g.dr));
+      const R irh = recip_r((R)(j + 0.5)) * idr;
       const C b0 = bo.bx1;
       const C curl = cadd(cscale(csub(cscale(sm.et1[k + 1], (R)(j + 1)), cscale(sm.et1[k], (R)j)), irh),
                           cscale(cmuli(sm.er1[k]), irh));
@@ -213,7 +220,7 @@ __device__ inline void tile_node(const Geo& g, const Grids<R>& f, const DepositB
       f.bxb1[o] = cscale(cadd(b0, b1), (R)0.5);
     }
     if (i <= g.nx - 1) {
-      const C exr = j == 0 ? cscale(sm.ex1[k + 1], idr) : cscale(sm.ex1[k], (R)(1.0 / (j * g.dr)));
+      const C exr = j == 0 ? cscale(sm.ex1[k + 1], idr) : cscale(sm.ex1[k], recip_r((R)j) * idr);
       const C b0 = bo.br1;
       const C b1 = cadd(b0, cscale(cadd(cmuli(exr), cscale(csub(sm.et1[kp], sm.et1[k]), idx_)), dt));
       f.br1_n[o] = b1;
