@@ -301,6 +301,30 @@ __device__ inline int item_of(int b, int n) {
   return ((q / XG) * XCDS + x) * XG + (q - (q / XG) * XG);
 }
 
+// Rank of this lane among the lanes of its wavefront with the same slot
+// (slot < 0: none), added to a counter per slot with one LDS atomic per
+// distinct slot in the wavefront.  The lanes of a wavefront mostly share
+// one destination, which a per-lane atomic serialises on one LDS word.
+// Ranks follow lane order within a slot.  Call from wavefront-uniform
+// control flow.
+__device__ inline int wave_slot_rank(int slot, int* counters) {
+  const int lane = (int)__lane_id();
+  const unsigned long long below = (1ull << lane) - 1ull;
+  unsigned long long pending = __ballot(slot >= 0);
+  int rank = 0;
+  while (pending) {
+    const int leader = __ffsll((unsigned long long)pending) - 1;
+    const int s = __shfl(slot, leader);
+    const unsigned long long m = __ballot(slot == s);
+    int base = 0;
+    if (lane == leader) base = atomicAdd(&counters[s], (int)__popcll(m));
+    base = __shfl(base, leader);
+    if (slot == s) rank = base + (int)__popcll(m & below);
+    pending &= ~m;
+  }
+  return rank;
+}
+
 // SCAT: SCAT_NONE updates p in place and keeps the layout; otherwise every
 // particle moves into the next layout (the tiles of x^n).  SCAT_TILE keeps
 // the particles' relative order (coalesced writes); SCAT_CELL orders each
@@ -395,14 +419,14 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   for (int u = 0; u < PPT; ++u) {
     const int k = threadIdx.x + u * WG;
     slot_rank[u] = -1;
+    int tslot = -1;  // SCAT_TILE: destination tile of the 3 x 3 neighbourhood
     if (k < count) {
       const unsigned cw = src.cell[start + k];
       if (cw != kDead) {
         if (SCAT == SCAT_TILE) {
           const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
           const int dtr = clampi(cell_jr(cw) / TR - q.tcr, -1, 1, bad);
-          const int slot = (dtx + 1) * 3 + (dtr + 1);
-          slot_rank[u] = (slot << 16) | atomicAdd(&sm.ccell[slot], 1);
+          tslot = (dtx + 1) * 3 + (dtr + 1);
         } else if (SCAT == SCAT_CELL) {
           const int sx = clampi(cell_ix(cw) - (q.T * TX - SORT_EVERY), 0, CR - 1, bad);
           const int sr = clampi(cell_jr(cw) - (q.tcr * TR - SORT_EVERY), 0, CR - 1, bad);
@@ -412,6 +436,10 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
           slot_rank[u] = 0;
         }
       }
+    }
+    if (SCAT == SCAT_TILE) {  // the loop is wavefront-uniform (PPT iterations)
+      const int r = wave_slot_rank(tslot, sm.ccell);
+      if (tslot >= 0) slot_rank[u] = (tslot << 16) | r;
     }
   }
   __syncthreads();
