@@ -391,6 +391,35 @@ def test_dense_clusters_parity(E, oracle_mod, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+def test_fixed_point_sums_at_full_work_items(E, oracle_mod):
+    """The FP32 path's 64-bit fixed-point deposit sums at their bound: a
+    window of 4.2 M particle slots gives work items of 4096 particles, and
+    50 000 electrons of one weight share the axis cell (the smallest node
+    volume, which sets the scale) moving radially at 0.98 c, so every work
+    item adds 4096 contributions near the largest one (2^49) to the same LDS
+    words, about 2^61.  Three steps against the oracle at the FP32 bars."""
+    cfg = dict(nx=256, nr=64, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=0.0, ppc=(4, 4, 16))
+    say("fixed-point bound, 4096-particle work items")
+    rng = np.random.default_rng(4096)
+    n = 50_000
+    x = (128 + rng.uniform(0.0, 1.0, n)) * cfg["dx"]
+    r = rng.uniform(0.02, 0.5, n) * cfg["dr"]
+    th = rng.uniform(0.0, 2 * np.pi, n)
+    pr = rng.choice([-5.0, 5.0], n)
+    parts = dict(x=x, y=r * np.cos(th), z=r * np.sin(th), px=rng.uniform(-0.5, 0.5, n), py=pr * np.cos(th),
+                 pz=pr * np.sin(th), w=np.full(n, 1e-3), id=np.arange(n, dtype=np.uint32))
+    g = E.Sim(cfg, E.FP32_BULK)
+    o = oracle_mod.OracleSim(cfg)
+    g.set_particles(parts)
+    o.set_particles(parts)
+    g.step(3)
+    o.step(3)
+    assert g.state() == o.state()
+    assert g.diagnostics()["nonfinite"] == 0
+    compare_fields(g, o, 1e-4, names=("chi", "ex", "er", "bt", "jx", "jr"), modes=2)
+    compare_particles(g.get_particles(), o.get_particles(), 1e-3, 1e-3)
+
+
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_axis_crossing_and_wall_reflection(E, oracle_mod, prec):
     """Particles aimed through the axis and at r_max: crossings of r = 0
