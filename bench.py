@@ -254,7 +254,7 @@ def main():
         return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU; the multi-GPU x-slab "
-                                   "decomposition is not built (see DESIGN.md)", "n_gpus": args.gpus}))
+                                   "decomposition is a design only, not built", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import torch
