@@ -391,6 +391,43 @@ def test_dense_clusters_parity(E, oracle_mod, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_tile_scatter_to_many_destinations(E, oracle_mod, prec, tf, tp):
+    """Electrons clustered at every interior tile corner with fast random
+    momenta: the re-sorts at steps 3, 6 and 9 (the first by cell, then by
+    tile) send the particles of one wavefront to several of the nine
+    neighbouring tiles, which the per-wavefront destination ranks of the tile
+    scatter must count and order exactly.  Ten steps against the oracle."""
+    cfg = dict(nx=64, nr=48, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=0.0, ppc=(1, 1, 1),
+               capacity=40_000)
+    say("tile scatter to many destinations", prec)
+    rng = np.random.default_rng(916)
+    xs, ys, zs = [], [], []
+    for cx in (16, 32, 48):
+        for cr in (16, 32):
+            n = 1500
+            u = cx + rng.uniform(-1.0, 1.0, n)
+            v = cr + rng.uniform(-1.0, 1.0, n)
+            th = rng.uniform(0.0, 2 * np.pi, n)
+            xs.append(u * cfg["dx"])
+            ys.append(v * cfg["dr"] * np.cos(th))
+            zs.append(v * cfg["dr"] * np.sin(th))
+    x, y, z = np.concatenate(xs), np.concatenate(ys), np.concatenate(zs)
+    n = len(x)
+    p = rng.normal(0.0, 1.5, (3, n))
+    parts = dict(x=x, y=y, z=z, px=p[0], py=p[1], pz=p[2], w=rng.uniform(0.5, 1.5, n) * 1e-3,
+                 id=np.arange(n, dtype=np.uint32))
+    g = E.Sim(cfg, _prec(E, prec))
+    o = oracle_mod.OracleSim(cfg)
+    g.set_particles(parts)
+    o.set_particles(parts)
+    g.step(10)
+    o.step(10)
+    assert g.state() == o.state()
+    compare_fields(g, o, tf, names=("chi", "ex", "er", "bt", "jx", "jr"), modes=2)
+    compare_particles(g.get_particles(), o.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
 def test_fixed_point_sums_at_full_work_items(E, oracle_mod):
     """The FP32 path's 64-bit fixed-point deposit sums at their bound: a
     window of 4.2 M particle slots gives work items of 4096 particles, and
