@@ -303,6 +303,9 @@ int envpic_load(envpic_sim* s, const void* host_blob, size_t bytes);
  * detection through the diagnostics). */
 int envpic_debug_poison(envpic_sim* s, int field);
 
+/* Frees the handle.  It first waits for every kernel the simulation has
+ * queued on its stream, so the caller may release or reuse the arena as soon
+ * as this returns.  NULL is ignored. */
 void envpic_sim_destroy(envpic_sim* s);
 
 /* Message of the last error on this thread (s may be NULL). */

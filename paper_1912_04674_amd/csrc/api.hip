@@ -1370,7 +1370,13 @@ int envpic_load(envpic_sim* s, const void* blob, size_t bytes) {
 
 int envpic_debug_poison(envpic_sim* s, int field) { return s ? s->poison(field) : fail(ENVPIC_EINVAL, "NULL sim"); }
 
-void envpic_sim_destroy(envpic_sim* s) { delete s; }
+void envpic_sim_destroy(envpic_sim* s) {
+  if (!s) return;
+  // the arena returns to the caller: no kernel of this simulation may still
+  // be reading or writing it
+  (void)hipStreamSynchronize(s->stream);
+  delete s;
+}
 
 const char* envpic_last_error(const envpic_sim*) { return g_last_error.c_str(); }
 

@@ -171,10 +171,15 @@ class Sim:
         self.nx, self.nr = self.params.nx, self.params.nr
         self.precision = precision
         need = footprint(self.params, precision)
-        if arena is None:
+        own = arena is None
+        if own:
             arena = torch.empty(need, dtype=torch.uint8, device="cuda")
         self.arena = arena
         self.stream = stream if stream is not None else torch.cuda.current_stream()
+        if own and self.stream != torch.cuda.current_stream():
+            # the caching allocator must not hand the block out again while
+            # kernels queued on the simulation's stream may still use it
+            arena.record_stream(self.stream)
         h = ctypes.c_void_p()
         _check(lib().envpic_sim_init(ctypes.byref(self.params), int(precision),
                                      ctypes.c_void_p(arena.data_ptr()), arena.numel() * arena.element_size(),
