@@ -65,6 +65,17 @@
  *                          fold; discrete Gauss law and continuity of the
  *                          order-2 Esirkepov current with axis folds; mode-1
  *                          J fold parity; moving window = static run
+ *   diagnostics            U_EM of fields sampled from closed forms (a uniform
+ *                          transverse field as mode 1, sines along x, known
+ *                          quadrature defects of the node and half-row volumes
+ *                          along r); kinetic energy and P_x of rational-gamma
+ *                          momenta and after a uniform-E_x kick; L_x of a
+ *                          rotating ring; sum |A|^2 V of the initial paraxial
+ *                          pulse with the Euler-Maclaurin axis terms
+ *   plasma profiles        column charge of the ramp and bump, chi following
+ *                          the linear ramp exactly, per-cell charge of the
+ *                          perturbed density; sixteen planted mistakes in
+ *                          these sums and profiles each fail a pin
  *   step order, gbar and   documented choices with no value printed in the
  *   Phi centring (R6-R8)   paper: PARITY UNPINNED beyond the convergence
  *                          order the luminal test fixes.

@@ -60,15 +60,18 @@ def build(force=False):
     return LIB_PATH
 
 
-_lib = None
+_libs = {}
 
 
-def lib():
-    global _lib
-    if _lib is None:
-        if not os.path.exists(LIB_PATH):
+def lib(path=None):
+    """The loaded oracle library (by default liboracle.so next to this file;
+    `path` loads another build of the same source, e.g. a planted-mistake
+    variant made by build_variant)."""
+    path = path or LIB_PATH
+    if path not in _libs:
+        if path == LIB_PATH and not os.path.exists(LIB_PATH):
             build()
-        L = ctypes.CDLL(LIB_PATH)
+        L = ctypes.CDLL(path)
         vp = ctypes.c_void_p
         dp = ctypes.POINTER(ctypes.c_double)
         up = ctypes.POINTER(ctypes.c_uint32)
@@ -90,8 +93,40 @@ def lib():
         L.oracle_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                      ctypes.c_int64]
         L.oracle_uniform.restype = ctypes.c_double
-        _lib = L
-    return _lib
+        _libs[path] = L
+    return _libs[path]
+
+
+def build_variant(edits, workdir):
+    """Compile a copy of oracle.cpp with textual edits [(old, new), ...] into
+    `workdir` and return the library path.  Used only to show that the pins
+    catch planted mistakes; every `old` must occur exactly once."""
+    src = open(os.path.join(_HERE, "oracle.cpp")).read()
+    for old, new in edits:
+        assert src.count(old) == 1, f"edit target not unique: {old!r}"
+        src = src.replace(old, new)
+    os.makedirs(workdir, exist_ok=True)
+    cpp = os.path.join(workdir, "oracle.cpp")
+    with open(cpp, "w") as f:
+        f.write(src)
+    out = os.path.join(workdir, "liboracle.so")
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-I", _HERE,
+                           "-o", out, cpp])
+    return out
+
+
+class Variant:
+    """Module-like view of another oracle build (same interface as this
+    module's OracleSim and uniform)."""
+
+    def __init__(self, path):
+        self.path = path
+
+    def OracleSim(self, cfg):
+        return OracleSim(cfg, lib_path=self.path)
+
+    def uniform(self, seed, stream, col, j):
+        return lib(self.path).oracle_uniform(seed, stream, col, j)
 
 
 def _dptr(a):
@@ -128,19 +163,20 @@ def make_params(cfg):
 class OracleSim:
     """One oracle simulation (host memory)."""
 
-    def __init__(self, cfg):
+    def __init__(self, cfg, lib_path=None):
+        self._L = lib(lib_path)
         self.cfg = dict(cfg)
         self.nx, self.nr = int(cfg["nx"]), int(cfg["nr"])
         self._p = make_params(cfg)
         h = ctypes.c_void_p()
-        rc = lib().oracle_create(ctypes.byref(self._p), ctypes.byref(h))
+        rc = self._L.oracle_create(ctypes.byref(self._p), ctypes.byref(h))
         if rc != 0:
             raise ValueError(f"oracle_create failed ({rc}) for {cfg}")
         self._h = h
 
     def close(self):
         if self._h:
-            lib().oracle_destroy(self._h)
+            self._L.oracle_destroy(self._h)
             self._h = None
 
     def __del__(self):
@@ -151,27 +187,27 @@ class OracleSim:
 
     # stages
     def momentum_chi(self):
-        lib().oracle_momentum_chi(self._h)
+        self._L.oracle_momentum_chi(self._h)
 
     def envelope(self):
-        lib().oracle_envelope(self._h)
+        self._L.oracle_envelope(self._h)
 
     def position_J(self):
-        lib().oracle_position_J(self._h)
+        self._L.oracle_position_J(self._h)
 
     def field_step(self):
-        lib().oracle_field_step(self._h)
+        self._L.oracle_field_step(self._h)
 
     def filter_J(self):
-        lib().oracle_filter_J(self._h)
+        self._L.oracle_filter_J(self._h)
 
     def step(self, n=1):
-        lib().oracle_step(self._h, int(n))
+        self._L.oracle_step(self._h, int(n))
 
     # state
     def state(self):
         n, s, npart = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
-        lib().oracle_state(self._h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(npart))
+        self._L.oracle_state(self._h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(npart))
         return n.value, s.value, npart.value
 
     @property
@@ -182,7 +218,7 @@ class OracleSim:
         npart = self.n_particles
         out = {k: np.zeros(npart) for k in ("x", "y", "z", "px", "py", "pz", "w")}
         ids = np.zeros(npart, dtype=np.uint32)
-        lib().oracle_get_particles(self._h, *(_dptr(out[k]) for k in
+        self._L.oracle_get_particles(self._h, *(_dptr(out[k]) for k in
                                               ("x", "y", "z", "px", "py", "pz", "w")),
                                    ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
         out["id"] = ids
@@ -193,26 +229,26 @@ class OracleSim:
         arrs = [np.ascontiguousarray(parts[k], dtype=np.float64)
                 for k in ("x", "y", "z", "px", "py", "pz", "w")]
         ids = np.ascontiguousarray(parts["id"], dtype=np.uint32)
-        rc = lib().oracle_set_particles(self._h, n, *(_dptr(a) for a in arrs),
+        rc = self._L.oracle_set_particles(self._h, n, *(_dptr(a) for a in arrs),
                                         ids.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32)))
         if rc != 0:
             raise ValueError("oracle_set_particles failed")
 
     def get_gbar(self):
         g = np.zeros(self.n_particles)
-        lib().oracle_get_gbar(self._h, _dptr(g))
+        self._L.oracle_get_gbar(self._h, _dptr(g))
         return g
 
     def get_field(self, name):
         shape = (self.nx + 1, self.nr + 1)
         if name in COMPLEX_FIELDS:
             buf = np.zeros(2 * shape[0] * shape[1])
-            rc = lib().oracle_get_field(self._h, FIELDS[name], _dptr(buf))
+            rc = self._L.oracle_get_field(self._h, FIELDS[name], _dptr(buf))
             if rc != 0:
                 raise ValueError(f"field {name} unavailable")
             return (buf[0::2] + 1j * buf[1::2]).reshape(shape)
         buf = np.zeros(shape[0] * shape[1])
-        rc = lib().oracle_get_field(self._h, FIELDS[name], _dptr(buf))
+        rc = self._L.oracle_get_field(self._h, FIELDS[name], _dptr(buf))
         if rc != 0:
             raise ValueError(f"field {name} unavailable")
         return buf.reshape(shape)
@@ -227,13 +263,13 @@ class OracleSim:
             buf[0::2], buf[1::2] = flat.real, flat.imag
         else:
             buf = np.ascontiguousarray(arr, dtype=np.float64).ravel()
-        rc = lib().oracle_set_field(self._h, FIELDS[name], _dptr(buf))
+        rc = self._L.oracle_set_field(self._h, FIELDS[name], _dptr(buf))
         if rc != 0:
             raise ValueError(f"field {name} unavailable")
 
     def diagnostics(self):
         out = np.zeros(len(DIAG_NAMES))
-        lib().oracle_diagnostics(self._h, _dptr(out))
+        self._L.oracle_diagnostics(self._h, _dptr(out))
         return dict(zip(DIAG_NAMES, out))
 
 
