@@ -227,10 +227,7 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   S.ccur = cv.take<int>(ng);
   S.err = cv.take<int>(1);
   S.pending = cv.take<int>(2);
-  Geo g{};
-  g.nx = p.nx;
-  g.nr = p.nr;
-  S.diag_scratch = cv.take<double>((size_t)diag_scratch_doubles(s.max_items, g));
+  S.diag_scratch = cv.take<double>((size_t)diag_scratch_doubles());
   S.diag_out = cv.take<double>(ENVPIC_NDIAG);
   S.beam.hist = cv.take<unsigned long long>(BEAM_MAX_BINS);
   S.beam.hist_f = cv.take<double>(BEAM_MAX_BINS);
@@ -947,8 +944,8 @@ template <class R> struct SimT : envpic_sim {
 
   int diagnostics(double* out) override {
     const Geo g = geo();
-    launch_diag<R>(g, S.parts[cur], S.lay[cur], sz.max_items, S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0,
-                   S.diag_scratch, S.diag_out, stream);
+    launch_diag<R>(g, S.parts[cur], S.lay[cur], S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0, S.diag_scratch,
+                   S.diag_out, stream);
     int rc = launched("diagnostics");
     if (rc) return rc;
     if ((rc = hip_check(hipMemcpyAsync(out, S.diag_out, ENVPIC_NDIAG * sizeof(double), hipMemcpyDeviceToHost, stream), "diag read"))) return rc;

@@ -76,10 +76,13 @@ void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, co
 template <class R>
 void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st);
 
-int diag_scratch_doubles(int max_items, const Geo& g);
+// FP64 diagnostics (sort_diag.hip): a fixed number of work groups, so the
+// partial sums take diag_scratch_doubles() doubles for any simulation size
+constexpr int DIAG_BLOCKS = 1024;
+int diag_scratch_doubles();
 template <class R>
-void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, int max_items, const Grids<R>& f, const R* chi,
-                 int fp64_rows, double* scratch, double* out, hipStream_t st);
+void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, const Grids<R>& f, const R* chi, int fp64_rows,
+                 double* scratch, double* out, hipStream_t st);
 
 // injected-beam parameters (beam.hip)
 constexpr int BEAM_MAX_BINS = 4096;

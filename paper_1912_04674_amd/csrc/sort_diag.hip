@@ -1,35 +1,64 @@
-// sort_diag.hip -- the FP64 conserved-sum diagnostics (work-group tree
-// reductions, summed in a fixed order).  The counting sort's scans are in
-// scan.hpp (run inside the field-stage kernel).
+// sort_diag.hip -- the FP64 conserved-sum diagnostics: charge, chi V,
+// kinetic energy, field energy, envelope norm, L_x, P_x and a non-finite
+// count of the state.  (The counting sort's scans are in scan.hpp, run inside
+// the field-stage kernel.)
+//
+// Reduction order is fixed, so a sum is bitwise the same from run to run:
+//   * a fixed number of work groups (DIAG_BLOCKS) strides over the work
+//     items (particle sums) or the grid nodes (grid sums), each thread adding
+//     its own elements in index order;
+//   * each wavefront sums its 64 lanes with a shuffle butterfly (lanes l and
+//     l ^ m exchange and add, m = 32 .. 1; IEEE addition is commutative, so
+//     every lane ends with the same total);
+//   * the group adds its wavefronts' totals in wavefront order, and a last
+//     one-group kernel adds the groups' totals, lane-strided, then one more
+//     butterfly.
+// The partial sums need DIAG_BLOCKS * (NPD + NGD) doubles whatever the
+// simulation's size.
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
 
 namespace envpic {
 
-// ---------------------------------------------------------- diagnostics --
-constexpr int DG = 256;
+constexpr int DG = 256;            // threads per group (4 wavefronts)
+constexpr int DWAVES = DG / 64;
+constexpr int NPD = 6;             // count, charge, kinetic energy, L_x, P_x, non-finite
+constexpr int NGD = 5;             // chi V, |A|^2 V, mode-0 energy, mode-1 energy, non-finite
 
-template <int N>
-__device__ inline void block_sum(double (&v)[N], double* red /* [N][DG] */, double* out) {
-  for (int k = 0; k < N; ++k) red[k * DG + threadIdx.x] = v[k];
-  __syncthreads();
-  for (int s = DG / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s)
-      for (int k = 0; k < N; ++k) red[k * DG + threadIdx.x] += red[k * DG + threadIdx.x + s];
-    __syncthreads();
-  }
-  if (threadIdx.x < N) out[threadIdx.x] = red[threadIdx.x * DG];
+// sum of v over the lanes of this wavefront, in the same order on every call
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
 }
 
-// per work item: count, charge, kinetic energy, L_x, P_x, non-finite count
-constexpr int NPD = 6;
+// the group's sums of v[0..N) into out[0..N): wavefront butterflies, then
+// the wavefront totals in wavefront order
+template <int N>
+__device__ inline void group_sum(const double (&v)[N], double* out) {
+  __shared__ double wv[DWAVES][N];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < N; ++k) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) wv[wave][k] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < N) {
+    double s = 0.0;
+    for (int w = 0; w < DWAVES; ++w) s += wv[w][threadIdx.x];
+    out[threadIdx.x] = s;
+  }
+}
+
+// per group: count, charge, kinetic energy, L_x, P_x, non-finite count over
+// the work items b, b + DIAG_BLOCKS, ...
 template <class R>
 __global__ __launch_bounds__(DG) void k_diag_particles(Geo g, Parts<R> P, Layout L, double* __restrict__ part) {
-  __shared__ double red[NPD * DG];
   double v[NPD] = {0, 0, 0, 0, 0, 0};
-  const int item = blockIdx.x;
-  if (item < *L.n_items) {
+  const int n_items = *L.n_items;
+  for (int item = blockIdx.x; item < n_items; item += DIAG_BLOCKS) {
     const int4 it = L.items[item];
     for (int k = threadIdx.x; k < it.z; k += DG) {
       const int p = it.y + k;
@@ -43,29 +72,28 @@ __global__ __launch_bounds__(DG) void k_diag_particles(Geo g, Parts<R> P, Layout
       const double p2 = px * px + py * py + pz * pz;
       v[0] += 1.0;
       v[1] += -w;
-      v[2] += w * p2 / (1.0 + sqrt(1.0 + p2));
-      v[3] += w * r * (c * pz - s * py);  // y p_z - z p_y
+      v[2] += w * p2 / (1.0 + sqrt(1.0 + p2));  // w (gamma - 1) without cancellation
+      v[3] += w * r * (c * pz - s * py);        // y p_z - z p_y
       v[4] += w * px;
       const double vals[7] = {w, px, py, pz, fr, th, fx};
       for (int e = 0; e < 7; ++e)
         if (!isfinite(vals[e])) v[5] += 1.0;
     }
   }
-  block_sum<NPD>(v, red, part + (size_t)item * NPD);
+  group_sum<NPD>(v, part + (size_t)blockIdx.x * NPD);
 }
 
-// per block of nodes: sum chi V, sum |A|^2 V, mode-0 and mode-1 energy, non-finite count
-constexpr int NGD = 5;
+// per group: sum chi V, sum |A|^2 V, mode-0 and mode-1 field energy sums,
+// non-finite count over the nodes idx = (b + k DIAG_BLOCKS) DG + t
 template <class R>
 __global__ __launch_bounds__(DG) void k_diag_grid(Geo g, Grids<R> f, const R* __restrict__ chi, int fp64_rows,
                                                   double* __restrict__ part) {
   using C = typename cplx_of<R>::type;
-  __shared__ double red[NGD * DG];
   double v[NGD] = {0, 0, 0, 0, 0};
   const int nr1 = g.nr + 1;
-  const long long idx = (long long)blockIdx.x * DG + threadIdx.x;
-  if (idx < (long long)(g.nx + 1) * nr1) {
-    const double pi = 3.14159265358979323846;
+  const long long nodes = (long long)(g.nx + 1) * nr1;
+  const double pi = 3.14159265358979323846;
+  for (long long idx = (long long)blockIdx.x * DG + threadIdx.x; idx < nodes; idx += (long long)DIAG_BLOCKS * DG) {
     const int i = (int)(idx / nr1), j = (int)(idx - (long long)i * nr1);
     const int pc = phys_col(g, i);
     const size_t o = (size_t)pc * g.pitch + j;
@@ -80,8 +108,8 @@ __global__ __launch_bounds__(DG) void k_diag_grid(Geo g, Grids<R> f, const R* __
       ai = f.env[o].y;
     }
     const double ch = chi[o];
-    v[0] = ch * vn;
-    v[1] = (ar * ar + ai * ai) * vn;
+    v[0] += ch * vn;
+    v[1] += (ar * ar + ai * ai) * vn;
     const double ex = f.ex[o], er = f.er[o], bt = f.bt[o];
     if (i <= g.nx - 1) v[2] += ex * ex * vn;
     if (j <= g.nr - 1) v[2] += er * er * vh;
@@ -99,39 +127,33 @@ __global__ __launch_bounds__(DG) void k_diag_grid(Geo g, Grids<R> f, const R* __
       if (i <= g.nx - 1 && j <= g.nr - 1) v[3] += (double)cnorm(bt1) * vh;
     }
   }
-  block_sum<NGD>(v, red, part + (size_t)blockIdx.x * NGD);
+  group_sum<NGD>(v, part + (size_t)blockIdx.x * NGD);
 }
 
-// fixed-order final sums (one thread per quantity)
-__global__ void k_diag_final(const double* __restrict__ pp, int np_blocks, const double* __restrict__ pg,
-                             int ng_blocks, double* __restrict__ out) {
-  // wavefront q sums quantity q: lane l takes blocks l, l + 64, ..., then a
-  // fixed-order tree over the lanes (the result does not depend on timing)
-  __shared__ double lanes[NPD + NGD][64];
-  const int q = threadIdx.x / 64, l = threadIdx.x % 64;
+// the groups' sums in a fixed order (wavefront q sums quantity q), mapped
+// onto the public diagnostics vector
+__global__ __launch_bounds__(64 * (NPD + NGD)) void k_diag_final(const double* __restrict__ pp,
+                                                                 const double* __restrict__ pg,
+                                                                 double* __restrict__ out) {
+  __shared__ double t[NPD + NGD];
+  const int q = threadIdx.x >> 6, l = threadIdx.x & 63;
   double s = 0.0;
   if (q < NPD) {
-    for (int b = l; b < np_blocks; b += 64) s += pp[(size_t)b * NPD + q];
-  } else if (q < NPD + NGD) {
-    for (int b = l; b < ng_blocks; b += 64) s += pg[(size_t)b * NGD + (q - NPD)];
+    for (int b = l; b < DIAG_BLOCKS; b += 64) s += pp[(size_t)b * NPD + q];
+  } else {
+    for (int b = l; b < DIAG_BLOCKS; b += 64) s += pg[(size_t)b * NGD + (q - NPD)];
   }
-  if (q < NPD + NGD) lanes[q][l] = s;
-  __syncthreads();
-  for (int h = 32; h > 0; h >>= 1) {
-    if (q < NPD + NGD && l < h) lanes[q][l] += lanes[q][l + h];
-    __syncthreads();
-  }
-  // map onto the public diagnostics vector
-  // pp: 0 count, 1 charge, 2 kin, 3 lx, 4 px, 5 nonfinite
-  // pg: 0 chi V, 1 |A|^2 V, 2 u0, 3 u1, 4 nonfinite
-  __shared__ double t[NPD + NGD];
-  if (l == 0 && q < NPD + NGD) t[q] = lanes[q][0];
+  s = wave_sum(s);
+  if (l == 0) t[q] = s;
   __syncthreads();
   if (threadIdx.x == 0) {
+    // pp: count, charge, kinetic, L_x, P_x, non-finite;
+    // pg: chi V, |A|^2 V, mode-0 energy, mode-1 energy, non-finite
     out[0] = t[0];
     out[1] = t[1];
     out[2] = t[NPD + 0];
     out[3] = t[2];
+    // a mode-1 amplitude F carries a mean square |F|^2 / 2 over the azimuth
     out[4] = 0.5 * t[NPD + 2] + 0.25 * t[NPD + 3];
     out[5] = t[NPD + 1];
     out[6] = t[3];
@@ -140,25 +162,21 @@ __global__ void k_diag_final(const double* __restrict__ pp, int np_blocks, const
   }
 }
 
-int diag_scratch_doubles(int max_items, const Geo& g) {
-  const long long nb = ((long long)(g.nx + 1) * (g.nr + 1) + DG - 1) / DG;
-  return max_items * NPD + (int)nb * NGD;
-}
+int diag_scratch_doubles() { return DIAG_BLOCKS * (NPD + NGD); }
 
 template <class R>
-void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, int max_items, const Grids<R>& f, const R* chi,
-                 int fp64_rows, double* scratch, double* out, hipStream_t st) {
-  const int nb = (int)(((long long)(g.nx + 1) * (g.nr + 1) + DG - 1) / DG);
+void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, const Grids<R>& f, const R* chi, int fp64_rows,
+                 double* scratch, double* out, hipStream_t st) {
   double* pp = scratch;
-  double* pg = scratch + (size_t)max_items * NPD;
-  hipLaunchKernelGGL((k_diag_particles<R>), dim3(max_items), dim3(DG), 0, st, g, P, L, pp);
-  hipLaunchKernelGGL((k_diag_grid<R>), dim3(nb), dim3(DG), 0, st, g, f, chi, fp64_rows, pg);
-  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * (NPD + NGD)), 0, st, pp, max_items, pg, nb, out);
+  double* pg = scratch + (size_t)DIAG_BLOCKS * NPD;
+  hipLaunchKernelGGL((k_diag_particles<R>), dim3(DIAG_BLOCKS), dim3(DG), 0, st, g, P, L, pp);
+  hipLaunchKernelGGL((k_diag_grid<R>), dim3(DIAG_BLOCKS), dim3(DG), 0, st, g, f, chi, fp64_rows, pg);
+  hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(64 * (NPD + NGD)), 0, st, pp, pg, out);
 }
 
-template void launch_diag<float>(const Geo&, const Parts<float>&, const Layout&, int, const Grids<float>&,
-                                 const float*, int, double*, double*, hipStream_t);
-template void launch_diag<double>(const Geo&, const Parts<double>&, const Layout&, int, const Grids<double>&,
+template void launch_diag<float>(const Geo&, const Parts<float>&, const Layout&, const Grids<float>&, const float*,
+                                 int, double*, double*, hipStream_t);
+template void launch_diag<double>(const Geo&, const Parts<double>&, const Layout&, const Grids<double>&,
                                   const double*, int, double*, double*, hipStream_t);
 
 }  // namespace envpic

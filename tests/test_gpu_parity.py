@@ -214,6 +214,96 @@ def test_window_modes01_parity(E, oracle_mod, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+DIAG_KEYS = ("count", "charge", "chi_v", "kin", "uem", "env2_v", "lx", "px", "nonfinite")
+
+
+def _diag_state(cfg, oracle_mod, seed=31):
+    """The workload's loaded plasma given azimuthal momenta (p_theta of
+    either sign, so L_x = sum w r p_theta is far from zero) and a drift along
+    y (a mode-1 current), plus smooth random mode-1 E fields: a state whose
+    field energy has a large mode-1 part."""
+    r = oracle_mod.OracleSim(cfg)
+    parts = r.get_particles()
+    rng = np.random.default_rng(seed)
+    n = len(parts["x"])
+    rad = np.hypot(parts["y"], parts["z"])
+    c = np.where(rad > 0, parts["y"] / np.maximum(rad, 1e-300), 1.0)
+    sn = np.where(rad > 0, parts["z"] / np.maximum(rad, 1e-300), 0.0)
+    pt = rng.uniform(-0.3, 0.3, n) + 0.1
+    parts["py"] = -pt * sn + 0.02
+    parts["pz"] = pt * c
+    parts["px"] = rng.uniform(-0.05, 0.05, n)
+    fields = {name: random_grid(cfg, 40 + k, 0.01, True) for k, name in enumerate(("ex1", "er1", "et1"))}
+    return parts, {k: staggered(k, v) for k, v in fields.items()}
+
+
+def compare_diagnostics(dg, dr_, parts_ref, tol):
+    """All nine sums: counts exact; L_x against the scale sum |w r p_theta|
+    of the reference particles (it is a sum of terms of both signs); the rest
+    relative to their own size."""
+    say("diag gpu", {k: f"{dg[k]:.12e}" for k in DIAG_KEYS})
+    say("diag ref", {k: f"{dr_[k]:.12e}" for k in DIAG_KEYS})
+    assert dg["count"] == dr_["count"]
+    assert dg["nonfinite"] == dr_["nonfinite"] == 0
+    lx_scale = float(np.sum(np.abs(parts_ref["w"] * (parts_ref["y"] * parts_ref["pz"] - parts_ref["z"] * parts_ref["py"]))))
+    px_scale = float(np.sum(np.abs(parts_ref["w"] * parts_ref["px"])))
+    errs = {}
+    for k in ("charge", "chi_v", "kin", "uem", "env2_v"):  # (chi is zero before the first step)
+        errs[k] = abs(dg[k] - dr_[k]) / (abs(dr_[k]) if dr_[k] != 0 else 1.0)
+    errs["lx"] = abs(dg["lx"] - dr_["lx"]) / lx_scale
+    errs["px"] = abs(dg["px"] - dr_["px"]) / px_scale
+    say("diag errors", {k: f"{v:.2e}" for k, v in errs.items()})
+    for k, e in errs.items():
+        assert e <= tol, (k, e)
+    return errs
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-11), ("fp32", 2e-4)])
+def test_diagnostics_parity_modes01(E, oracle_mod, prec, tol):
+    """Every FP64 conserved sum (count, charge, chi V, kinetic energy, field
+    energy with its mode-1 part, |A|^2 V, L_x, P_x, non-finite count) of the
+    GPU against the oracle's, on a modes-0+1 window run with injection whose
+    electrons carry azimuthal momentum and whose mode-1 fields start nonzero:
+    at the start, after one step and after 100 steps (75 window shifts)."""
+    say("diagnostics parity, modes 0+1", prec)
+    parts, fields = _diag_state(C2_SMALL, oracle_mod)
+    g = E.Sim(C2_SMALL, _prec(E, prec))
+    r = oracle_mod.OracleSim(C2_SMALL)
+    for sim in (g, r):
+        sim.set_particles(parts)
+        for k, v in fields.items():
+            sim.set_field(k, v)
+    dg, dr_ = g.diagnostics(), r.diagnostics()
+    e0 = compare_diagnostics(dg, dr_, r.get_particles(), 1e-13 if prec == "fp64" else 2e-6)
+    assert abs(dr_["lx"]) > 0.05 * float(np.sum(np.abs(parts["w"] * np.hypot(parts["y"], parts["z"]) * 0.1)))
+    for steps in (1, 99):
+        g.step(steps)
+        r.step(steps)
+        compare_diagnostics(g.diagnostics(), r.diagnostics(), r.get_particles(), tol)
+    assert g.state()[:2] == r.state()[:2] == (100, 75)
+    # the mode-1 energy is a large part of the total: with the fields of
+    # mode 1 zeroed on both sides the totals drop by well over the tolerance
+    u_all = r.diagnostics()["uem"]
+    for n in ("ex1", "er1", "et1", "bx1", "br1", "bt1"):
+        z = np.zeros_like(r.get_field(n))
+        g.set_field(n, z)
+        r.set_field(n, z)
+    u0_ref, u0_gpu = r.diagnostics()["uem"], g.diagnostics()["uem"]
+    assert u_all - u0_ref > 100 * tol * u_all
+    assert abs(u0_gpu - u0_ref) <= tol * u0_ref
+
+
+def test_diagnostics_are_bitwise_reproducible(E):
+    """Fixed-order reductions: the same state gives the same sums, bit for
+    bit, on repeated calls."""
+    g = E.Sim(C2_SMALL, E.FP32_BULK)
+    g.step(7)
+    a = g.diagnostics()
+    for _ in range(3):
+        b = g.diagnostics()
+        assert all(a[k] == b[k] for k in DIAG_KEYS), (a, b)
+
+
 # ------------------------------------------------------------ API paths --
 # ------------------------------------------------------------ edge cases --
 RAGGED = dict(name="ragged", nx=101, nr=21, dx=0.8, dr=1.5, dt=0.6, n_modes=2, ppc=(2, 3, 3),
