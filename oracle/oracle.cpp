@@ -35,6 +35,11 @@
  *   R17 loading regular in x and r, one random angle per cell, equally spaced
  *       angles inside the cell, weights proportional to r
  *   R21 Bbar^n = (B^{n-1/2} + B^{n+1/2}) / 2
+ * Threads (oracle_set_threads, default 1): the particle loops of the
+ * momentum and position stages split the particles into equal contiguous
+ * ranges, one per thread; each thread deposits chi or J into grids of its
+ * own, which are then added in thread order.  Results are therefore
+ * identical for a given thread count; one thread is the plain loop.
  *   R24 optional binomial current filter (Sec. 4, nonlinear benchmark: an
  *       uncompensated binomial filter of 7 passes): N passes of 1-2-1 in
  *       index space, each along x then along r, on J^{n+1/2} of both modes
@@ -48,6 +53,7 @@
 #include <complex>
 #include <cstring>
 #include <new>
+#include <thread>
 #include <vector>
 
 namespace {
@@ -75,6 +81,23 @@ double uniform_of(uint64_t seed, uint64_t stream, int64_t col, int64_t j) {
 const uint64_t kStreamAngle = 1;
 const uint64_t kStreamDensity = 2;
 
+/* ------------------------------------------------------------ threads -- */
+int g_threads = 1;
+
+/* fn(t, lo, hi) for t = 0..T-1 over the contiguous ranges [lo, hi) of n
+ * items, thread t on its own std::thread (t = 0 on the caller's)           */
+template <class F>
+void for_ranges(size_t n, int T, F fn) {
+  if (T <= 1) {
+    fn(0, (size_t)0, n);
+    return;
+  }
+  std::vector<std::thread> th;
+  for (int t = 1; t < T; ++t) th.emplace_back(fn, t, n * t / T, n * (t + 1) / T);
+  fn(0, (size_t)0, n / T);
+  for (auto& x : th) x.join();
+}
+
 /* ---------------------------------------------------------------- state -- */
 struct Sim {
   oracle_params p;
@@ -90,7 +113,79 @@ struct Sim {
 
   size_t at(int i, int j) const { return (size_t)i * NR1 + j; }
   bool m1() const { return p.n_modes >= 2; }
+
+  /* per-thread deposit grids (threads > 1 only) */
+  std::vector<std::vector<double>> t_chi, t_jx, t_jr;
+  std::vector<std::vector<cplx>> t_jx1, t_jr1, t_jt1;
 };
+
+/* where one thread's deposits go: the simulation's own grids (one thread)
+ * or that thread's grids                                                  */
+struct Dep {
+  double* chi;
+  double *jx, *jr;
+  cplx *jx1, *jr1, *jt1;
+};
+
+/* T deposit targets, zeroed; for one thread the simulation's own grids */
+std::vector<Dep> deposit_targets(Sim& s, int T, bool chi) {
+  std::vector<Dep> d(T);
+  if (T == 1) {
+    if (chi) {
+      std::fill(s.chi.begin(), s.chi.end(), 0.0);
+    } else {
+      std::fill(s.Jx.begin(), s.Jx.end(), 0.0);
+      std::fill(s.Jr.begin(), s.Jr.end(), 0.0);
+      if (s.m1()) {
+        std::fill(s.Jx1.begin(), s.Jx1.end(), 0.0);
+        std::fill(s.Jr1.begin(), s.Jr1.end(), 0.0);
+        std::fill(s.Jt1.begin(), s.Jt1.end(), 0.0);
+      }
+    }
+    d[0] = Dep{s.chi.data(), s.Jx.data(), s.Jr.data(), s.m1() ? s.Jx1.data() : nullptr,
+               s.m1() ? s.Jr1.data() : nullptr, s.m1() ? s.Jt1.data() : nullptr};
+    return d;
+  }
+  const size_t ng = s.ng, n1 = s.m1() ? s.ng : 0;
+  if (chi) {
+    s.t_chi.resize(T);
+    for_ranges((size_t)T, T, [&](int, size_t lo, size_t hi) {
+      for (size_t t = lo; t < hi; ++t) s.t_chi[t].assign(ng, 0.0);
+    });
+    for (int t = 0; t < T; ++t) d[t] = Dep{s.t_chi[t].data(), nullptr, nullptr, nullptr, nullptr, nullptr};
+  } else {
+    s.t_jx.resize(T);
+    s.t_jr.resize(T);
+    s.t_jx1.resize(T);
+    s.t_jr1.resize(T);
+    s.t_jt1.resize(T);
+    for_ranges((size_t)T, T, [&](int, size_t lo, size_t hi) {
+      for (size_t t = lo; t < hi; ++t) {
+        s.t_jx[t].assign(ng, 0.0);
+        s.t_jr[t].assign(ng, 0.0);
+        s.t_jx1[t].assign(n1, 0.0);
+        s.t_jr1[t].assign(n1, 0.0);
+        s.t_jt1[t].assign(n1, 0.0);
+      }
+    });
+    for (int t = 0; t < T; ++t)
+      d[t] = Dep{nullptr, s.t_jx[t].data(), s.t_jr[t].data(), s.t_jx1[t].data(), s.t_jr1[t].data(),
+                 s.t_jt1[t].data()};
+  }
+  return d;
+}
+
+/* out[k] = sum over threads t = 0..T-1 (in that order) of parts[t][k] */
+template <class V>
+void sum_in_thread_order(V& out, const std::vector<V>& parts, int T) {
+  for_ranges(out.size(), T, [&](int, size_t lo, size_t hi) {
+    for (size_t k = lo; k < hi; ++k) {
+      typename V::value_type acc = parts[0][k];
+      for (int t = 1; t < T; ++t) acc += parts[t][k];
+      out[k] = acc;
+    }
+  });
+}
 
 /* ------------------------------------------------ cylindrical volumes --
  * R12: node volume of the primal row j (axis disc of radius dr/2 for j=0),
@@ -261,7 +356,6 @@ void init_fields(Sim& s) {
 void momentum_chi(Sim& s) {
   const int Nx = s.Nx, Nr = s.Nr;
   const double dx = s.dx, dr = s.dr, dt = s.dt;
-  std::fill(s.chi.begin(), s.chi.end(), 0.0);
   std::vector<double> phi(s.ng), gx(s.ng), gr(s.ng);
   for (size_t k = 0; k < s.ng; ++k) phi[k] = 0.5 * std::norm(s.A[k]);
   for (int i = 0; i <= Nx; ++i)
@@ -278,68 +372,74 @@ void momentum_chi(Sim& s) {
     }
   const size_t np = s.x.size();
   s.gbar.assign(np, 1.0);
-  for (size_t k = 0; k < np; ++k) {
-    double ux = s.x[k] / dx - (double)s.shift;
-    double r = std::sqrt(s.y[k] * s.y[k] + s.z[k] * s.z[k]);
-    double ur = r / dr;
-    Sh Px = primal(s, ux), Dx = dual(s, ux), Pr = primal(s, ur), Dr = dual(s, ur);
-    double c = 1.0, sn = 0.0;
-    if (r > 0.0) {
-      c = s.y[k] / r;
-      sn = s.z[k] / r;
-    }
-    /* parities across the axis (R23): axial components (-1)^m, radial and
-     * azimuthal ones (-1)^(m+1); Phi and its x-derivative even, its
-     * r-derivative odd */
-    double ex = interp(s, s.Ex, Dx, Pr, Nx - 1, Nr, PRIMAL_R, 1.0);
-    double er = interp(s, s.Er, Px, Dr, Nx, Nr - 1, HALF_R, -1.0);
-    double bt = interp(s, s.Btb, Dx, Dr, Nx - 1, Nr - 1, HALF_R, -1.0);
-    double et = 0.0, bx = 0.0, br = 0.0;
-    double ph = interp(s, phi, Px, Pr, Nx, Nr, PRIMAL_R, 1.0);
-    double gxp = interp(s, gx, Px, Pr, Nx, Nr, PRIMAL_R, 1.0);
-    double grp = interp(s, gr, Px, Pr, Nx, Nr, PRIMAL_R, -1.0);
-    if (s.m1()) {
-      ex += mode1(interp(s, s.Ex1, Dx, Pr, Nx - 1, Nr, PRIMAL_R, -1.0), c, sn);
-      er += mode1(interp(s, s.Er1, Px, Dr, Nx, Nr - 1, HALF_R, 1.0), c, sn);
-      et += mode1(interp(s, s.Et1, Px, Pr, Nx, Nr, PRIMAL_R, 1.0), c, sn);
-      bx += mode1(interp(s, s.Bxb1, Px, Dr, Nx, Nr - 1, HALF_R, -1.0), c, sn);
-      br += mode1(interp(s, s.Brb1, Dx, Pr, Nx - 1, Nr, PRIMAL_R, 1.0), c, sn);
-      bt += mode1(interp(s, s.Btb1, Dx, Dr, Nx - 1, Nr - 1, HALF_R, 1.0), c, sn);
-    }
-    /* rotate (x, r, theta) components to Cartesian */
-    double E[3] = {ex, er * c - et * sn, er * sn + et * c};
-    double B[3] = {bx, br * c - bt * sn, br * sn + bt * c};
-    double G[3] = {gxp, grp * c, grp * sn};
-    double p[3] = {s.px[k], s.py[k], s.pz[k]};
-    double g0 = std::sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + ph);
-    double F[3], pm[3];
-    for (int d = 0; d < 3; ++d) {
-      F[d] = -E[d] - G[d] / (2.0 * g0);
-      pm[d] = p[d] + 0.5 * dt * F[d];
-    }
-    double gb = std::sqrt(1.0 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2] + ph);
-    double t[3], sv[3];
-    for (int d = 0; d < 3; ++d) t[d] = -0.5 * dt * B[d] / gb;
-    double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
-    for (int d = 0; d < 3; ++d) sv[d] = 2.0 * t[d] / (1.0 + t2);
-    double pp[3] = {pm[0] + pm[1] * t[2] - pm[2] * t[1], pm[1] + pm[2] * t[0] - pm[0] * t[2],
-                    pm[2] + pm[0] * t[1] - pm[1] * t[0]};
-    double pl[3] = {pm[0] + pp[1] * sv[2] - pp[2] * sv[1], pm[1] + pp[2] * sv[0] - pp[0] * sv[2],
-                    pm[2] + pp[0] * sv[1] - pp[1] * sv[0]};
-    s.px[k] = pl[0] + 0.5 * dt * F[0];
-    s.py[k] = pl[1] + 0.5 * dt * F[1];
-    s.pz[k] = pl[2] + 0.5 * dt * F[2];
-    s.gbar[k] = gb;
-    /* chi^n deposit at the primal nodes around x^n (even across the
-     * axis); the volume is that of the row the contribution lands on */
-    for (int a = 0; a < Px.n; ++a)
-      for (int b = 0; b < Pr.n; ++b) {
-        int i = Px.i + a, j = Pr.i + b;
-        if (j < 0) j = mirror_row(j, PRIMAL_R);
-        if (i < 0 || i > Nx || j < 0 || j > Nr) continue;
-        s.chi[s.at(i, j)] += s.w[k] * Px.w[a] * Pr.w[b] / (gb * vol_node(s, j));
+  const int T = np >= 4096 ? g_threads : 1;
+  std::vector<Dep> dep = deposit_targets(s, T, true);
+  for_ranges(np, T, [&](int t, size_t k_lo, size_t k_hi) {
+    double* chi = dep[t].chi;
+    for (size_t k = k_lo; k < k_hi; ++k) {
+      double ux = s.x[k] / dx - (double)s.shift;
+      double r = std::sqrt(s.y[k] * s.y[k] + s.z[k] * s.z[k]);
+      double ur = r / dr;
+      Sh Px = primal(s, ux), Dx = dual(s, ux), Pr = primal(s, ur), Dr = dual(s, ur);
+      double c = 1.0, sn = 0.0;
+      if (r > 0.0) {
+        c = s.y[k] / r;
+        sn = s.z[k] / r;
       }
-  }
+      /* parities across the axis (R23): axial components (-1)^m, radial and
+       * azimuthal ones (-1)^(m+1); Phi and its x-derivative even, its
+       * r-derivative odd */
+      double ex = interp(s, s.Ex, Dx, Pr, Nx - 1, Nr, PRIMAL_R, 1.0);
+      double er = interp(s, s.Er, Px, Dr, Nx, Nr - 1, HALF_R, -1.0);
+      double bt = interp(s, s.Btb, Dx, Dr, Nx - 1, Nr - 1, HALF_R, -1.0);
+      double et = 0.0, bx = 0.0, br = 0.0;
+      double ph = interp(s, phi, Px, Pr, Nx, Nr, PRIMAL_R, 1.0);
+      double gxp = interp(s, gx, Px, Pr, Nx, Nr, PRIMAL_R, 1.0);
+      double grp = interp(s, gr, Px, Pr, Nx, Nr, PRIMAL_R, -1.0);
+      if (s.m1()) {
+        ex += mode1(interp(s, s.Ex1, Dx, Pr, Nx - 1, Nr, PRIMAL_R, -1.0), c, sn);
+        er += mode1(interp(s, s.Er1, Px, Dr, Nx, Nr - 1, HALF_R, 1.0), c, sn);
+        et += mode1(interp(s, s.Et1, Px, Pr, Nx, Nr, PRIMAL_R, 1.0), c, sn);
+        bx += mode1(interp(s, s.Bxb1, Px, Dr, Nx, Nr - 1, HALF_R, -1.0), c, sn);
+        br += mode1(interp(s, s.Brb1, Dx, Pr, Nx - 1, Nr, PRIMAL_R, 1.0), c, sn);
+        bt += mode1(interp(s, s.Btb1, Dx, Dr, Nx - 1, Nr - 1, HALF_R, 1.0), c, sn);
+      }
+      /* rotate (x, r, theta) components to Cartesian */
+      double E[3] = {ex, er * c - et * sn, er * sn + et * c};
+      double B[3] = {bx, br * c - bt * sn, br * sn + bt * c};
+      double G[3] = {gxp, grp * c, grp * sn};
+      double p[3] = {s.px[k], s.py[k], s.pz[k]};
+      double g0 = std::sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + ph);
+      double F[3], pm[3];
+      for (int d = 0; d < 3; ++d) {
+        F[d] = -E[d] - G[d] / (2.0 * g0);
+        pm[d] = p[d] + 0.5 * dt * F[d];
+      }
+      double gb = std::sqrt(1.0 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2] + ph);
+      double t[3], sv[3];
+      for (int d = 0; d < 3; ++d) t[d] = -0.5 * dt * B[d] / gb;
+      double t2 = t[0] * t[0] + t[1] * t[1] + t[2] * t[2];
+      for (int d = 0; d < 3; ++d) sv[d] = 2.0 * t[d] / (1.0 + t2);
+      double pp[3] = {pm[0] + pm[1] * t[2] - pm[2] * t[1], pm[1] + pm[2] * t[0] - pm[0] * t[2],
+                      pm[2] + pm[0] * t[1] - pm[1] * t[0]};
+      double pl[3] = {pm[0] + pp[1] * sv[2] - pp[2] * sv[1], pm[1] + pp[2] * sv[0] - pp[0] * sv[2],
+                      pm[2] + pp[0] * sv[1] - pp[1] * sv[0]};
+      s.px[k] = pl[0] + 0.5 * dt * F[0];
+      s.py[k] = pl[1] + 0.5 * dt * F[1];
+      s.pz[k] = pl[2] + 0.5 * dt * F[2];
+      s.gbar[k] = gb;
+      /* chi^n deposit at the primal nodes around x^n (even across the
+       * axis); the volume is that of the row the contribution lands on */
+      for (int a = 0; a < Px.n; ++a)
+        for (int b = 0; b < Pr.n; ++b) {
+          int i = Px.i + a, j = Pr.i + b;
+          if (j < 0) j = mirror_row(j, PRIMAL_R);
+          if (i < 0 || i > Nx || j < 0 || j > Nr) continue;
+          chi[s.at(i, j)] += s.w[k] * Px.w[a] * Pr.w[b] / (gb * vol_node(s, j));
+        }
+    }
+  });
+  if (T > 1) sum_in_thread_order(s.chi, s.t_chi, T);
 }
 
 /* -------------------------------------------- envelope stage (Sec. 3) --
@@ -386,7 +486,7 @@ void envelope(Sim& s) {
  * between (ux0, ur0) and (ux1, ur1) (cell units, window-relative):
  *   W_x = (S1x - S0x)(S0r + S1r)/2,  W_r = (S1r - S0r)(S0x + S1x)/2,
  * fluxes accumulated from the low side, divided by face area and dt.    */
-void deposit_J_mode0(Sim& s, double w, double ux0, double ur0, double ux1, double ur1) {
+void deposit_J_mode0(const Sim& s, const Dep& d, double w, double ux0, double ur0, double ux1, double ur1) {
   const int Nx = s.Nx, Nr = s.Nr;
   const double q = -1.0;
   Sh a0 = primal(s, ux0), a1 = primal(s, ux1), b0 = primal(s, ur0), b1 = primal(s, ur1);
@@ -409,7 +509,7 @@ void deposit_J_mode0(Sim& s, double w, double ux0, double ur0, double ux1, doubl
       int i = imin + a, j = jmin + b;
       if (j < 0) j = mirror_row(j, PRIMAL_R);
       if (i < 0 || i > Nx - 1 || j < 0 || j > Nr) continue;
-      s.Jx[s.at(i, j)] += -q * w * acc / (area_x(s, j) * s.dt);
+      d.jx[s.at(i, j)] += -q * w * acc / (area_x(s, j) * s.dt);
     }
   }
   /* J_r at the face j + 1/2: odd across the axis (the face at -1/2 folds
@@ -425,7 +525,7 @@ void deposit_J_mode0(Sim& s, double w, double ux0, double ur0, double ux1, doubl
         sg = -1.0;
       }
       if (i < 0 || i > Nx || j < 0 || j > Nr - 1) continue;
-      s.Jr[s.at(i, j)] += sg * -q * w * acc / (area_r(s, j) * s.dt);
+      d.jr[s.at(i, j)] += sg * -q * w * acc / (area_r(s, j) * s.dt);
     }
   }
 }
@@ -433,7 +533,7 @@ void deposit_J_mode0(Sim& s, double w, double ux0, double ur0, double ux1, doubl
 /* mode-1 current, deposited directly with the particle's mid-point shape:
  * J_1 += 2 q w v S e^{+i theta} / V (factor 2 and e^{+i theta} from the
  * Fourier coefficient of a point current at azimuth theta).              */
-void deposit_J_mode1(Sim& s, double w, double ux, double ur, double c, double sn,
+void deposit_J_mode1(const Sim& s, const Dep& d, double w, double ux, double ur, double c, double sn,
                      const double v[3]) {
   const int Nx = s.Nx, Nr = s.Nr;
   const double q = -1.0;
@@ -450,7 +550,7 @@ void deposit_J_mode1(Sim& s, double w, double ux, double ur, double c, double sn
         sg = -1.0;
       }
       if (i < 0 || i > Nx - 1 || j < 0 || j > Nr) continue;
-      s.Jx1[s.at(i, j)] += sg * 2.0 * q * w * v[0] * Dx.w[a] * Pr.w[b] * e / vol_node(s, j);
+      d.jx1[s.at(i, j)] += sg * 2.0 * q * w * v[0] * Dx.w[a] * Pr.w[b] * e / vol_node(s, j);
     }
   /* J_r1 at (i, j+1/2): even for mode 1 (row -1/2 folds onto +1/2) */
   for (int a = 0; a < Px.n; ++a)
@@ -458,7 +558,7 @@ void deposit_J_mode1(Sim& s, double w, double ux, double ur, double c, double sn
       int i = Px.i + a, j = Dr.i + b;
       if (j < 0) j = mirror_row(j, HALF_R);
       if (i < 0 || i > Nx || j < 0 || j > Nr - 1) continue;
-      s.Jr1[s.at(i, j)] += 2.0 * q * w * vr * Px.w[a] * Dr.w[b] * e / vol_half(s, j);
+      d.jr1[s.at(i, j)] += 2.0 * q * w * vr * Px.w[a] * Dr.w[b] * e / vol_half(s, j);
     }
   /* J_t1 at (i, j): even for mode 1 */
   for (int a = 0; a < Px.n; ++a)
@@ -466,7 +566,7 @@ void deposit_J_mode1(Sim& s, double w, double ux, double ur, double c, double sn
       int i = Px.i + a, j = Pr.i + b;
       if (j < 0) j = mirror_row(j, PRIMAL_R);
       if (i < 0 || i > Nx || j < 0 || j > Nr) continue;
-      s.Jt1[s.at(i, j)] += 2.0 * q * w * vt * Px.w[a] * Pr.w[b] * e / vol_node(s, j);
+      d.jt1[s.at(i, j)] += 2.0 * q * w * vt * Px.w[a] * Pr.w[b] * e / vol_node(s, j);
     }
 }
 
@@ -477,13 +577,6 @@ void deposit_J_mode1(Sim& s, double w, double ux, double ur, double c, double sn
 void position_J(Sim& s) {
   const int Nx = s.Nx, Nr = s.Nr;
   const double dx = s.dx, dr = s.dr, dt = s.dt;
-  std::fill(s.Jx.begin(), s.Jx.end(), 0.0);
-  std::fill(s.Jr.begin(), s.Jr.end(), 0.0);
-  if (s.m1()) {
-    std::fill(s.Jx1.begin(), s.Jx1.end(), 0.0);
-    std::fill(s.Jr1.begin(), s.Jr1.end(), 0.0);
-    std::fill(s.Jt1.begin(), s.Jt1.end(), 0.0);
-  }
   /* after the envelope stage A = A^{n+1}, Ap = A^n */
   std::vector<double> phh(s.ng);
   for (size_t k = 0; k < s.ng; ++k) phh[k] = 0.25 * (std::norm(s.A[k]) + std::norm(s.Ap[k]));
@@ -491,43 +584,57 @@ void position_J(Sim& s) {
   const double xlo = (double)s.shift * dx, xhi = (double)(s.shift + Nx) * dx;
   const size_t np = s.x.size();
   std::vector<char> keep(np, 1);
-  for (size_t k = 0; k < np; ++k) {
-    double ux = s.x[k] / dx - (double)s.shift;
-    double r = std::sqrt(s.y[k] * s.y[k] + s.z[k] * s.z[k]);
-    double ph = interp(s, phh, primal(s, ux), primal(s, r / dr), Nx, Nr, PRIMAL_R, 1.0);
-    double p[3] = {s.px[k], s.py[k], s.pz[k]};
-    double g = std::sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + ph);
-    double v[3] = {p[0] / g, p[1] / g, p[2] / g};
-    double xn = s.x[k] + dt * v[0], yn = s.y[k] + dt * v[1], zn = s.z[k] + dt * v[2];
-    double rn = std::sqrt(yn * yn + zn * zn);
-    if (rn >= rmax) {
-      double f = (2.0 * rmax - rn) / rn;
-      double cr = yn / rn, sr = zn / rn;
-      yn *= f;
-      zn *= f;
-      rn = 2.0 * rmax - rn;
-      double prad = s.py[k] * cr + s.pz[k] * sr;
-      s.py[k] -= 2.0 * prad * cr;
-      s.pz[k] -= 2.0 * prad * sr;
-    }
-    if (xn < xlo || xn >= xhi) {
-      keep[k] = 0;
-      continue;
-    }
-    deposit_J_mode0(s, s.w[k], ux, r / dr, xn / dx - (double)s.shift, rn / dr);
-    if (s.m1()) {
-      double xm = 0.5 * (s.x[k] + xn), ym = 0.5 * (s.y[k] + yn), zm = 0.5 * (s.z[k] + zn);
-      double rm = std::sqrt(ym * ym + zm * zm);
-      double c = 1.0, sn = 0.0;
-      if (rm > 0.0) {
-        c = ym / rm;
-        sn = zm / rm;
+  const int T = np >= 4096 ? g_threads : 1;
+  std::vector<Dep> dep = deposit_targets(s, T, false);
+  for_ranges(np, T, [&](int t, size_t k_lo, size_t k_hi) {
+    const Dep& d = dep[t];
+    for (size_t k = k_lo; k < k_hi; ++k) {
+      double ux = s.x[k] / dx - (double)s.shift;
+      double r = std::sqrt(s.y[k] * s.y[k] + s.z[k] * s.z[k]);
+      double ph = interp(s, phh, primal(s, ux), primal(s, r / dr), Nx, Nr, PRIMAL_R, 1.0);
+      double p[3] = {s.px[k], s.py[k], s.pz[k]};
+      double g = std::sqrt(1.0 + p[0] * p[0] + p[1] * p[1] + p[2] * p[2] + ph);
+      double v[3] = {p[0] / g, p[1] / g, p[2] / g};
+      double xn = s.x[k] + dt * v[0], yn = s.y[k] + dt * v[1], zn = s.z[k] + dt * v[2];
+      double rn = std::sqrt(yn * yn + zn * zn);
+      if (rn >= rmax) {
+        double f = (2.0 * rmax - rn) / rn;
+        double cr = yn / rn, sr = zn / rn;
+        yn *= f;
+        zn *= f;
+        rn = 2.0 * rmax - rn;
+        double prad = s.py[k] * cr + s.pz[k] * sr;
+        s.py[k] -= 2.0 * prad * cr;
+        s.pz[k] -= 2.0 * prad * sr;
       }
-      deposit_J_mode1(s, s.w[k], xm / dx - (double)s.shift, rm / dr, c, sn, v);
+      if (xn < xlo || xn >= xhi) {
+        keep[k] = 0;
+        continue;
+      }
+      deposit_J_mode0(s, d, s.w[k], ux, r / dr, xn / dx - (double)s.shift, rn / dr);
+      if (s.m1()) {
+        double xm = 0.5 * (s.x[k] + xn), ym = 0.5 * (s.y[k] + yn), zm = 0.5 * (s.z[k] + zn);
+        double rm = std::sqrt(ym * ym + zm * zm);
+        double c = 1.0, sn = 0.0;
+        if (rm > 0.0) {
+          c = ym / rm;
+          sn = zm / rm;
+        }
+        deposit_J_mode1(s, d, s.w[k], xm / dx - (double)s.shift, rm / dr, c, sn, v);
+      }
+      s.x[k] = xn;
+      s.y[k] = yn;
+      s.z[k] = zn;
     }
-    s.x[k] = xn;
-    s.y[k] = yn;
-    s.z[k] = zn;
+  });
+  if (T > 1) {
+    sum_in_thread_order(s.Jx, s.t_jx, T);
+    sum_in_thread_order(s.Jr, s.t_jr, T);
+    if (s.m1()) {
+      sum_in_thread_order(s.Jx1, s.t_jx1, T);
+      sum_in_thread_order(s.Jr1, s.t_jr1, T);
+      sum_in_thread_order(s.Jt1, s.t_jt1, T);
+    }
   }
   size_t m = 0;
   for (size_t k = 0; k < np; ++k) {
@@ -770,6 +877,12 @@ bool check_params(const oracle_params* p) {
 
 /* ============================================================= C ABI == */
 extern "C" {
+
+int oracle_set_threads(int n) {
+  if (n < 1 || n > 256) return ORACLE_EINVAL;
+  g_threads = n;
+  return ORACLE_OK;
+}
 
 double oracle_uniform(uint64_t seed, uint64_t stream, int64_t col, int64_t j) {
   return uniform_of(seed, stream, col, j);

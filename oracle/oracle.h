@@ -190,6 +190,12 @@ int oracle_get_field(void* sim, int field, double* out);
 int oracle_set_field(void* sim, int field, const double* in);
 int oracle_diagnostics(void* sim, double* out);
 
+/* Threads of the particle loops (process-wide, default 1): the particles are
+ * split into equal contiguous ranges, each thread deposits into grids of its
+ * own and these are added in thread order, so results are identical for a
+ * given thread count (and differ between counts by summation order only). */
+int oracle_set_threads(int n);
+
 /* counter-based uniform deviate in [0,1) used for loading (SplitMix64) */
 double oracle_uniform(uint64_t seed, uint64_t stream, int64_t col, int64_t j);
 

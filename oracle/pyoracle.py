@@ -55,7 +55,7 @@ def build(force=False):
     src = os.path.join(_HERE, "oracle.cpp")
     if force or not os.path.exists(LIB_PATH) or os.path.getmtime(LIB_PATH) < max(
             os.path.getmtime(src), os.path.getmtime(os.path.join(_HERE, "oracle.h"))):
-        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-Wall", "-pthread",
                                "-o", LIB_PATH, src])
     return LIB_PATH
 
@@ -93,6 +93,7 @@ def lib(path=None):
         L.oracle_uniform.argtypes = [ctypes.c_uint64, ctypes.c_uint64, ctypes.c_int64,
                                      ctypes.c_int64]
         L.oracle_uniform.restype = ctypes.c_double
+        L.oracle_set_threads.argtypes = [ctypes.c_int]
         _libs[path] = L
     return _libs[path]
 
@@ -110,7 +111,7 @@ def build_variant(edits, workdir):
     with open(cpp, "w") as f:
         f.write(src)
     out = os.path.join(workdir, "liboracle.so")
-    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-I", _HERE,
+    subprocess.check_call(["g++", "-std=c++17", "-O2", "-fPIC", "-shared", "-pthread", "-I", _HERE,
                            "-o", out, cpp])
     return out
 
@@ -275,3 +276,19 @@ class OracleSim:
 
 def uniform(seed, stream, col, j):
     return lib().oracle_uniform(seed, stream, col, j)
+
+
+def set_threads(n):
+    """Threads of the oracle's particle loops (process-wide; 1 is the plain
+    serial loop).  Results are identical for a given count."""
+    if lib().oracle_set_threads(int(n)) != 0:
+        raise ValueError(f"bad thread count {n}")
+
+
+def host_threads(cap=16):
+    """The CPUs this process may run on, at most `cap`."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(cap, n))
