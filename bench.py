@@ -40,10 +40,16 @@ def algorithmic_bytes(cfg, n_particles, prec_bytes=4):
     pos_p = 4 + 7 * w + 4 + 3 * w             # read 8 words, write cell + 3 offsets
     mom_c = 3 * w + 2 * w + w + (12 * w if m1 else 0)   # E_x, E_r, Bbar_t, A; chi; mode-1 gathers
     pos_c = 4 * w + 2 * w + (6 * w if m1 else 0)        # A^n, A^{n+1}; J_x, J_r; mode-1 J
+    # field update per cell: mode 0 reads E_x, E_r, B_t, J_x, J_r and writes
+    # E_x, E_r, B_t, Bbar_t (9 words); mode 1 reads six complex E/B and three
+    # complex J and writes six complex E/B and three complex Bbar (18 complex)
+    fld_c = 9 * w + (36 * w if m1 else 0)
+    env_c = 7 * w                                       # A^n, A^{n-1}, chi read; A^{n+1} written
     return {"k_momentum": mom_p * n_particles + mom_c * cells,
             "k_position": pos_p * n_particles + pos_c * cells,
-            "per_particle": {"k_momentum": mom_p, "k_position": pos_p},
-            "per_cell": {"k_momentum": mom_c, "k_position": pos_c}}
+            "k_field": fld_c * cells, "k_envelope": env_c * cells,
+            "per_particle": {"k_momentum": mom_p, "k_position": pos_p, "k_field": 0, "k_envelope": 0},
+            "per_cell": {"k_momentum": mom_c, "k_position": pos_c, "k_field": fld_c, "k_envelope": env_c}}
 
 
 def source_digest():
@@ -70,10 +76,13 @@ def traffic_record(kernel, workload):
     return rec.get("bytes_per_launch")
 
 
-# stage events on every 7th step of the timed region: 7 is coprime to the
-# sort periods (3 and 24 steps), so every kernel variant is sampled evenly,
-# and the events' own cost stays small
-TIMING_EVERY = 7
+# Per-kernel times come from a pass after the timed region (the timed steps
+# carry no events): HIP events around each stage on every step, for two full
+# cycles of the sort schedule (a tile sort every third step, a cell-ordered
+# one every 24th; every second and 16th with quadratic shapes), so each
+# variant of the momentum pass counts with its share of the launches.
+KERNEL_PASS_STEPS = 48
+STAGE_KERNEL = {"momentum": "k_momentum", "envelope": "k_envelope", "position": "k_position", "field": "k_field"}
 
 
 # beam parameters of the final state (Table BeamParams): electrons above
@@ -96,16 +105,14 @@ def time_beam(sim, torch, reps=20):
 
 def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True, beam=False):
     """Warm up, then time `steps` steps issued by the library's own loop
-    (envpic_step_n) on the simulation's stream.  With `per_kernel`, the
-    library records HIP events around each stage's kernels on that same
-    stream on every TIMING_EVERY-th step of the timed region."""
+    (envpic_step_n) on the simulation's stream.  With `per_kernel`, a pass of
+    KERNEL_PASS_STEPS more steps follows with HIP events around each stage
+    on that stream on every step (the library's stage timing)."""
     stream = torch.cuda.current_stream()
     sim = E.Sim(cfg, prec, stream=stream)
     sim.step(warmup)
     torch.cuda.synchronize()
     n0 = sim.state()[2]
-    step0 = int(sim.state()[0])
-    sim.set_timing(per_kernel, every=TIMING_EVERY)
     t_start = torch.cuda.Event(enable_timing=True)
     t_end = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
@@ -119,13 +126,14 @@ def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True, beam=False):
     gpu_ms = t_start.elapsed_time(t_end)
     out = {"wall_s": wall, "gpu_ms": gpu_ms, "particles": 0.5 * (n0 + n1), "n0": n0, "n1": n1}
     if per_kernel:
+        sim.set_timing(True, every=1)
+        sim.step(KERNEL_PASS_STEPS)
         t = sim.timing()
-        out["k_momentum_ms"] = t["momentum"][0]
-        out["k_position_ms"] = t["position"][0]
+        sim.set_timing(False)
+        assert all(v[1] == KERNEL_PASS_STEPS for v in t.values()), t
         out["stage_ms"] = {k: round(v[0], 5) for k, v in t.items()}
-        timed = sum(1 for k in range(step0, step0 + steps) if k % TIMING_EVERY == 0)
-        assert t["momentum"][1] == timed and t["position"][1] == timed, (t, timed)
-        out["timed_launches"] = timed
+        out["kernel_ms"] = {STAGE_KERNEL[k]: v[0] for k, v in t.items()}
+        out["kernel_pass_particles"] = sim.state()[2]
     if beam:
         out["beam"] = time_beam(sim, torch)
     sim.close()
@@ -134,13 +142,18 @@ def run_gpu(E, torch, cfg, prec, steps, warmup, per_kernel=True, beam=False):
     return out
 
 
-def run_serving(E, prec, budget_bytes, steps=300):
+def run_serving(E, prec, budget_bytes, steps=300, repeat=0, burst=False):
     """The scan-serving trace: 64 jobs arriving as a Poisson process (mean
-    4 jobs/s), grids from {512x64, 1024x128, 2048x256}, 300 steps each,
-    served by continuous batching inside one arena of `budget_bytes`."""
-    from inputs import c4_trace
+    4 jobs/s; repeat r draws jobs and arrivals from seed base + 99 + 10 r),
+    grids from {512x64, 1024x128, 2048x256}, 300 steps each, served by
+    continuous batching inside one arena of `budget_bytes`.  With `burst`
+    every job arrives at t = 0 (the server saturated)."""
+    import numpy as np
+    from inputs import BASE_SEED, c4_trace
     from paper_1912_04674_amd.serve import DONE, GpuBackend, ScanServer, latency_stats
-    cfgs, arrivals = c4_trace()
+    cfgs, arrivals = c4_trace(seed=BASE_SEED + 99 + 10 * repeat)
+    if burst:
+        arrivals = np.zeros_like(arrivals)
     be = GpuBackend(budget_bytes, precision=prec, lineout=True)
     # load the kernels' code objects before the trace starts
     warm = ScanServer(be, chunk=5)
@@ -158,26 +171,74 @@ def run_serving(E, prec, budget_bytes, steps=300):
     return {"jobs": len(jobs), "done": len(ok), "p50_s": st["p50"], "p99_s": st["p99"], "mean_s": st["mean"],
             "makespan_s": makespan, "aggregate_pushes_per_s": pushes / makespan,
             "median_latency_s_by_grid": {k: float(sorted(v)[(len(v) - 1) // 2]) for k, v in sorted(by_grid.items())},
-            "budget_bytes": budget_bytes}
+            "budget_bytes": budget_bytes, "arrival_seed": int(BASE_SEED + 99 + 10 * repeat), "burst": burst}
+
+
+def cpu_model():
+    """CPU model name of the host (from /proc/cpuinfo)."""
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.lower().startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(pyoracle, cfg, steps, threads):
+    """Pushes and cell updates per second of the oracle on cfg (creation not
+    timed)."""
+    pyoracle.set_threads(threads)
+    try:
+        sim = pyoracle.OracleSim(cfg)
+        n0 = sim.n_particles
+        t0 = time.perf_counter()
+        sim.step(steps)
+        dt = time.perf_counter() - t0
+        n1 = sim.n_particles
+        sim.close()
+    finally:
+        pyoracle.set_threads(1)
+    return {"pushes_per_s": 0.5 * (n0 + n1) * steps / dt, "cell_updates_per_s": cfg["nx"] * cfg["nr"] * steps / dt,
+            "particles": int(0.5 * (n0 + n1)), "steps": steps, "seconds": round(dt, 3)}
 
 
 def cpu_baseline(cfg, cols=256, steps=20):
-    """The FP64 oracle (single thread) on a slab of the same workload: the
-    last `cols` cell columns (where the pulse is), full radius, same loading."""
+    """The FP64 oracle, as it stands, on the host's cores: the particle loops
+    on 1 thread and on every core this process may use (at most 16, the host
+    share of one GPU).  The headline sample is a slab of the benchmarked
+    workload (its last `cols` cell columns, where the pulse is; full radius,
+    same loading) for `steps` steps; beside it, on all threads: the mode-0
+    parity workload in full (100 steps), a 256-column slab of the bandwidth
+    workload (20 steps) and one scan job per grid size for 30 of its 300
+    steps (the job's CPU latency is scaled from those)."""
     import pyoracle
-    from inputs import scaled
+    from inputs import C1, C3, C4_GRIDS, c4_job, scaled
+    import numpy as np
     pyoracle.build()
+    nthr = pyoracle.host_threads()
     start = cfg["nx"] - cols
     sub = scaled(cfg, nx=cols, start_col=start)
-    sim = pyoracle.OracleSim(sub)
-    n0 = sim.n_particles
-    t0 = time.perf_counter()
-    sim.step(steps)
-    dt = time.perf_counter() - t0
-    n1 = sim.n_particles
-    return {"value": 0.5 * (n0 + n1) * steps / dt, "unit": "particle-pushes/s", "cores": 1, "kind": "oracle",
-            "sample": f"{cfg['name']} columns [{start}, {cfg['nx']}) x {cfg['nr']} rows, "
-                      f"{int(0.5 * (n0 + n1))} particles, {steps} steps, FP64, 1 thread ({dt:.1f} s)"}
+    one = _oracle_rate(pyoracle, sub, max(4, steps // 4), 1)
+    many = _oracle_rate(pyoracle, sub, steps, nthr)
+    others = {"c1_parity_256x32 (full, 100 steps)": _oracle_rate(pyoracle, C1, 100, nthr),
+              "c3_bandwidth_4096x512 columns [1920, 2176), 20 steps":
+                  _oracle_rate(pyoracle, scaled(C3, nx=256, start_col=1920), 20, nthr)}
+    rng = np.random.default_rng(7)
+    for nx, nr in C4_GRIDS:
+        job = c4_job(0, rng)
+        job = scaled(job, nx=nx, nr=nr, x_c=nx * 0.8 - 90.0, x_f=nx * 0.8 - 90.0, name=f"c4_{nx}x{nr}")
+        r = _oracle_rate(pyoracle, job, 30, nthr)
+        r["job_latency_s_300_steps"] = round(r["seconds"] * 300 / 30, 2)
+        others[f"c4 scan job {nx}x{nr} (30 of 300 steps)"] = r
+    return {"value": many["pushes_per_s"], "unit": "particle-pushes/s", "cores": nthr, "kind": "oracle",
+            "sample": f"{cfg['name']} columns [{start}, {cfg['nx']}) x {cfg['nr']} rows, {many['particles']} particles, "
+                      f"{steps} steps, FP64, {nthr} threads ({many['seconds']:.1f} s)",
+            "cpu_model": cpu_model(),
+            "one_thread": {"value": one["pushes_per_s"], "cores": 1,
+                           "sample": f"same slab, {one['steps']} steps ({one['seconds']:.1f} s)"},
+            "cell_updates_per_s": many["cell_updates_per_s"],
+            "other_samples": others}
 
 
 def bunch_solve_line(workload):
@@ -215,21 +276,43 @@ def progress(*a):
 
 
 
-def copy_seconds(torch, n, reps):
+def copy_seconds(torch, n, reps, variant=None):
     """Seconds per plain device copy of n bytes (read n, write n), averaged
-    over reps copies after one untimed copy: the practical streaming ceiling
-    the kernels' bandwidth is read against."""
+    over reps copies after one untimed copy: torch's copy (variant None) or
+    the library's streaming copy kernel (variant 0-3)."""
+    import paper_1912_04674_amd as E
     src = torch.ones(n, dtype=torch.uint8, device="cuda")
     dst = torch.empty_like(src)
-    dst.copy_(src)
+
+    def once():
+        if variant is None:
+            dst.copy_(src)
+        else:
+            E.stream_copy(dst, src, variant)
+    once()
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
     for _ in range(reps):
-        dst.copy_(src)
+        once()
+    b.record()
     torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / reps
+    dt = a.elapsed_time(b) * 1e-3 / reps
     del src, dst
     return dt
+
+
+def copy_ceiling(torch, n=512 * 2**20, reps=10):
+    """The measured streaming ceiling: the library's hand-written copy kernel
+    (16 B per lane, 4 or 8 accesses in flight, ordinary or non-temporal) and
+    torch's copy, each moving n bytes in and n out (n above the 256 MB
+    Infinity Cache)."""
+    names = {0: "hip_copy_u4", 1: "hip_copy_u8", 2: "hip_copy_u4_nt", 3: "hip_copy_u8_nt", None: "torch_copy"}
+    rates = {names[v]: round(2 * n / copy_seconds(torch, n, reps, v) / 1e9, 1) for v in (0, 1, 2, 3, None)}
+    best = max((k for k in rates if k.startswith("hip")), key=lambda k: rates[k])
+    return {"GBps": rates[best], "frac_of_peak": round(rates[best] / HBM_PEAK_GBS, 4), "kernel": best,
+            "bytes": 2 * n, "all_GBps": rates}
+
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -251,11 +334,17 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MiB",
                     help="only run a plain device copy of this many MiB, 10 times (reference for "
                          "the FETCH_SIZE / WRITE_SIZE counters)")
+    ap.add_argument("--copy-variant", type=int, default=0, choices=[0, 1, 2, 3],
+                    help="the library copy kernel's variant for --copy-calibration")
+    ap.add_argument("--serving-repeats", type=int, default=1,
+                    help="run the scan trace this many times (arrival seeds base + 99 + 10 r)")
+    ap.add_argument("--serving-burst", action="store_true",
+                    help="also serve the 64 jobs of the trace all arriving at t = 0 (saturation)")
     args = ap.parse_args()
     if args.copy_calibration:
         import torch
         n = args.copy_calibration * 2**20
-        dt = copy_seconds(torch, n, 10)
+        dt = copy_seconds(torch, n, 10, variant=args.copy_variant)
         print(json.dumps({"copy_bytes_read": n, "copy_bytes_written": n, "seconds": dt,
                           "GBps_read_plus_write": 2 * n / dt / 1e9}))
         return
@@ -283,30 +372,29 @@ def main():
     pushes = r32["particles"] * args.steps
     value = pushes / r32["wall_s"]
     cells = cfg["nx"] * cfg["nr"]
-    ab = algorithmic_bytes(cfg, r32["particles"], 4)
+    ab = algorithmic_bytes(cfg, r32["kernel_pass_particles"], 4)
     kernels = {}
-    for k in ("k_momentum", "k_position"):
-        ms = r32[k + "_ms"]
-        kernels[k] = {"avg_ms": ms, "alg_bytes": ab[k], "GBps": ab[k] / (ms * 1e-3) / 1e9}
+    for k, ms in r32["kernel_ms"].items():
+        kernels[k] = {"avg_ms": ms, "alg_bytes": ab[k], "GBps": ab[k] / (ms * 1e-3) / 1e9,
+                      "frac": ab[k] / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS}
+    # every kernel runs once per step: the dominant one takes the most time
     dom = max(kernels, key=lambda k: kernels[k]["avg_ms"])
     achieved = kernels[dom]["GBps"]
     tr = traffic_record(dom, cfg["name"])
-    # the measured streaming ceiling beside the published peak: a 512 MiB
-    # device copy (larger than the 256 MB Infinity Cache)
-    ncopy = 512 * 2**20
-    copy_gbs = 2 * ncopy / copy_seconds(torch, ncopy, 10) / 1e9
+    ceiling = copy_ceiling(torch)
+    progress(f"copy ceiling {ceiling['all_GBps']}")
     roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr,
-                "copy_ceiling": {"GBps": round(copy_gbs, 1), "frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
-                                 "bytes": 2 * ncopy},
+                "copy_ceiling": ceiling,
                 "alg_bytes_per_particle": ab["per_particle"][dom], "alg_bytes_per_cell": ab["per_cell"][dom],
+                "kernel_times": f"HIP events around each stage on every step of {KERNEL_PASS_STEPS} steps "
+                                "after the timed region (two cycles of the sort schedule)",
                 "kernels": {k: {kk: round(vv, 4) if isinstance(vv, float) else vv for kk, vv in v.items()}
                             for k, v in kernels.items()}}
     extra = {"cell_updates_per_s": cells * args.steps / r32["wall_s"],
              "gpu_event_ms_per_step": r32["gpu_ms"] / args.steps,
              "stage_avg_ms": r32["stage_ms"],
-             "stage_timed_steps": r32["timed_launches"], "stage_timing_every": TIMING_EVERY,
              "particles_start_end": [r32["n0"], r32["n1"]]}
     # the beam pass reads cell, momentum and weight of every particle three
     # times (histogram, means, centred moments): 60 B per particle
@@ -314,6 +402,13 @@ def main():
     bm["alg_bytes"] = 3 * (4 + 3 * 4 + 4) * r32["n1"]
     bm["GBps_alg_incl_host_sync"] = bm["alg_bytes"] / (bm["ms"] * 1e-3) / 1e9
     extra["beam_diag"] = bm
+    if args.workload == "c3" and cfg.get("sort_every") == 1:
+        # the same workload with the default sort period (every third step)
+        r3 = run_gpu(E, torch, dict(cfg, sort_every=0), E.FP32_BULK, args.steps, args.warmup)
+        extra["sort_every_3"] = {"ms_per_step": 1e3 * r3["wall_s"] / args.steps,
+                                 "pushes_per_s": r3["particles"] * args.steps / r3["wall_s"],
+                                 "stage_avg_ms": r3["stage_ms"]}
+        progress("c3 with the default sort period done")
     if not args.no_fp64:
         s64 = max(10, args.steps // 5)
         r64 = run_gpu(E, torch, cfg, E.FP64, s64, min(args.warmup, 5), per_kernel=False)
@@ -336,12 +431,17 @@ def main():
     if not args.no_serving:
         budget = int(args.serving_budget_gib * 2**30)
         line["serving"] = {"trace": "64 jobs, Poisson 4 jobs/s, grids {512x64, 1024x128, 2048x256}, m=0, "
-                                    "2x2x2 ppc, 300 steps, window on",
-                           "fp32": run_serving(E, E.FP32_BULK, budget)}
-        progress("fp32 serving trace done")
-        if not args.no_fp64:
-            line["serving"]["fp64"] = run_serving(E, E.FP64, budget)
-            progress("fp64 serving trace done")
+                                    "2x2x2 ppc, 300 steps, window on"}
+        precs = [("fp32", E.FP32_BULK)] + ([] if args.no_fp64 else [("fp64", E.FP64)])
+        for name, prec in precs:
+            runs = []
+            for r in range(args.serving_repeats):
+                runs.append(run_serving(E, prec, budget, repeat=r))
+                progress(f"{name} serving trace {r} done")
+            line["serving"][name] = runs[0] if len(runs) == 1 else runs
+            if args.serving_burst:
+                line["serving"][name + "_burst"] = run_serving(E, prec, budget, burst=True)
+                progress(f"{name} serving burst done")
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(cfg)
         progress("cpu baseline done")

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define ENVPIC_PARAMS_VERSION 2
+#define ENVPIC_PARAMS_VERSION 3
 
 enum envpic_status {
   ENVPIC_OK = 0,
@@ -96,6 +96,10 @@ typedef struct envpic_params {
                               (cloud in cell), 2 quadratic B-spline (Sec. 4's
                               nonlinear benchmark configuration); order 2 re-sorts
                               every second step and has no deferred deposits */
+  int32_t sort_every;      /* steps between two tile sorts of the particles: 0 for
+                              the default (3 linear, 2 quadratic, the most the LDS
+                              halo allows), or 1 .. that default */
+  int32_t reserved;        /* must be 0 */
 } envpic_params;
 #define ENVPIC_FILTER_MAX 8
 
@@ -307,6 +311,15 @@ int envpic_debug_poison(envpic_sim* s, int field);
  * queued on its stream, so the caller may release or reuse the arena as soon
  * as this returns.  NULL is ignored. */
 void envpic_sim_destroy(envpic_sim* s);
+
+/* A plain streaming device-to-device copy of `bytes` bytes (a multiple of 16;
+ * both pointers 16-byte aligned, caller-owned device memory, not
+ * overlapping), asynchronous on `stream`: the bandwidth reference the
+ * kernels' HBM rates are compared with.  variant: 0 and 1 ordinary loads and
+ * stores with 4 or 8 16-byte accesses in flight per lane, 2 and 3 the same
+ * with non-temporal loads and stores.  ENVPIC_EINVAL on a bad size,
+ * alignment or variant; ENVPIC_EDEVICE if the launch fails. */
+int envpic_stream_copy(void* dst, const void* src, size_t bytes, int variant, void* stream);
 
 /* Message of the last error on this thread (s may be NULL). */
 const char* envpic_last_error(const envpic_sim* s);

@@ -12,7 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libenvpic.so")
-SOURCES = ["particles.hip", "grid.hip", "sort_diag.hip", "beam.hip", "bunch.hip", "api.hip"]
+SOURCES = ["particles.hip", "grid.hip", "sort_diag.hip", "beam.hip", "bunch.hip", "api.hip", "copy.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -96,6 +96,9 @@ int validate(const envpic_params* p) {
   if (p->filter_passes > 0 && (p->nx <= 2 * p->filter_passes || p->nr <= 2 * p->filter_passes))
     return fail(ENVPIC_EINVAL, "the binomial filter needs nx and nr above twice its passes");
   if (p->shape_order < 0 || p->shape_order > 2) return fail(ENVPIC_EINVAL, "shape_order must be 0, 1 (linear) or 2 (quadratic)");
+  if (p->sort_every < 0 || p->sort_every > (p->shape_order == 2 ? SORT_EVERY - 1 : SORT_EVERY))
+    return fail(ENVPIC_EINVAL, "sort_every must be 0 (default) or between 1 and 3 (2 for quadratic shapes)");
+  if (p->reserved != 0) return fail(ENVPIC_EINVAL, "reserved must be 0");
   if (p->n0 < 0) return fail(ENVPIC_EINVAL, "n0 must be >= 0");
   if (p->profile == ENVPIC_PROFILE_RAMP && !(p->ramp_len > 0)) return fail(ENVPIC_EINVAL, "ramp_len must be > 0");
   if (p->profile == ENVPIC_PROFILE_BUMP && !(p->bump_w > 0)) return fail(ENVPIC_EINVAL, "bump_w must be > 0");
@@ -411,7 +414,10 @@ struct envpic_sim {
   // Steps between sorts: particles drift at most one cell per step, and the
   // LDS halo holds SORT_EVERY cells of drift plus the linear stencil, or
   // SORT_EVERY - 1 cells plus the wider quadratic one.
-  int sort_every() const { return p.shape_order == 2 ? SORT_EVERY - 1 : SORT_EVERY; }
+  int sort_every() const {
+    const int most = p.shape_order == 2 ? SORT_EVERY - 1 : SORT_EVERY;
+    return p.sort_every > 0 && p.sort_every < most ? p.sort_every : most;
+  }
   bool presort() const { return n + 1 - sorted_at >= sort_every(); }
   bool shift_due() const {
     return p.moving_window && (double)(n + 1) * p.dt >= (double)(shift + 1) * p.dx;
@@ -1056,7 +1062,7 @@ void envpic_params_default(envpic_params* p, int preset) {
     case 3:  // bandwidth case
       p->nx = 4096; p->nr = 512; p->n_modes = 2; p->ppc_t = 4; p->profile = ENVPIC_PROFILE_PERTURB;
       p->n0 = 0.001; p->perturb = 0.01; p->a0 = 2.5; p->w0 = 150.0; p->tau = 80.0;
-      p->x_c = p->x_f = 4096 * 0.8 / 2;
+      p->x_c = p->x_f = 4096 * 0.8 / 2; p->sort_every = 1;
       break;
     case 4:  // largest scan-job shape
       p->nx = 2048; p->nr = 256; p->ppc_t = 2; p->profile = ENVPIC_PROFILE_UNIFORM; p->n0 = 0.0025;
@@ -1335,7 +1341,7 @@ int envpic_load(envpic_sim* s, const void* blob, size_t bytes) {
       h.modes != s->p.n_modes)
     return fail(ENVPIC_EINVAL, "checkpoint does not match this simulation");
   // the parameter block has no padding: equal parameters are equal bytes
-  static_assert(sizeof(envpic_params) == 12 * 4 + 8 + 13 * 8 + 8 + 2 * 4, "envpic_params has padding");
+  static_assert(sizeof(envpic_params) == 12 * 4 + 8 + 13 * 8 + 8 + 4 * 4, "envpic_params has padding");
   if (std::memcmp(&h.params, &s->p, sizeof(envpic_params)) != 0)
     return fail(ENVPIC_EINVAL, "checkpoint written with other parameters");
   if (h.nfields != n_ckpt_fields(s->p)) return fail(ENVPIC_EINVAL, "checkpoint field count does not match");

@@ -254,7 +254,6 @@ template <class R, bool M1>
 __device__ inline void maxwell_tile(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din,
                                     const DepositBufs<R>& dnext, int i0, int j0, bool left_edge_zero,
                                     MwShared<R, M1>& sm) {
-  using C = typename cplx_of<R>::type;
   constexpr int HJ = MwShared<R, M1>::HJ, HN = MwShared<R, M1>::HN;
   static_assert(HN <= 2 * MW_T, "two nodes per thread at most");
   auto put = [&](int k, const ENew<R, M1>& e) {

@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libenvpic.so")
 HEADER = os.path.join(_HERE, "..", "include", "envpic.h")
 
-PARAMS_VERSION = 1
+PARAMS_VERSION = 3
 FP32_BULK, FP64 = 0, 1
 MOMENTUM, POSITION = 0, 1
 DEFER_DEPOSIT = 0x100
@@ -56,6 +56,7 @@ class Params(ctypes.Structure):
         ("bump_x", ctypes.c_double), ("bump_w", ctypes.c_double),
         ("capacity", ctypes.c_int64),
         ("filter_passes", ctypes.c_int32), ("shape_order", ctypes.c_int32),
+        ("sort_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
     ]
 
 
@@ -67,7 +68,7 @@ EXPORTS = [
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
     "envpic_set_timing", "envpic_get_timing", "envpic_set_graph", "envpic_beam_diagnostics",
-    "envpic_bunch_fields",
+    "envpic_bunch_fields", "envpic_stream_copy",
 ]
 
 
@@ -109,6 +110,7 @@ def lib():
     L.envpic_load.argtypes = [vp, vp, ctypes.c_size_t]
     L.envpic_debug_poison.argtypes = [vp, ctypes.c_int]
     L.envpic_sim_destroy.argtypes = [vp]
+    L.envpic_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int, vp]
     L.envpic_sim_destroy.restype = None
     L.envpic_last_error.argtypes = [vp]
     L.envpic_last_error.restype = ctypes.c_char_p
@@ -152,6 +154,7 @@ def make_params(cfg):
     p.capacity = int(cfg.get("capacity", 0))
     p.filter_passes = int(cfg.get("filter_passes", 0))
     p.shape_order = int(cfg.get("shape_order", 0))
+    p.sort_every = int(cfg.get("sort_every", 0))
     return p
 
 
@@ -321,6 +324,18 @@ class Sim:
 
     def poison(self, name):
         _check(lib().envpic_debug_poison(self._h, FIELDS[name]))
+
+
+def stream_copy(dst, src, variant=0, stream=None):
+    """Plain streaming copy of the device tensor src into dst (same number of
+    bytes) with the library's copy kernel, on `stream` (default: torch's
+    current stream)."""
+    import torch
+    n = src.numel() * src.element_size()
+    assert dst.numel() * dst.element_size() == n
+    stream = stream if stream is not None else torch.cuda.current_stream()
+    _check(lib().envpic_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), n,
+                                    int(variant), ctypes.c_void_p(stream.cuda_stream)))
 
 
 def batch_step(sims, nsteps, stream=None):

@@ -41,7 +41,7 @@ C2 = _cfg(name="c2_lwfa_2048x256", nx=2048, nr=256, n_modes=2, ppc=(2, 2, 4),
 # particle sort every step.
 C3 = _cfg(name="c3_bandwidth_4096x512", nx=4096, nr=512, n_modes=2, ppc=(2, 2, 4),
           profile="perturb", n0=0.001, perturb=0.01, a0=2.5, w0=150.0, tau=80.0,
-          x_c=4096 * 0.8 / 2, x_f=4096 * 0.8 / 2, moving_window=0,
+          x_c=4096 * 0.8 / 2, x_f=4096 * 0.8 / 2, moving_window=0, sort_every=1,
           seed=BASE_SEED + 3, steps=500)
 
 # C5: scale case, 8192 x 768, modes 0 and 1, 2x2x6 (151 M particles),
@@ -53,6 +53,11 @@ C5 = _cfg(name="c5_extreme_8192x768", nx=8192, nr=768, n_modes=2, ppc=(2, 2, 6),
           moving_window=1, seed=BASE_SEED + 5, steps=2000)
 
 CONFIGS = {"C1": C1, "C2": C2, "C3": C3, "C5": C5}
+
+# a small window of the LWFA shape (host-side checks of the parameter block)
+C2_SMALL_LIKE = _cfg(name="c2_small_like", nx=192, nr=48, n_modes=2, ppc=(2, 2, 4), profile="ramp",
+                     n0=0.004, ramp_len=40.0, a0=2.0, w0=20.0, tau=15.0, x_c=108.6, x_f=108.6,
+                     moving_window=1, seed=BASE_SEED + 6)
 
 # C4: serving scan -- 64 jobs, Poisson arrivals at 4 jobs/s, grids drawn
 # from {512x64, 1024x128, 2048x256}, mode 0, 2x2x2 particles per cell,

@@ -17,15 +17,18 @@ from inputs import C2, C3  # noqa: E402
 def test_algorithmic_bytes_per_launch():
     """Per particle: momentum reads cell, offsets, azimuth, p, w (32 B) and
     writes p (12 B); position reads the same 32 B and writes cell, offsets,
-    azimuth (16 B).  Per cell (modes 0 and 1): 72 B and 48 B."""
+    azimuth (16 B).  Per cell (modes 0 and 1): 72 B and 48 B.  The field
+    update moves 36 B per cell for mode 0 and 144 B more for mode 1; the
+    envelope update 28 B."""
     n = 2048 * 256 * 16
     ab = bench.algorithmic_bytes(C2, n)
-    assert ab["per_particle"] == {"k_momentum": 44, "k_position": 48}
-    assert ab["per_cell"] == {"k_momentum": 72, "k_position": 48}
+    assert ab["per_particle"] == {"k_momentum": 44, "k_position": 48, "k_field": 0, "k_envelope": 0}
+    assert ab["per_cell"] == {"k_momentum": 72, "k_position": 48, "k_field": 180, "k_envelope": 28}
     assert ab["k_momentum"] == 44 * n + 72 * 2048 * 256 == 406_847_488
     assert ab["k_position"] == 48 * n + 48 * 2048 * 256 == 427_819_008
+    assert ab["k_field"] == 180 * 2048 * 256
     m0 = bench.algorithmic_bytes(dict(C3, n_modes=1), 10)
-    assert m0["per_cell"] == {"k_momentum": 24, "k_position": 24}
+    assert m0["per_cell"] == {"k_momentum": 24, "k_position": 24, "k_field": 36, "k_envelope": 28}
 
 
 def test_traffic_records_follow_the_sources(tmp_path, monkeypatch):

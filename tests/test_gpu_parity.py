@@ -304,6 +304,37 @@ def test_diagnostics_are_bitwise_reproducible(E):
         assert all(a[k] == b[k] for k in DIAG_KEYS), (a, b)
 
 
+@pytest.mark.parametrize("sort_every", [1, 2])
+def test_runtime_sort_period_parity(E, oracle_mod, sort_every):
+    """A particle sort every step (or every second step) instead of every
+    third: the window run of modes 0 and 1 still matches the oracle, which
+    never sorts, after 100 steps (FP32 bars)."""
+    cfg = dict(C2_SMALL, sort_every=sort_every)
+    g = E.Sim(cfg, E.FP32_BULK)
+    r = oracle_mod.OracleSim(C2_SMALL)
+    g.step(100)
+    r.step(100)
+    assert g.state() == r.state()
+    compare_fields(g, r, 1e-4, modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), 1e-3, 1e-3)
+
+
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
+def test_stream_copy_kernel(E, variant):
+    """The bandwidth-reference copy moves every byte, for sizes that are not
+    multiples of its rounds, and rejects misaligned or ragged sizes."""
+    import torch
+    for n in (16, 4096 + 48, 3 * 2**20 + 16 * 7):
+        src = torch.randint(0, 256, (n,), dtype=torch.uint8, device="cuda")
+        dst = torch.zeros_like(src)
+        E.stream_copy(dst, src, variant)
+        torch.cuda.synchronize()
+        assert torch.equal(dst, src), n
+    a = torch.zeros(64, dtype=torch.uint8, device="cuda")
+    with pytest.raises(E.EnvpicError):
+        E.stream_copy(a[:40], a[8:48], variant)  # 40 bytes: not a multiple of 16
+
+
 # ------------------------------------------------------------ API paths --
 # ------------------------------------------------------------ edge cases --
 RAGGED = dict(name="ragged", nx=101, nr=21, dx=0.8, dr=1.5, dt=0.6, n_modes=2, ppc=(2, 3, 3),

@@ -95,3 +95,17 @@ def test_beam_diagnostics_null_sim_rejected(E):
     dp = out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     assert E.lib().envpic_beam_diagnostics(None, 0.0, 1.0, 8, dp, None) == -1
     assert len(E.envpic.BEAM_NAMES) == 12
+
+
+def test_sort_period_is_validated(E):
+    """sort_every: 0 (default) or 1 .. 3, and at most 2 with quadratic
+    shapes (the LDS halo holds that many steps of drift)."""
+    from inputs import C2_SMALL_LIKE
+    for v, order, ok in ((0, 1, True), (1, 1, True), (3, 1, True), (4, 1, False), (-1, 1, False),
+                         (2, 2, True), (3, 2, False)):
+        cfg = dict(C2_SMALL_LIKE, sort_every=v, shape_order=order)
+        if ok:
+            assert E.footprint(cfg) > 0
+        else:
+            with pytest.raises(E.EnvpicError):
+                E.footprint(cfg)
