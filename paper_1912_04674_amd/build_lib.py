@@ -24,19 +24,22 @@ FLAGS = [
 ]
 
 
-def build(verbose=False):
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose=False, csrc=CSRC, out=LIB, build_dir=BUILD, defines=()):
+    """Compile the sources of `csrc` into the shared library `out` (by
+    default the package's own sources and library); `defines` are extra
+    -D options."""
+    os.makedirs(build_dir, exist_ok=True)
     procs, objs = [], []
     for src in SOURCES:
-        obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        obj = os.path.join(build_dir, src.replace(".hip", ".o"))
         objs.append(obj)
-        cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"), "-c",
-               os.path.join(CSRC, src), "-o", obj]
+        cmd = [HIPCC, *FLAGS, *(f"-D{d}" for d in defines), "-I", os.path.join(HERE, "..", "include"), "-c",
+               os.path.join(csrc, src), "-o", obj]
         procs.append((src, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.STDOUT)))
     failed = []
     for src, pr in procs:
-        out, _ = pr.communicate()
-        text = out.decode(errors="replace")
+        log, _ = pr.communicate()
+        text = log.decode(errors="replace")
         # hipcc's host pass does not know the packed-fp32 target feature
         lines = [ln for ln in text.splitlines() if "packed-fp32-ops" not in ln and ln.strip()]
         if pr.returncode != 0:
@@ -46,10 +49,10 @@ def build(verbose=False):
             sys.stderr.write(f"[build] {src}:\n" + "\n".join(lines) + "\n")
     if failed:
         raise RuntimeError(f"hipcc failed for {failed}")
-    tmp = LIB + ".tmp"
+    tmp = out + ".tmp"
     subprocess.check_call([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

@@ -39,13 +39,14 @@ template <class R> __device__ inline Lin<R> dual_w(int c, R f) {
   return Lin<R>{c, (R)1 - v, v};
 }
 
-template <class R> __device__ inline R interp2(const R* a, Lin<R> sx, Lin<R> sr) {
-  return sx.a * (sr.a * a[sx.i * LR + sr.i] + sr.b * a[sx.i * LR + sr.i + 1]) +
-         sx.b * (sr.a * a[(sx.i + 1) * LR + sr.i] + sr.b * a[(sx.i + 1) * LR + sr.i + 1]);
+// (RL: the row length of the LDS region the values are staged in)
+template <class R, int RL = LR> __device__ inline R interp2(const R* a, Lin<R> sx, Lin<R> sr) {
+  return sx.a * (sr.a * a[sx.i * RL + sr.i] + sr.b * a[sx.i * RL + sr.i + 1]) +
+         sx.b * (sr.a * a[(sx.i + 1) * RL + sr.i] + sr.b * a[(sx.i + 1) * RL + sr.i + 1]);
 }
-template <class C, class R> __device__ inline C interp2c(const C* a, Lin<R> sx, Lin<R> sr) {
-  C v00 = a[sx.i * LR + sr.i], v01 = a[sx.i * LR + sr.i + 1];
-  C v10 = a[(sx.i + 1) * LR + sr.i], v11 = a[(sx.i + 1) * LR + sr.i + 1];
+template <class C, class R, int RL = LR> __device__ inline C interp2c(const C* a, Lin<R> sx, Lin<R> sr) {
+  C v00 = a[sx.i * RL + sr.i], v01 = a[sx.i * RL + sr.i + 1];
+  C v10 = a[(sx.i + 1) * RL + sr.i], v11 = a[(sx.i + 1) * RL + sr.i + 1];
   R w00 = sx.a * sr.a, w01 = sx.a * sr.b, w10 = sx.b * sr.a, w11 = sx.b * sr.b;
   return mk<C>(w00 * v00.x + w01 * v01.x + w10 * v10.x + w11 * v11.x,
                w00 * v00.y + w01 * v01.y + w10 * v10.y + w11 * v11.y);
@@ -68,20 +69,21 @@ template <class R> __device__ inline Quad<R> quad_primal(int c, R f) {
 }
 template <class R> __device__ inline Quad<R> quad_dual(int c, R f) { return quad_of<R>(c - 1, f - (R)0.5); }
 
-template <class R> __device__ inline R interp3(const R* a, const Quad<R>& sx, const Quad<R>& sr) {
+template <class R, int RL = LR> __device__ inline R interp3(const R* a, const Quad<R>& sx, const Quad<R>& sr) {
   R acc = 0;
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
-    const R* col = a + (sx.i + u) * LR + sr.i;
+    const R* col = a + (sx.i + u) * RL + sr.i;
     acc += sx.w[u] * (sr.w[0] * col[0] + sr.w[1] * col[1] + sr.w[2] * col[2]);
   }
   return acc;
 }
-template <class C, class R> __device__ inline C interp3c(const C* a, const Quad<R>& sx, const Quad<R>& sr) {
+template <class C, class R, int RL = LR>
+__device__ inline C interp3c(const C* a, const Quad<R>& sx, const Quad<R>& sr) {
   R re = 0, im = 0;
 #pragma unroll
   for (int u = 0; u < 3; ++u) {
-    const C* col = a + (sx.i + u) * LR + sr.i;
+    const C* col = a + (sx.i + u) * RL + sr.i;
     re += sx.w[u] * (sr.w[0] * col[0].x + sr.w[1] * col[1].x + sr.w[2] * col[2].x);
     im += sx.w[u] * (sr.w[0] * col[0].y + sr.w[1] * col[1].y + sr.w[2] * col[2].y);
   }
@@ -256,20 +258,21 @@ __device__ inline int placed_rank(int r, int v, int chunk) {
   return lo + transpose_rank(r - lo, hi - lo);
 }
 
-// the tile region of a work item: lab column X0 = T TX - HALO, row R0
+// the tile region of a work item with a margin of h cells: lab column
+// X0 = T TX - h, row R0 = tcr TR - h
 struct Region {
   int T, tcx, tcr;
   int X0;  // lab column (lab columns fit 20 bits)
   int relX0, R0;
 };
-__device__ inline Region region_of(const Geo& g, int key) {
+__device__ inline Region region_of(const Geo& g, int key, int h = HALO) {
   Region q;
   q.tcx = key / g.ntr;
   q.tcr = key - q.tcx * g.ntr;
   q.T = lab_tile(g, q.tcx);
-  q.X0 = q.T * TX - HALO;
+  q.X0 = q.T * TX - h;
   q.relX0 = (int)((long long)q.X0 - g.shift);
-  q.R0 = q.tcr * TR - HALO;
+  q.R0 = q.tcr * TR - h;
   return q;
 }
 
@@ -277,14 +280,22 @@ __device__ inline Region region_of(const Geo& g, int key) {
 // The chi deposit accumulates in 64-bit LDS words (Acc0): 64-bit atomics
 // run at a much higher rate than ds_add_f32 on gfx950 (measured), and the
 // accumulated sums are rounded once, at the flush.
-template <class R, bool M1> struct SmemMom {
+// A region with a margin of H cells: (TX + 2H + 1) x (TR + 2H + 1) nodes.
+template <int H> struct Halo {
+  static constexpr int X = TX + 2 * H + 1, R = TR + 2 * H + 1, N = X * R;
+};
+// The staged gradient of Phi is kept for quadratic shapes only (its ghost row
+// below the axis); linear gathers difference Phi where they read it.  The
+// sort counters exist only in the scattering variants.
+template <class R, bool M1, int H, int O, bool SC> struct SmemMom {
   using C = typename cplx_of<R>::type;
-  R ex[LN], er[LN], bt[LN], phi[LN], gx[LN], gr[LN];
-  typename Acc0<R>::T chi[LN];
-  C ex1[M1 ? LN : 1], er1[M1 ? LN : 1], et1[M1 ? LN : 1];
-  C bx1[M1 ? LN : 1], br1[M1 ? LN : 1], bt1[M1 ? LN : 1];
-  R ivol[LR];
-  int ccell[CRN];  // sort: particles per destination cell, then their first slot
+  static constexpr int N = Halo<H>::N;
+  R ex[N], er[N], bt[N], phi[N], gx[O == 2 ? N : 1], gr[O == 2 ? N : 1];
+  typename Acc0<R>::T chi[N];
+  C ex1[M1 ? N : 1], er1[M1 ? N : 1], et1[M1 ? N : 1];
+  C bx1[M1 ? N : 1], br1[M1 ? N : 1], bt1[M1 ? N : 1];
+  R ivol[Halo<H>::R];
+  int ccell[SC ? CRN : 1];  // sort: particles per destination cell, then their first slot
 };
 constexpr int PPT = CHUNK / WG;  // particles per thread of a work item
 
@@ -333,17 +344,31 @@ __device__ inline int wave_slot_rank(int slot, int* counters) {
 // LDS atomics do not collide), at the price of strided writes.
 // O: particle shape order (1 linear, 2 quadratic; order 2 re-sorts every
 // second step, so its wider stencil stays inside the same halo).
+// Waves per SIMD the compiler must allow: the FP32 linear in-place pass fits
+// four work groups per CU in LDS (its smaller region), so its registers are
+// held to 64 per lane (eight waves per SIMD); the others are not constrained.
+template <class R, bool DEFER, int SCAT, int O> constexpr int mom_waves_per_simd() {
+  return (sizeof(R) == 4 && !DEFER && SCAT == SCAT_NONE && O == 1) ? 8 : 1;
+}
+
+// Margin: a scattering pass gathers at most SORT_EVERY cells of drift from
+// the tile (SORT_EVERY - 1 with quadratic shapes) and needs the full HALO;
+// the passes in between have drifted one cell less and stage a region with
+// one cell less of margin (fewer bytes staged, less LDS per work group).
 template <class R, bool M1, bool DEFER, int SCAT, int O>
-__global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restrict__ chi_out,
+__global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void k_momentum(
+    Geo g, Grids<R> f, R* __restrict__ chi_out,
                                                  Parts<R> src, Parts<R> dst, Layout Ls, Layout Ld,
                                                  int* __restrict__ ccur, R* __restrict__ gscr, int* err) {
   using C = typename cplx_of<R>::type;
-  __shared__ SmemMom<R, M1> sm;
+  constexpr int H = (SCAT == SCAT_NONE && !DEFER) ? HALO - 1 : HALO;
+  constexpr int RX = Halo<H>::X, RL = Halo<H>::R, RN = Halo<H>::N;
+  __shared__ SmemMom<R, M1, H, O, SCAT != SCAT_NONE> sm;
   const int item = item_of(blockIdx.x, gridDim.x);
   if (item >= *Ls.n_items) return;
   const int4 it = Ls.items[item];
   const int start = it.y, count = it.z;
-  const Region q = region_of(g, it.x);
+  const Region q = region_of(g, it.x, H);
   const R hdt = (R)(0.5 * g.dt);
 
   // ---- stage E, Bbar, Phi (and mode 1) of the region in LDS.  Every load
@@ -353,8 +378,8 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   // parity of the component (odd for mode-0 E_r and Bbar_t and mode-1 B_x).
   // The quadratic stencil also reaches the primal ghost row j = -1, which
   // mirrors row 1 (odd: mode-1 E_x; even: the others).
-  for (int k = threadIdx.x; k < LN; k += WG) {
-    const int a = k / LR, b = k - (k / LR) * LR;
+  for (int k = threadIdx.x; k < RN; k += WG) {
+    const int a = k / RL, b = k - (k / RL) * RL;
     const int rel = q.relX0 + a, j = q.R0 + b;
     const bool px = rel >= 0 && rel <= g.nx, dxok = rel >= 0 && rel <= g.nx - 1;
     const size_t o = (px || dxok) ? (size_t)phys_col(g, rel) * g.pitch : 0;
@@ -384,7 +409,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
       sm.bt1[k] = dxok ? cscale(bt, hp) : z;
     }
   }
-  for (int k = threadIdx.x; k < LR; k += WG) {
+  for (int k = threadIdx.x; k < RL; k += WG) {
     const int j = q.R0 + k;
     sm.ivol[k] = (j >= 0 && j <= g.nr) ? inv_vol_node<R>(g, j) : (R)0;
   }
@@ -392,15 +417,17 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     for (int k = threadIdx.x; k < (SCAT == SCAT_CELL ? CRN : 9); k += WG) sm.ccell[k] = 0;
   __syncthreads();
   // grad Phi by centred differences on the primal nodes (zero radial
-  // derivative on the axis); the outermost ring of the region is unused
-  {
-    const R i2dx = (R)(0.5 / g.dx), i2dr = (R)(0.5 / g.dr);
-    for (int k = threadIdx.x; k < LN; k += WG) {
-      const int a = k / LR, b = k - (k / LR) * LR;
+  // derivative on the axis); the outermost ring of the region is unused.
+  // Quadratic shapes stage it (with its odd ghost row below the axis);
+  // linear gathers difference the staged Phi themselves (below).
+  const R i2dx = (R)(0.5 / g.dx), i2dr = (R)(0.5 / g.dr);
+  if constexpr (O == 2) {
+    for (int k = threadIdx.x; k < RN; k += WG) {
+      const int a = k / RL, b = k - (k / RL) * RL;
       R vx = 0, vr = 0;
-      if (a >= 1 && a <= LX - 2 && b >= 1 && b <= LR - 2) {
-        vx = (sm.phi[k + LR] - sm.phi[k - LR]) * i2dx;
-        if (O == 2 && q.R0 + b == -1)  // odd below the axis: minus the value on row 1
+      if (a >= 1 && a <= RX - 2 && b >= 1 && b <= RL - 2) {
+        vx = (sm.phi[k + RL] - sm.phi[k - RL]) * i2dx;
+        if (q.R0 + b == -1)  // odd below the axis: minus the value on row 1
           vr = -((sm.phi[k + 3] - sm.phi[k + 1]) * i2dr);
         else if (q.R0 + b != 0)
           vr = (sm.phi[k + 1] - sm.phi[k - 1]) * i2dr;
@@ -502,11 +529,12 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
     }
     const R fx = src.fx[p], fr = src.fr[p], th = src.th[p], w = src.w[p];
     R pv[3] = {src.px[p], src.py[p], src.pz[p]};
-    // the cell relative to the region: [1, LX - 3] for the linear stencils;
-    // order 2 (two steps of drift at most) keeps [2, LX - 4], the range its
-    // position pass needs for the current stencil of the old and new cells
-    const int a = O == 2 ? clampi(cell_ix(cw) - q.X0, 2, LX - 4, bad) : clampi(cell_ix(cw) - q.X0, 1, LX - 3, bad);
-    const int b = O == 2 ? clampi(cell_jr(cw) - q.R0, 2, LR - 4, bad) : clampi(cell_jr(cw) - q.R0, 1, LR - 3, bad);
+    // the cell relative to the region: [1, RX - 3] for the linear stencils
+    // (and the differences of Phi one node further out); order 2 keeps
+    // [2, RX - 4], the range its position pass needs for the current
+    // stencil of the old and new cells
+    const int a = O == 2 ? clampi(cell_ix(cw) - q.X0, 2, RX - 4, bad) : clampi(cell_ix(cw) - q.X0, 1, RX - 3, bad);
+    const int b = O == 2 ? clampi(cell_jr(cw) - q.R0, 2, RL - 4, bad) : clampi(cell_jr(cw) - q.R0, 1, RL - 3, bad);
     R s, c;
     sincos_r(th, &s, &c);
     R ex, er, bt, et = 0, bx = 0, br = 0, ph, gx, gr;
@@ -516,37 +544,47 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
       Qx = quad_primal<R>(a, fx);
       Qr = quad_primal<R>(b, fr);
       const Quad<R> Ux = quad_dual<R>(a, fx), Ur = quad_dual<R>(b, fr);
-      ex = interp3<R>(sm.ex, Ux, Qr);
-      er = interp3<R>(sm.er, Qx, Ur);
-      bt = interp3<R>(sm.bt, Ux, Ur);
-      ph = interp3<R>(sm.phi, Qx, Qr);
-      gx = interp3<R>(sm.gx, Qx, Qr);
-      gr = interp3<R>(sm.gr, Qx, Qr);
+      ex = interp3<R, RL>(sm.ex, Ux, Qr);
+      er = interp3<R, RL>(sm.er, Qx, Ur);
+      bt = interp3<R, RL>(sm.bt, Ux, Ur);
+      ph = interp3<R, RL>(sm.phi, Qx, Qr);
+      gx = interp3<R, RL>(sm.gx, Qx, Qr);
+      gr = interp3<R, RL>(sm.gr, Qx, Qr);
       if (M1) {
-        ex += mode1_at<C, R>(interp3c<C, R>(sm.ex1, Ux, Qr), c, s);
-        er += mode1_at<C, R>(interp3c<C, R>(sm.er1, Qx, Ur), c, s);
-        et = mode1_at<C, R>(interp3c<C, R>(sm.et1, Qx, Qr), c, s);
-        bx = mode1_at<C, R>(interp3c<C, R>(sm.bx1, Qx, Ur), c, s);
-        br = mode1_at<C, R>(interp3c<C, R>(sm.br1, Ux, Qr), c, s);
-        bt += mode1_at<C, R>(interp3c<C, R>(sm.bt1, Ux, Ur), c, s);
+        ex += mode1_at<C, R>(interp3c<C, R, RL>(sm.ex1, Ux, Qr), c, s);
+        er += mode1_at<C, R>(interp3c<C, R, RL>(sm.er1, Qx, Ur), c, s);
+        et = mode1_at<C, R>(interp3c<C, R, RL>(sm.et1, Qx, Qr), c, s);
+        bx = mode1_at<C, R>(interp3c<C, R, RL>(sm.bx1, Qx, Ur), c, s);
+        br = mode1_at<C, R>(interp3c<C, R, RL>(sm.br1, Ux, Qr), c, s);
+        bt += mode1_at<C, R>(interp3c<C, R, RL>(sm.bt1, Ux, Ur), c, s);
       }
     } else {
       Px = primal_w<R>(a, fx);
       Pr = primal_w<R>(b, fr);
       const Lin<R> Dx = dual_w<R>(a, fx), Dr = dual_w<R>(b, fr);
-      ex = interp2<R>(sm.ex, Dx, Pr);
-      er = interp2<R>(sm.er, Px, Dr);
-      bt = interp2<R>(sm.bt, Dx, Dr);
-      ph = interp2<R>(sm.phi, Px, Pr);
-      gx = interp2<R>(sm.gx, Px, Pr);
-      gr = interp2<R>(sm.gr, Px, Pr);
+      ex = interp2<R, RL>(sm.ex, Dx, Pr);
+      er = interp2<R, RL>(sm.er, Px, Dr);
+      bt = interp2<R, RL>(sm.bt, Dx, Dr);
+      // Phi on the 4 x 4 nodes around the cell (corners unused): itself on
+      // the inner 2 x 2, its centred differences at those four nodes (the
+      // radial one zero on the axis row)
+      const R* pc = &sm.phi[a * RL + b];
+      const R p00 = pc[0], p01 = pc[1], p10 = pc[RL], p11 = pc[RL + 1];
+      ph = Px.a * (Pr.a * p00 + Pr.b * p01) + Px.b * (Pr.a * p10 + Pr.b * p11);
+      const R gx00 = (p10 - pc[-RL]) * i2dx, gx01 = (p11 - pc[1 - RL]) * i2dx;
+      const R gx10 = (pc[2 * RL] - p00) * i2dx, gx11 = (pc[2 * RL + 1] - p01) * i2dx;
+      gx = Px.a * (Pr.a * gx00 + Pr.b * gx01) + Px.b * (Pr.a * gx10 + Pr.b * gx11);
+      const bool axis = q.R0 + b == 0;
+      const R gr00 = axis ? (R)0 : (p01 - pc[-1]) * i2dr, gr10 = axis ? (R)0 : (p11 - pc[RL - 1]) * i2dr;
+      const R gr01 = (pc[2] - p00) * i2dr, gr11 = (pc[RL + 2] - p10) * i2dr;
+      gr = Px.a * (Pr.a * gr00 + Pr.b * gr01) + Px.b * (Pr.a * gr10 + Pr.b * gr11);
       if (M1) {
-        ex += mode1_at<C, R>(interp2c<C, R>(sm.ex1, Dx, Pr), c, s);
-        er += mode1_at<C, R>(interp2c<C, R>(sm.er1, Px, Dr), c, s);
-        et = mode1_at<C, R>(interp2c<C, R>(sm.et1, Px, Pr), c, s);
-        bx = mode1_at<C, R>(interp2c<C, R>(sm.bx1, Px, Dr), c, s);
-        br = mode1_at<C, R>(interp2c<C, R>(sm.br1, Dx, Pr), c, s);
-        bt += mode1_at<C, R>(interp2c<C, R>(sm.bt1, Dx, Dr), c, s);
+        ex += mode1_at<C, R>(interp2c<C, R, RL>(sm.ex1, Dx, Pr), c, s);
+        er += mode1_at<C, R>(interp2c<C, R, RL>(sm.er1, Px, Dr), c, s);
+        et = mode1_at<C, R>(interp2c<C, R, RL>(sm.et1, Px, Pr), c, s);
+        bx = mode1_at<C, R>(interp2c<C, R, RL>(sm.bx1, Px, Dr), c, s);
+        br = mode1_at<C, R>(interp2c<C, R, RL>(sm.br1, Dx, Pr), c, s);
+        bt += mode1_at<C, R>(interp2c<C, R, RL>(sm.bt1, Dx, Dr), c, s);
       }
     }
     // (x, r, theta) -> Cartesian, r-hat = (0, c, s), theta-hat = (0, -s, c)
@@ -582,7 +620,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
         const double wa = (double)(wg * Qx.w[aa]);
 #pragma unroll
         for (int bb = 0; bb < 3; ++bb)
-          Acc0<R>::add_prod(&sm.chi[(Qx.i + aa) * LR + Qr.i + bb], wa, (double)Qr.w[bb]);
+          Acc0<R>::add_prod(&sm.chi[(Qx.i + aa) * RL + Qr.i + bb], wa, (double)Qr.w[bb]);
       }
     } else {
       const R wg = w * igb * (R)Acc0<R>::scale(g);
@@ -591,7 +629,7 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
         const double wa = (double)(wg * (aa ? Px.b : Px.a));
 #pragma unroll
         for (int bb = 0; bb < 2; ++bb)
-          Acc0<R>::add_prod(&sm.chi[(Px.i + aa) * LR + Pr.i + bb], wa, (double)(bb ? Pr.b : Pr.a));
+          Acc0<R>::add_prod(&sm.chi[(Px.i + aa) * RL + Pr.i + bb], wa, (double)(bb ? Pr.b : Pr.a));
       }
     }
     if (SCAT != SCAT_NONE) {
@@ -613,8 +651,8 @@ __global__ __launch_bounds__(WG) void k_momentum(Geo g, Grids<R> f, R* __restric
   if (bad) atomicOr(err, ERR_HALO);
   if (DEFER) return;
   __syncthreads();
-  for (int k = threadIdx.x; k < LN; k += WG) {
-    const int a = k / LR, b = k - (k / LR) * LR;
+  for (int k = threadIdx.x; k < RN; k += WG) {
+    const int a = k / RL, b = k - (k / RL) * RL;
     const int rel = q.relX0 + a, j = q.R0 + b;
     typename Acc0<R>::T v = sm.chi[k];
     // order 2: the row below the axis (two LDS rows down) belongs to row 1

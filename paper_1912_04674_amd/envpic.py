@@ -73,14 +73,16 @@ EXPORTS = [
 
 
 def lib():
-    """Load libenvpic.so (raises if it is not built)."""
+    """Load libenvpic.so (raises if it is not built).  ENVPIC_LIB in the
+    environment names another build of the library to load instead."""
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+    path = os.environ.get("ENVPIC_LIB") or LIB_PATH
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with "
                            "`python -m paper_1912_04674_amd.build_lib`")
-    L = ctypes.CDLL(LIB_PATH)
+    L = ctypes.CDLL(path)
     vp, dp = ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)
     up, i64p = ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_int64)
     pp = ctypes.POINTER(Params)
