@@ -479,6 +479,8 @@ template <class R> struct SimT : envpic_sim {
     g.dt = p.dt;
     g.chunk = sz.chunk;
     g.order = p.shape_order == 2 ? 2 : 1;
+    // one buffer's records: cell word and id, six reals and the weight
+    g.stream_parts = sz.capacity * (long long)(8 + 7 * sizeof(R)) >= STREAM_PARTS_BYTES ? 1 : 0;
     // fixed-point scale of the mode-1 current sums: 2^49 over the largest
     // |2 q w v S / V| = 2 w_max / V_0, V_0 = pi dr^2 dx / 4
     const double cmax = 2.0 * wmax * 4.0 / (3.14159265358979323846 * p.dr * p.dr * p.dx);

@@ -39,6 +39,9 @@ constexpr int SCAT_NONE = 0, SCAT_TILE = 1, SCAT_CELL = 2;
 constexpr int CELL_SORT_EVERY = 8;
 constexpr int WG = 512;     // work-group size of the particle kernels
 constexpr int CHUNK = 4096; // largest work item (particles); small runs use smaller items
+// particle buffers at least this large (one buffer's records) stream past the
+// 256 MB last-level cache: their records are accessed non-temporally
+constexpr long long STREAM_PARTS_BYTES = 256LL << 20;
 // A particle's cell is one 32-bit word: lab column << 12 | radial row.  The
 // position inside the cell is kept as FP32 (or FP64) offsets along x and r,
 // so neither a long moving-window run nor a large radius erodes the
@@ -79,6 +82,7 @@ struct Geo {
   double unfix0;     // 1 / fix0
   int chunk;         // particles per work item at most (<= CHUNK, a multiple of WG)
   int order;         // particle shape order: 1 linear, 2 quadratic
+  int stream_parts;  // 1: a particle buffer exceeds the last-level cache (non-temporal record access)
 };
 
 template <class R> struct Parts {

@@ -52,7 +52,7 @@ def compare_particles(pg, pr, tol_p, tol_x_cells, dx=0.8, dr=1.5):
         errs[k] = float(np.abs(pg[k] - pr[k]).max() / pmax)
     errs["x_cells"] = float(np.abs(pg["x"] - pr["x"]).max() / dx)
     errs["yz_cells"] = float(max(np.abs(pg["y"] - pr["y"]).max(), np.abs(pg["z"] - pr["z"]).max()) / dr)
-    say("particle errors", errs)
+    say("particle errors", errs, "max |p_ref|", float(pmax))
     for k in ("px", "py", "pz"):
         assert errs[k] <= tol_p, (k, errs[k])
     assert errs["x_cells"] <= tol_x_cells and errs["yz_cells"] <= tol_x_cells
@@ -64,12 +64,12 @@ MODE1 = {"ex1": "ex", "er1": "er", "et1": "er", "bx1": "bt", "br1": "bt", "bt1":
          "bx1_bar": "bt_bar", "br1_bar": "bt_bar", "bt1_bar": "bt_bar", "jx1": "jx", "jr1": "jr", "jt1": "jr"}
 
 
-CURRENTS = {"jx", "jr", "jx1", "jr1", "jt1"}
+DEPOSITS = {"chi", "jx", "jr", "jx1", "jr1", "jt1"}
 
 
 def compare_fields(gpu, ref, tol, names=MODE0, modes=1, tol_j=None):
-    """Every named grid (and the mode-1 grids) within tol; the deposited
-    currents within tol_j when given (see J_TOL_FP32)."""
+    """Every named grid (and the mode-1 grids) within tol; the deposits
+    (chi and the currents) within tol_j when given (see DEPOSIT_TOL_FP32)."""
     errs = {}
     for n in names:
         errs[n] = ferr(gpu.get_field(n), ref.get_field(n))
@@ -78,22 +78,23 @@ def compare_fields(gpu, ref, tol, names=MODE0, modes=1, tol_j=None):
             errs[n] = ferr(gpu.get_field(n), ref.get_field(n), scale=np.abs(ref.get_field(n0)).max())
     say("field errors", {k: f"{v:.2e}" for k, v in errs.items()})
     for n, e in errs.items():
-        assert e <= (tol_j if (tol_j is not None and n in CURRENTS) else tol), (n, e)
+        assert e <= (tol_j if (tol_j is not None and n in DEPOSITS) else tol), (n, e)
     return errs
 
 
-# The deposited current J^{n+1/2} is not state: it is recomputed each step from
-# the old and new positions.  With linear shapes the share of a particle's
-# current that lands on each face depends, to first order, on where it
-# crosses a node, so a position difference of d cells changes that particle's
-# current by about d / (v dt / dx) of itself.  The FP32 path's positions
-# differ from the FP64 oracle's by up to 2e-4 cells after 100 steps of the
-# full-size workloads (measured), which puts J_x, J_r at 1e-4 to 3e-4 of
-# their maxima there, while the fields they drive stay within 1e-4 (the
-# field update sums J over steps).  Quadratic shapes, without the kinks,
-# keep J below 1e-4.  Full-size runs hold J to this bar; every state grid to
-# 1e-4.
-J_TOL_FP32 = 3e-4
+# The deposits chi^n and J^{n+1/2} are not state: each step recomputes them
+# from the particles' positions.  With linear shapes a particle's share of a
+# node changes by the position difference d (in cells) itself, and for the
+# current the share that lands on each face depends, to first order, on where
+# the particle crosses a node (d / (v dt / dx) of its current).  The FP32
+# path's positions differ from the FP64 oracle's by up to 2e-4 cells after
+# 100 steps of the full-size workloads (measured), which puts chi and J at 1e-4
+# to 3e-4 of their maxima there (measured: chi 1.25e-4 on the 4096 x 512
+# workload, J_x 1.7e-4 on the 2048 x 256 one), while the grids they drive
+# stay within 1e-4 (the envelope and field updates sum them over steps).
+# Quadratic shapes, without the kinks, keep J below 1e-4.  Full-size runs
+# hold the deposits to this bar and every state grid (A, E, B, Bbar) to 1e-4.
+DEPOSIT_TOL_FP32 = 3e-4
 
 
 PRECS = [("fp64", 1e-9, 1e-9), ("fp32", 1e-4, 1e-3)]
@@ -867,7 +868,7 @@ def _full_size_slab(E, oracle_mod, cfg, c0, w, steps, reach=SLAB_REACH):
     rs = r.state()[1]
     del r
     out = None
-    for prec, tol, tol_j, tp in (("fp64", 1e-9, 1e-9, 1e-9), ("fp32", 1e-4, J_TOL_FP32, 1e-3)):
+    for prec, tol, tol_j, tp in (("fp64", 1e-9, 1e-9, 1e-9), ("fp32", 1e-4, DEPOSIT_TOL_FP32, 1e-3)):
         g = E.Sim(cfg, _prec(E, prec))
         g.step(steps)
         gn, gs, _ = g.state()
@@ -879,7 +880,7 @@ def _full_size_slab(E, oracle_mod, cfg, c0, w, steps, reach=SLAB_REACH):
                 scale = np.abs(ref[{"ex1": "ex", "er1": "er", "bt1": "bt", "jx1": "jx"}[n]]).max()
             e = ferr(a, b, scale)
             say("slab field", prec, n, f"{e:.2e}")
-            assert e <= (tol_j if n in CURRENTS else tol), (prec, n, e)
+            assert e <= (tol_j if n in DEPOSITS else tol), (prec, n, e)
         pg = g.get_particles()
         dx = cfg["dx"]
         x_lo = (rs + lo + 1) * dx  # lab x of the oracle window's column lo + 1
@@ -913,11 +914,12 @@ def test_c3_full_size_slab(E, oracle_mod):
 def test_c5_full_size_window_slab(E, oracle_mod):
     """The 8192 x 768, modes 0-1, 151 M-particle workload with the moving
     window and injection at the leading edge, 20 steps (15 window shifts),
-    against an oracle replica of the 96 leading columns; the particle count
-    stays that of the full window (each shift drops one column and injects
-    one)."""
+    against an oracle replica of the 512 leading columns (the pulse sits
+    337 cells behind the leading edge, so the compared particles include the
+    ones it pushes); the particle count stays that of the full window (each
+    shift drops one column and injects one)."""
     say("C5 full size window slab")
-    g = _full_size_slab(E, oracle_mod, C5, C5["nx"] - 96, 96, 20)
+    g = _full_size_slab(E, oracle_mod, C5, C5["nx"] - 512, 512, 20)
     n, shift, count = g.state()
     assert shift == 15
     ppc = int(np.prod(C5["ppc"]))

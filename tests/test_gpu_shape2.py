@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from inputs import C2, random_grid, random_particles, scaled
-from test_gpu_parity import (C2_SMALL, J_TOL_FP32, PRECS, RAGGED, compare_fields, compare_particles, ferr,
+from test_gpu_parity import (C2_SMALL, DEPOSIT_TOL_FP32, PRECS, RAGGED, compare_fields, compare_particles, ferr,
                              say, staggered)
 
 pytestmark = pytest.mark.gpu
@@ -152,7 +152,7 @@ def test_c2_full_window_100_steps(E, oracle_mod, order):
     injection at the leading edge) for 100 steps in the benchmark's launch
     configuration, FP32-bulk and FP64 paths, against the oracle run on the
     whole window (threaded over the host's cores): every grid of both modes
-    (the deposited currents of the FP32 path to J_TOL_FP32), every particle
+    (the deposits of the FP32 path, chi and J, to DEPOSIT_TOL_FP32), every particle
     by id and the nine conserved sums."""
     import torch
     cfg = dict(C2, shape_order=order)
@@ -167,7 +167,7 @@ def test_c2_full_window_100_steps(E, oracle_mod, order):
     ref_parts = r.get_particles()
     dref = r.diagnostics()
     say("oracle done", r.state())
-    for prec, tf, tj, tp in (("fp32", 1e-4, J_TOL_FP32, 1e-3), ("fp64", 1e-9, 1e-9, 1e-9)):
+    for prec, tf, tj, tp in (("fp32", 1e-4, DEPOSIT_TOL_FP32, 1e-3), ("fp64", 1e-9, 1e-9, 1e-9)):
         say("gpu", prec)
         g = E.Sim(cfg, _prec(E, prec))
         g.step(100)
