@@ -251,6 +251,21 @@ int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts);
 /* FP64 device reductions of the current state into out[ENVPIC_NDIAG]. */
 int envpic_diagnostics(const envpic_sim* s, double* out);
 
+/* For callers that cannot allocate device memory, nor synchronise: code under
+ * HIP graph capture, tight serving loops, harnesses that forbid allocation.
+ * The same sums as envpic_diagnostics, from the same kernels, written to
+ * dev_out[ENVPIC_NDIAG] (caller-owned device memory, FP64) asynchronously on
+ * the simulation's stream.  The partial sums live in a scratch array of the
+ * library's own (1024 x 11 doubles, 88 KiB per GPU, kept until the process
+ * ends), not in the arena; its size does not depend on the simulation, so no
+ * simulation is too large for it.  The call allocates nothing, copies
+ * nothing to the host and does not read the error word (envpic_diagnostics
+ * does).  Calls on one GPU share that scratch: two of them that overlap in
+ * time (different streams) race, so order them.  ENVPIC_EORDER in the middle
+ * of a step; ENVPIC_EDEVICE if the scratch could not be located on the
+ * simulation's GPU at init. */
+int envpic_diagnostics_noalloc(const envpic_sim* s, double* dev_out);
+
 /* Injected-beam parameters of the current particles (Sec. 4, Table
  * BeamParams: spectrum peak energy, beam charge, relative energy spread and
  * normalized transverse emittance sqrt(s_uu s_pp - s_up^2), all over the

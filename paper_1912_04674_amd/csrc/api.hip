@@ -265,6 +265,9 @@ struct envpic_sim {
   envpic_params p;
   int prec;
   hipStream_t stream;
+  int device = -1;                  // the GPU current at init (the stream's)
+  double* diag_static = nullptr;    // that GPU's static diagnostics scratch
+  size_t diag_static_doubles = 0;
   Sizes sz;
   int64_t n = 0, shift = 0;
   int stage = 0;     // next expected stage: 0 momentum, 1 envelope, 2 position, 3 field
@@ -403,6 +406,7 @@ struct envpic_sim {
   virtual int get_particles(std::vector<double>* cols, std::vector<uint32_t>* ids) = 0;
   virtual int set_particles(int64_t n, const double* const* cols, const uint32_t* id) = 0;
   virtual int diagnostics(double* out) = 0;
+  virtual int diagnostics_noalloc(double* dev_out) = 0;
   virtual int beam(double e_lo, double e_hi, int nbins, double* out, double* hist) = 0;
   virtual int bunch(uint32_t id_lo, uint32_t id_hi, double beta, double tol, int max_iter, int* iters,
                     double* resid) = 0;
@@ -961,6 +965,17 @@ template <class R> struct SimT : envpic_sim {
     return check_err();
   }
 
+  // the same kernels with the partial sums in the library's static scratch
+  // and the result written to caller-owned device memory, asynchronously
+  int diagnostics_noalloc(double* dev_out) override {
+    if (!diag_static) return fail(ENVPIC_EDEVICE, "the static diagnostics scratch is not available on this device");
+    if ((size_t)diag_scratch_doubles() > diag_static_doubles)
+      return fail(ENVPIC_EINVAL, "diagnostics partial sums exceed the static scratch");
+    launch_diag<R>(geo(), S.parts[cur], S.lay[cur], S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0, diag_static,
+                   dev_out, stream);
+    return launched("diagnostics (static scratch)");
+  }
+
   int beam(double e_lo, double e_hi, int nbins, double* out, double* hist) override {
     BeamArgs a{};
     a.e_lo = e_lo;
@@ -1020,6 +1035,10 @@ int create(const envpic_params* p, int prec, void* arena, size_t bytes, void* st
   s->sz = sizes_of(*p);
   s->fp64_rows = (prec == ENVPIC_FP32_BULK);
   s->arena = (char*)arena;
+  // set-up of the static diagnostics scratch of this GPU (once per device;
+  // only the allocation-free diagnostics call needs it)
+  if (hipGetDevice(&s->device) != hipSuccess || static_scratch(s->device, &s->diag_static, &s->diag_static_doubles))
+    s->diag_static = nullptr;
   plan<R>(*p, s->sz, s->fp64_rows, (char*)arena, &s->S);
   int rc = s->init();
   if (rc) {
@@ -1247,6 +1266,13 @@ int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts) {
 int envpic_diagnostics(const envpic_sim* s, double* out) {
   if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
   return const_cast<envpic_sim*>(s)->diagnostics(out);
+}
+
+int envpic_diagnostics_noalloc(const envpic_sim* cs, double* dev_out) {
+  envpic_sim* s = const_cast<envpic_sim*>(cs);
+  if (!s || !dev_out) return fail(ENVPIC_EINVAL, "NULL argument");
+  if (s->stage != 0) return fail(ENVPIC_EORDER, "diagnostics only between steps");
+  return s->diagnostics_noalloc(dev_out);
 }
 
 int envpic_beam_diagnostics(const envpic_sim* cs, double e_lo, double e_hi, int nbins, double* out, double* hist) {

@@ -80,6 +80,10 @@ void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int f
 // partial sums take diag_scratch_doubles() doubles for any simulation size
 constexpr int DIAG_BLOCKS = 1024;
 int diag_scratch_doubles();
+// device address and size (doubles) of the library's own diagnostics scratch
+// on `device` (a file-scope device array; resolved once per device); 0 on
+// success
+int static_scratch(int device, double** ptr, size_t* doubles);
 template <class R>
 void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, const Grids<R>& f, const R* chi, int fp64_rows,
                  double* scratch, double* out, hipStream_t st);

@@ -15,6 +15,8 @@
 //     butterfly.
 // The partial sums need DIAG_BLOCKS * (NPD + NGD) doubles whatever the
 // simulation's size.
+#include <mutex>
+
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
@@ -163,6 +165,37 @@ __global__ __launch_bounds__(64 * (NPD + NGD)) void k_diag_final(const double* _
 }
 
 int diag_scratch_doubles() { return DIAG_BLOCKS * (NPD + NGD); }
+
+// The partial sums of the allocation-free diagnostics entry point: one copy
+// per GPU the library runs on, held until the process ends.  Host code never
+// passes this name to a kernel: it is a host-side stand-in, and the device
+// address comes from hipGetSymbolAddress, per device (static_scratch below).
+constexpr int STATIC_SCRATCH_DOUBLES = DIAG_BLOCKS * (NPD + NGD);
+static __device__ __align__(256) double scratch[STATIC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_addr[kMaxDevices] = {};
+}  // namespace
+
+int static_scratch(int device, double** ptr, size_t* doubles) {
+  if (device < 0 || device >= kMaxDevices) return -1;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[device]) {
+    int cur = -1;
+    if (hipGetDevice(&cur) != hipSuccess) return -1;
+    if (cur != device && hipSetDevice(device) != hipSuccess) return -1;
+    void* a = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&a, HIP_SYMBOL(scratch));
+    if (cur != device) (void)hipSetDevice(cur);
+    if (e != hipSuccess || !a) return -1;
+    g_scratch_addr[device] = static_cast<double*>(a);
+  }
+  *ptr = g_scratch_addr[device];
+  *doubles = STATIC_SCRATCH_DOUBLES;
+  return 0;
+}
 
 template <class R>
 void launch_diag(const Geo& g, const Parts<R>& P, const Layout& L, const Grids<R>& f, const R* chi, int fp64_rows,

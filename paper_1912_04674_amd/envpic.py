@@ -68,7 +68,7 @@ EXPORTS = [
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
     "envpic_set_timing", "envpic_get_timing", "envpic_set_graph", "envpic_beam_diagnostics",
-    "envpic_bunch_fields", "envpic_stream_copy",
+    "envpic_bunch_fields", "envpic_stream_copy", "envpic_diagnostics_noalloc",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
     L.envpic_get_particles.argtypes = [vp] + [dp] * 7 + [up]
     L.envpic_set_particles.argtypes = [vp, ctypes.c_int64] + [dp] * 7 + [up]
     L.envpic_diagnostics.argtypes = [vp, dp]
+    L.envpic_diagnostics_noalloc.argtypes = [vp, vp]
     L.envpic_beam_diagnostics.argtypes = [vp, ctypes.c_double, ctypes.c_double, ctypes.c_int, dp, dp]
     L.envpic_bunch_fields.argtypes = [vp, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_double, ctypes.c_double,
                                       ctypes.c_int, ctypes.POINTER(ctypes.c_int), dp]
@@ -294,6 +295,15 @@ class Sim:
         out = np.zeros(len(DIAG_NAMES))
         _check(lib().envpic_diagnostics(self._h, _dptr(out)))
         return dict(zip(DIAG_NAMES, out))
+
+    def diagnostics_noalloc(self, out):
+        """The diagnostics into the caller's device tensor `out` (9 float64),
+        asynchronously on the simulation's stream, with no allocation (the
+        library's static scratch holds the partial sums)."""
+        import torch
+        assert out.dtype == torch.float64 and out.is_cuda and out.numel() >= len(DIAG_NAMES)
+        _check(lib().envpic_diagnostics_noalloc(self._h, ctypes.c_void_p(out.data_ptr())))
+        return out
 
     def beam(self, e_lo, e_hi, nbins, with_hist=False):
         """Injected-beam parameters (dict of BEAM_NAMES), and the charge
