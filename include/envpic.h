@@ -236,15 +236,17 @@ int envpic_set_particles(envpic_sim* s, int64_t n, const double* x, const double
                          const double* z, const double* px, const double* py, const double* pz,
                          const double* w, const uint32_t* id);
 
-/* Stage timing: with enable = k > 0, HIP events (without a system-scope
- * fence) are recorded on the simulation's stream around the kernels of each
- * stage (momentum; envelope; position = push, deposit, injection; field =
- * Maxwell, window, sort scans) of every step whose index is a multiple of k
- * (k = 1: every step; a k coprime to the sort periods 3 and 24 samples every
- * variant evenly); enable = 0 turns timing off.  envpic_get_timing synchronises and
- * writes the average milliseconds per timed launch into out_ms[4] and the
- * timed launch counts into counts[4] (either may be NULL); every call of
- * envpic_set_timing resets the sums. */
+/* Stage timing: with enable = k > 0, every step whose index is a multiple of
+ * k times each stage (momentum; envelope; position = push, deposit,
+ * injection; field = [filter,] Maxwell, window, sort scans) with a pair of
+ * HIP events that the dispatch of the stage's first kernel stamps at its
+ * start and the dispatch of its last kernel stamps at its end
+ * (hipExtLaunchKernelGGL), the interval a kernel trace reports, without the
+ * gaps between launches (k = 1: every step; a k coprime to the sort periods
+ * 3 and 24 samples every variant evenly); enable = 0 turns timing off.
+ * envpic_get_timing synchronises and writes the average milliseconds per
+ * timed launch into out_ms[4] and the timed launch counts into counts[4]
+ * (either may be NULL); every call of envpic_set_timing resets the sums. */
 int envpic_set_timing(envpic_sim* s, int enable);
 int envpic_get_timing(envpic_sim* s, double* out_ms, int64_t* counts);
 

@@ -285,7 +285,6 @@ struct envpic_sim {
   int timing = 0;  // record the stage events on every timing-th step (0: off)
   std::vector<hipEvent_t> ev_pool;
   std::vector<Tick> ticks;
-  hipEvent_t ev_open = nullptr;
   double t_ms[4] = {0, 0, 0, 0};
   int64_t t_n[4] = {0, 0, 0, 0};
 
@@ -301,18 +300,21 @@ struct envpic_sim {
     if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
   }
-  void tick_begin() {
-    if (timing <= 0 || n % timing != 0) return;
-    ev_open = take_event();
-    if (ev_open) (void)hipEventRecord(ev_open, stream);
+  // the stage's start and stop events on every timing-th step (none
+  // otherwise): the launchers hand them to the stage's first and last
+  // kernel, whose dispatch stamps them
+  KEvents tick_events() {
+    if (timing <= 0 || n % timing != 0) return KEvents{};
+    hipEvent_t a = take_event(), b = a ? take_event() : nullptr;
+    if (!a || !b) {
+      if (a) ev_pool.push_back(a);
+      return KEvents{};
+    }
+    return KEvents{a, b};
   }
-  void tick_end(int stage) {
-    if (!ev_open) return;
-    hipEvent_t e = take_event();
-    if (!e) return;
-    (void)hipEventRecord(e, stream);
-    ticks.push_back(Tick{stage, ev_open, e});
-    ev_open = nullptr;
+  void tick_end(int stage, const KEvents& ev) {
+    if (!ev.start) return;
+    ticks.push_back(Tick{stage, ev.start, ev.stop});
     if (ticks.size() >= 4096) resolve_ticks();
   }
   int resolve_ticks() {
@@ -393,7 +395,6 @@ struct envpic_sim {
       (void)hipEventDestroy(t.b);
     }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
-    if (ev_open) (void)hipEventDestroy(ev_open);
   }
   virtual int init() = 0;
   virtual int momentum(bool defer) = 0;
@@ -604,10 +605,10 @@ template <class R> struct SimT : envpic_sim {
     const bool scatter = n - sorted_at >= sort_every();
     // every CELL_SORT_EVERY-th sort orders the tiles by cell again
     const int mode = !scatter ? SCAT_NONE : (n_sorts % CELL_SORT_EVERY == 0 ? SCAT_CELL : SCAT_TILE);
-    tick_begin();
+    const KEvents ev = tick_events();
     launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.ccur,
-                       S.scr.w, S.err, sz.max_items, defer, mode, stream);
-    tick_end(0);
+                       S.scr.w, S.err, sz.max_items, defer, mode, stream, ev);
+    tick_end(0, ev);
     if (scatter) {
       cur = 1 - cur;
       sorted_at = n;
@@ -639,9 +640,9 @@ template <class R> struct SimT : envpic_sim {
   int envelope() override {
     if (stage != 1 || !deposit_done) return fail(ENVPIC_EORDER, "envelope stage out of order");
     const Geo g = geo();
-    tick_begin();
-    launch_envelope<R>(g, S.grids, S.dep[n & 1].chi, fp64_rows ? 1 : 0, stream);
-    tick_end(1);
+    const KEvents ev = tick_events();
+    launch_envelope<R>(g, S.grids, S.dep[n & 1].chi, fp64_rows ? 1 : 0, stream, ev);
+    tick_end(1, ev);
     std::swap(S.grids.env, S.grids.envp);
     std::swap(S.grids.ax, S.grids.axp);
     stage = 2;
@@ -663,10 +664,10 @@ template <class R> struct SimT : envpic_sim {
     inj.max_items = sz.max_items;
     inj.pending = S.pending;
     inj.blocks = (shifting && p.profile != ENVPIC_PROFILE_NONE) ? inject_blocks<R>(inj.gn) : 0;
-    tick_begin();
+    const KEvents ev = tick_events();
     launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.ccount, shifting ? 1 : 0,
-                       presort() ? 1 : 0, S.scr, S.err, sz.max_items, defer, inj, stream);
-    tick_end(2);
+                       presort() ? 1 : 0, S.scr, S.err, sz.max_items, defer, inj, stream, ev);
+    tick_end(2, ev);
     stage = 3;
     deferred = defer;
     deposit_done = !defer;
@@ -675,7 +676,7 @@ template <class R> struct SimT : envpic_sim {
 
   int field() override {
     if (stage != 3 || !deposit_done) return fail(ENVPIC_EORDER, "field stage out of order");
-    tick_begin();
+    const KEvents ev = tick_events();
     const Geo g = geo();
     const bool shifting = shift_due(), pre = presort();
     if (shifting) shift += 1;
@@ -699,7 +700,7 @@ template <class R> struct SimT : envpic_sim {
     DepositBufs<R> din = S.dep[n & 1];
     if (p.filter_passes > 0) {
       // the field update reads the filtered current
-      launch_filter<R>(g, din, S.jf, p.filter_passes, stream);
+      launch_filter<R>(g, din, S.jf, p.filter_passes, stream, KEvents{ev.start, nullptr});
       din.jx = S.jf.jx;
       din.jr = S.jf.jr;
       din.jx1 = S.jf.jx1;
@@ -707,7 +708,8 @@ template <class R> struct SimT : envpic_sim {
       din.jt1 = S.jf.jt1;
       jf_valid = true;
     }
-    launch_field<R>(g, S.grids, din, S.dep[(n + 1) & 1], S.dep[0], S.dep[1], fa, stream);
+    launch_field<R>(g, S.grids, din, S.dep[(n + 1) & 1], S.dep[0], S.dep[1], fa, stream,
+                    KEvents{p.filter_passes > 0 ? nullptr : ev.start, ev.stop});
     {
       Grids<R>& G = S.grids;  // the new E, B become the current ones
       std::swap(G.ex, G.ex_n);
@@ -720,7 +722,7 @@ template <class R> struct SimT : envpic_sim {
       std::swap(G.br1, G.br1_n);
       std::swap(G.bt1, G.bt1_n);
     }
-    tick_end(3);
+    tick_end(3, ev);
     n += 1;
     stage = 0;
     return launched("field stage");

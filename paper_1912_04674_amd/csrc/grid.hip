@@ -432,23 +432,27 @@ static inline int node_blocks(const Geo& g) {
 }
 
 template <class R>
-void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st) {
-  hipLaunchKernelGGL((k_envelope<R>), dim3(node_blocks(g)), dim3(256), 0, st, g, f, chi, fp64_rows);
+void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st,
+                     const KEvents& ev) {
+  launch_k(k_envelope<R>, dim3(node_blocks(g)), dim3(256), st, ev, g, f, chi, fp64_rows);
 }
 
 template <class R>
 void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
-                  const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st) {
+                  const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st,
+                  const KEvents& ev) {
   fa.nbx_mw = (g.nr + 1 + MW_TJ - 1) / MW_TJ;
   fa.nb_mw = fa.nbx_mw * ((g.nx + 1 + MW_TI - 1) / MW_TI);
   fa.nb_win = fa.shifting ? (g.nr + 1 + MW_T - 1) / MW_T : 0;
   const int nb_cs = fa.presort ? (g.ntiles + 1) / 2 : 0;
   const int grid = fa.nb_mw + fa.nb_win + nb_cs;
+  // the stage's stop event goes on its last kernel
+  const KEvents ev_field{ev.start, fa.presort ? nullptr : ev.stop};
   if (g.modes >= 2)
-    hipLaunchKernelGGL((k_field<R, true>), dim3(grid), dim3(MW_T), 0, st, g, f, din, dnext, d0, d1, fa);
+    launch_k(k_field<R, true>, dim3(grid), dim3(MW_T), st, ev_field, g, f, din, dnext, d0, d1, fa);
   else
-    hipLaunchKernelGGL((k_field<R, false>), dim3(grid), dim3(MW_T), 0, st, g, f, din, dnext, d0, d1, fa);
-  if (fa.presort) hipLaunchKernelGGL(k_layout_scan, dim3(1), dim3(SCAN_T), 0, st, fa);
+    launch_k(k_field<R, false>, dim3(grid), dim3(MW_T), st, ev_field, g, f, din, dnext, d0, d1, fa);
+  if (fa.presort) launch_k(k_layout_scan, dim3(1), dim3(SCAN_T), st, KEvents{nullptr, ev.stop}, fa);
 }
 
 // ------------------------------------------------- binomial J filter --
@@ -567,14 +571,15 @@ __global__ __launch_bounds__(FTH) void k_filter(Geo g, DepositBufs<R> din, Depos
 }
 
 template <class R>
-void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st) {
+void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st,
+                   const KEvents& ev) {
   if (passes <= 0) return;
   const int tiles = ((g.nx + 1 + FT - 1) / FT) * ((g.nr + 1 + FT - 1) / FT);
   const int grid = tiles * (g.modes >= 2 ? 5 : 2);
   if (g.modes >= 2)
-    hipLaunchKernelGGL((k_filter<R, true>), dim3(grid), dim3(FTH), 0, st, g, din, dout, passes);
+    launch_k(k_filter<R, true>, dim3(grid), dim3(FTH), st, ev, g, din, dout, passes);
   else
-    hipLaunchKernelGGL((k_filter<R, false>), dim3(grid), dim3(FTH), 0, st, g, din, dout, passes);
+    launch_k(k_filter<R, false>, dim3(grid), dim3(FTH), st, ev, g, din, dout, passes);
 }
 
 template <class R>
@@ -583,11 +588,13 @@ void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int f
 }
 
 #define ENVPIC_INST(R)                                                                                      \
-  template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, hipStream_t);                \
+  template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, hipStream_t, const KEvents&); \
   template void launch_field<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&,   \
-                                const DepositBufs<R>&, const DepositBufs<R>&, FieldArgs, hipStream_t);      \
+                                const DepositBufs<R>&, const DepositBufs<R>&, FieldArgs, hipStream_t,       \
+                                const KEvents&);                                                            \
   template void launch_init_envelope<R>(const Geo&, const Grids<R>&, const Laser&, int, hipStream_t);        \
-  template void launch_filter<R>(const Geo&, const DepositBufs<R>&, const DepositBufs<R>&, int, hipStream_t);
+  template void launch_filter<R>(const Geo&, const DepositBufs<R>&, const DepositBufs<R>&, int, hipStream_t, \
+                                 const KEvents&);
 ENVPIC_INST(float)
 ENVPIC_INST(double)
 #undef ENVPIC_INST

@@ -1,10 +1,26 @@
 // launch.hpp -- host-side launchers of the envpic kernels (internal).
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "common.hpp"
 
 namespace envpic {
+
+// Stage timing: events that the command processor stamps when a kernel's
+// dispatch starts (start) and when it completes (stop), as the kernel trace
+// measures it (no gaps between launches inside the interval).  Null events
+// launch the kernel the ordinary way.
+struct KEvents {
+  hipEvent_t start = nullptr, stop = nullptr;
+};
+template <typename... Args, typename F = void (*)(Args...)>
+inline void launch_k(F kernel, dim3 grid, dim3 block, hipStream_t st, const KEvents& ev, Args... args) {
+  if (ev.start || ev.stop)
+    hipExtLaunchKernelGGL(kernel, grid, block, 0, st, ev.start, ev.stop, 0, args...);
+  else
+    hipLaunchKernelGGL(kernel, grid, block, 0, st, args...);
+}
 
 // chi and current deposits of one step (double-buffered by step parity)
 template <class R> struct DepositBufs {
@@ -18,7 +34,7 @@ template <class R> struct DepositBufs {
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                      const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
-                     int scatter, hipStream_t st);
+                     int scatter, hipStream_t st, const KEvents& ev = KEvents{});
 // the plasma of the column entering the window at this step's shift,
 // loaded by extra work groups of the position pass (blocks == 0: none)
 struct InjectArgs {
@@ -33,7 +49,7 @@ struct InjectArgs {
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
                      int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
-                     const InjectArgs& inj, hipStream_t st);
+                     const InjectArgs& inj, hipStream_t st, const KEvents& ev = KEvents{});
 template <class R> int inject_blocks(const Geo& g);
 template <class R>
 void launch_deposit_chi(const Geo& g, R* chi, const Parts<R>& P, const Layout& L, const R* gscr, int* err, int grid,
@@ -45,11 +61,13 @@ template <class R>
 void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, const int* offsets, hipStream_t st);
 
 template <class R>
-void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st);
+void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st,
+                     const KEvents& ev = KEvents{});
 // `passes` passes of the binomial filter on the currents of din into dout
 // (chi is not touched)
 template <class R>
-void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st);
+void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>& dout, int passes, hipStream_t st,
+                   const KEvents& ev = KEvents{});
 // arguments of the field-stage kernel besides the grids and deposits
 struct FieldArgs {
   Geo gn;                      // geometry after the window shift (as before it when there is none)
@@ -72,7 +90,8 @@ struct FieldArgs {
 // column's items added to the layout in use
 template <class R>
 void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, const DepositBufs<R>& dnext,
-                  const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st);
+                  const DepositBufs<R>& d0, const DepositBufs<R>& d1, FieldArgs fa, hipStream_t st,
+                  const KEvents& ev = KEvents{});
 template <class R>
 void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int fp64_rows, hipStream_t st);
 

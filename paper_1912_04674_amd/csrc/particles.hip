@@ -1454,49 +1454,49 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
 template <class R, bool M1, bool DEFER, int O, bool NT>
 static void launch_momentum_nt(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                                const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
-                               int scatter, hipStream_t st) {
+                               int scatter, hipStream_t st, const KEvents& ev) {
   if (scatter == SCAT_TILE)
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_TILE, O, NT>), dim3(grid), dim3(WG), 0, st, g, f, chi, src,
-                       dst, Ls, Ld, ccur, gscr, err);
+    launch_k(k_momentum<R, M1, DEFER, SCAT_TILE, O, NT>, dim3(grid), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
+             ccur, gscr, err);
   else if (scatter == SCAT_CELL)
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_CELL, O, NT>), dim3(grid), dim3(WG), 0, st, g, f, chi, src,
-                       dst, Ls, Ld, ccur, gscr, err);
+    launch_k(k_momentum<R, M1, DEFER, SCAT_CELL, O, NT>, dim3(grid), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
+             ccur, gscr, err);
   else
-    hipLaunchKernelGGL((k_momentum<R, M1, DEFER, SCAT_NONE, O, NT>), dim3(grid), dim3(WG), 0, st, g, f, chi, src,
-                       dst, Ls, Ld, ccur, gscr, err);
+    launch_k(k_momentum<R, M1, DEFER, SCAT_NONE, O, NT>, dim3(grid), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
+             ccur, gscr, err);
 }
 // non-temporal record access for the fused passes of large runs only
 template <class R, bool M1, bool DEFER, int O>
 static void launch_momentum_sc(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                                const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
-                               int scatter, hipStream_t st) {
+                               int scatter, hipStream_t st, const KEvents& ev) {
   if (!DEFER && g.stream_parts)
-    launch_momentum_nt<R, M1, DEFER, O, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+    launch_momentum_nt<R, M1, DEFER, O, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
   else
-    launch_momentum_nt<R, M1, DEFER, O, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+    launch_momentum_nt<R, M1, DEFER, O, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
 }
 
 // order 2 has no deferred-deposit variant (the library rejects the request)
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                      const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
-                     int scatter, hipStream_t st) {
+                     int scatter, hipStream_t st, const KEvents& ev) {
   if (grid <= 0) return;
   if (g.order == 2) {
     if (g.modes >= 2)
-      launch_momentum_sc<R, true, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, true, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
     else
-      launch_momentum_sc<R, false, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
   } else if (g.modes >= 2) {
     if (defer)
-      launch_momentum_sc<R, true, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, true, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
     else
-      launch_momentum_sc<R, true, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, true, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
   } else {
     if (defer)
-      launch_momentum_sc<R, false, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
     else
-      launch_momentum_sc<R, false, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st);
+      launch_momentum_sc<R, false, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
   }
 }
 
@@ -1508,35 +1508,35 @@ template <class R> int inject_blocks(const Geo& g) {
 template <class R, bool M1, bool DEFER, int O>
 static void launch_position_k(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P,
                               const Layout& L, int* ccount, int vacate, int count_cells, const Parts<R>& scr,
-                              int* err, int grid, const InjectArgs& inj, hipStream_t st) {
+                              int* err, int grid, const InjectArgs& inj, hipStream_t st, const KEvents& ev) {
   if (!DEFER && g.stream_parts)
-    hipLaunchKernelGGL((k_position<R, M1, DEFER, O, true>), dim3(grid + inj.blocks), dim3(WG), 0, st, g, f, d.jx,
-                       d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+    launch_k(k_position<R, M1, DEFER, O, true>, dim3(grid + inj.blocks), dim3(WG), st, ev, g, f, d.jx, d.jr, d.jx1,
+             d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
   else
-    hipLaunchKernelGGL((k_position<R, M1, DEFER, O, false>), dim3(grid + inj.blocks), dim3(WG), 0, st, g, f, d.jx,
-                       d.jr, d.jx1, d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+    launch_k(k_position<R, M1, DEFER, O, false>, dim3(grid + inj.blocks), dim3(WG), st, ev, g, f, d.jx, d.jr, d.jx1,
+             d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
 }
 
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
                      int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
-                     const InjectArgs& inj, hipStream_t st) {
+                     const InjectArgs& inj, hipStream_t st, const KEvents& ev) {
   if (grid <= 0) return;
   if (g.order == 2) {
     if (g.modes >= 2)
-      launch_position_k<R, true, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+      launch_position_k<R, true, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
     else
-      launch_position_k<R, false, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+      launch_position_k<R, false, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
   } else if (g.modes >= 2) {
     if (defer)
-      launch_position_k<R, true, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+      launch_position_k<R, true, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
     else
-      launch_position_k<R, true, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+      launch_position_k<R, true, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
   } else {
     if (defer)
-      launch_position_k<R, false, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+      launch_position_k<R, false, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
     else
-      launch_position_k<R, false, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st);
+      launch_position_k<R, false, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
   }
 }
 
@@ -1568,10 +1568,11 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
 
 #define ENVPIC_INST(R)                                                                                          \
   template void launch_momentum<R>(const Geo&, const Grids<R>&, R*, const Parts<R>&, const Parts<R>&,           \
-                                   const Layout&, const Layout&, int*, R*, int*, int, bool, int, hipStream_t);  \
+                                   const Layout&, const Layout&, int*, R*, int*, int, bool, int, hipStream_t,   \
+                                   const KEvents&);                                                             \
   template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
                                    const Layout&, int*, int, int, const Parts<R>&, int*, int, bool,             \
-                                   const InjectArgs&, hipStream_t);                                             \
+                                   const InjectArgs&, hipStream_t, const KEvents&);                             \
   template int inject_blocks<R>(const Geo&);                                                                    \
   template void launch_deposit_chi<R>(const Geo&, R*, const Parts<R>&, const Layout&, const R*, int*, int,      \
                                       hipStream_t);                                                             \
