@@ -203,15 +203,16 @@ def _oracle_rate(pyoracle, cfg, steps, threads):
             "particles": int(0.5 * (n0 + n1)), "steps": steps, "seconds": round(dt, 3)}
 
 
-def cpu_baseline(cfg, cols=256, steps=20):
+def cpu_baseline(cfg, cols=256, steps=100):
     """The FP64 oracle, as it stands, on the host's cores: the particle loops
     on 1 thread and on every core this process may use (at most 16, the host
     share of one GPU).  The headline sample is a slab of the benchmarked
     workload (its last `cols` cell columns, where the pulse is; full radius,
-    same loading) for `steps` steps; beside it, on all threads: the mode-0
-    parity workload in full (100 steps), a 256-column slab of the bandwidth
-    workload (20 steps) and one scan job per grid size for 30 of its 300
-    steps (the job's CPU latency is scaled from those)."""
+    same loading) for `steps` steps (a fifth as many on 1 thread); beside
+    it, on all threads: the mode-0 parity workload in full (100 steps), a
+    256-column slab of the bandwidth workload (20 steps) and one scan job per
+    grid size for 30 of its 300 steps (the job's CPU latency is scaled from
+    those)."""
     import pyoracle
     from inputs import C1, C3, C4_GRIDS, c4_job, scaled
     import numpy as np
@@ -219,7 +220,7 @@ def cpu_baseline(cfg, cols=256, steps=20):
     nthr = pyoracle.host_threads()
     start = cfg["nx"] - cols
     sub = scaled(cfg, nx=cols, start_col=start)
-    one = _oracle_rate(pyoracle, sub, max(4, steps // 4), 1)
+    one = _oracle_rate(pyoracle, sub, max(4, steps // 5), 1)
     many = _oracle_rate(pyoracle, sub, steps, nthr)
     others = {"c1_parity_256x32 (full, 100 steps)": _oracle_rate(pyoracle, C1, 100, nthr),
               "c3_bandwidth_4096x512 columns [1920, 2176), 20 steps":
