@@ -50,15 +50,29 @@ Sizes sizes_of(const envpic_params& p) {
   s.ntiles = s.ntxa * s.ntr;
   s.ppc = p.ppc_x * p.ppc_r * p.ppc_t;
   const long long window = (long long)p.nx * p.nr * s.ppc;
-  // one window of particles plus the columns injected between two sorts
-  s.capacity = p.capacity > 0 ? p.capacity : window + (SORT_EVERY + 1LL) * p.nr * s.ppc + 1024;
+  // one window of particles, overflow ranges for particles that change
+  // tile (1/16 of them), room for the tiles about to enter a moving window,
+  // and the columns injected until the layout is rebuilt
+  const long long column = (long long)p.nr * s.ppc;
+  s.capacity = p.capacity > 0 ? p.capacity
+                              : window + window / 16 + (long long)(ENTERING_TILES + 1) * TX * column +
+                                    (SORT_EVERY * (CELL_SORT_EVERY + 1LL) + 1) * column + 1024;
   // work-item size: about four items per compute unit (256 of them) so that
   // small runs fill the device, at most CHUNK, a multiple of WG
   const long long per = window / (4LL * 256);
   s.chunk = (int)std::max<long long>(WG, std::min<long long>(CHUNK, per / WG * WG));
+  // items: those of any layout of the tiles' particles, and those of the
+  // columns injected between two sorts (a tile sort whose overflow would
+  // need more rebuilds the layout instead)
   s.max_items = (int)(s.ntiles + s.capacity / s.chunk + SORT_EVERY * s.ntr + 16);
   s.ngrid = (size_t)s.nxa * s.pitch;
   return s;
+}
+
+// slots a rebuilt layout keeps free past the tiles' segments: the columns
+// injected until it is rebuilt again (at most one per step)
+long long slot_reserve(const envpic_params& p, const Sizes& s) {
+  return SORT_EVERY * (CELL_SORT_EVERY + 1LL) * p.nr * s.ppc;
 }
 
 int validate(const envpic_params* p) {
@@ -132,6 +146,8 @@ template <class R> struct State {
   DepositBufs<R> jf;  // filtered currents (chi unused) when the binomial filter is on
   Layout lay[2];
   int* hist;    // particles per tile at the next sort
+  int* arr;     // particles arriving from other tiles at the next (tile) sort
+  int* sort_stats;  // [incremental, rebuilt] layouts of the tile sorts
   int* ccount;  // particles per cell at the next sort ([phys col][row], as the grids)
   int* ccur;    // per-cell scatter cursors of the next sort
   int* err;
@@ -220,12 +236,18 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   for (int b = 0; b < 2; ++b) {
     Layout& L = S.lay[b];
     L.offsets = cv.take<int>((size_t)s.ntiles + 1);
+    L.ext = cv.take<int>((size_t)s.ntiles);
     L.cursor = cv.take<int>((size_t)s.ntiles);
+    L.ovb = cv.take<int>((size_t)s.ntiles);
+    L.ovn = cv.take<int>((size_t)s.ntiles);
     L.items = cv.take<int4>((size_t)s.max_items);
     L.n_items = cv.take<int>(1);
     L.fill = cv.take<int>(1);
+    L.mode = cv.take<int>(1);
   }
   S.hist = cv.take<int>((size_t)s.ntiles);
+  S.arr = cv.take<int>((size_t)s.ntiles);
+  S.sort_stats = cv.take<int>(2);
   S.ccount = cv.take<int>(ng);
   S.ccur = cv.take<int>(ng);
   S.err = cv.take<int>(1);
@@ -272,8 +294,10 @@ struct envpic_sim {
   int64_t n = 0, shift = 0;
   int stage = 0;     // next expected stage: 0 momentum, 1 envelope, 2 position, 3 field
   int cur = 0;       // particle buffer holding the current state
+  int lay = 0;       // its layout (a tile sort changes the layout, not the buffer)
   int64_t sorted_at = 0;  // step whose positions the layout of P[cur] is sorted by
   int64_t n_sorts = 0;    // sorts so far (selects tile or cell order)
+  int64_t n_cell_sorts = 0;
   bool deferred = false, deposit_done = true;
   int chi_last = 0;  // deposit buffer of the last momentum stage
   bool jf_valid = false;  // the filtered copy holds the current of the last field stage
@@ -414,6 +438,7 @@ struct envpic_sim {
   virtual int poison(int f) = 0;
   virtual int check_err() = 0;
   virtual int clear_deposits() = 0;
+  virtual int sort_counts(int64_t* incremental, int64_t* rebuilt) = 0;
 
   // the momentum stage of the next step re-sorts the particles
   // Steps between sorts: particles drift at most one cell per step, and the
@@ -424,6 +449,12 @@ struct envpic_sim {
     return p.sort_every > 0 && p.sort_every < most ? p.sort_every : most;
   }
   bool presort() const { return n + 1 - sorted_at >= sort_every(); }
+  // the kind of sort at the momentum stage of the next step (0: none);
+  // every CELL_SORT_EVERY-th sort orders the tiles by cell again
+  int next_sort() const {
+    if (!presort()) return 0;
+    return n_sorts % CELL_SORT_EVERY == 0 ? SCAT_CELL : SCAT_TILE;
+  }
   bool shift_due() const {
     return p.moving_window && (double)(n + 1) * p.dt >= (double)(shift + 1) * p.dx;
   }
@@ -538,6 +569,13 @@ template <class R> struct SimT : envpic_sim {
     int rc;
     if ((rc = hip_check(hipMemcpyAsync(S.lay[b].offsets, off.data(), off.size() * sizeof(int), hipMemcpyHostToDevice, stream), "upload offsets"))) return rc;
     if ((rc = hip_check(hipMemcpyAsync(S.lay[b].cursor, off.data(), (size_t)sz.ntiles * sizeof(int), hipMemcpyHostToDevice, stream), "upload cursor"))) return rc;
+    if ((rc = hip_check(hipMemcpyAsync(S.lay[b].ext, counts.data(), (size_t)sz.ntiles * sizeof(int), hipMemcpyHostToDevice, stream), "upload extents"))) return rc;
+    // the particles per tile, which the kernels keep current (exact for a
+    // particle upload; the first sort after loading is a cell sort, which
+    // counts them afresh)
+    if ((rc = hip_check(hipMemcpyAsync(S.hist, counts.data(), (size_t)sz.ntiles * sizeof(int), hipMemcpyHostToDevice, stream), "upload tile counts"))) return rc;
+    const int full = LAYOUT_FULL;
+    if ((rc = hip_check(hipMemcpyAsync(S.lay[b].mode, &full, sizeof(int), hipMemcpyHostToDevice, stream), "upload mode"))) return rc;
     if (ni && (rc = hip_check(hipMemcpyAsync(S.lay[b].items, items.data(), items.size() * sizeof(int4), hipMemcpyHostToDevice, stream), "upload items"))) return rc;
     if ((rc = hip_check(hipMemcpyAsync(S.lay[b].n_items, &ni, sizeof(int), hipMemcpyHostToDevice, stream), "upload n_items"))) return rc;
     if ((rc = hip_check(hipMemcpyAsync(S.lay[b].fill, &off[sz.ntiles], sizeof(int), hipMemcpyHostToDevice, stream), "upload fill"))) return rc;
@@ -559,8 +597,9 @@ template <class R> struct SimT : envpic_sim {
           const int cols = std::min(TX, p.nx - T * TX), rows = std::min(TR, p.nr - tr * TR);
           counts[(T % sz.ntxa) * sz.ntr + tr] = cols * rows * sz.ppc;
         }
-    if ((rc = upload_layout(cur, counts))) return rc;
-    if (p.profile != ENVPIC_PROFILE_NONE) launch_init_particles<R>(g, plasma(), S.parts[cur], S.lay[cur].offsets, stream);
+    lay = cur;
+    if ((rc = upload_layout(lay, counts))) return rc;
+    if (p.profile != ENVPIC_PROFILE_NONE) launch_init_particles<R>(g, plasma(), S.parts[cur], S.lay[lay].offsets, stream);
     launch_init_envelope<R>(g, S.grids, laser(), fp64_rows ? 1 : 0, stream);
     if ((rc = launched("init kernels"))) return rc;
     sorted_at = n;  // the particles of P[cur] sit in their tiles
@@ -585,6 +624,15 @@ template <class R> struct SimT : envpic_sim {
     return hip_check(hipStreamSynchronize(stream), "clear deposits");
   }
 
+  int sort_counts(int64_t* incremental, int64_t* rebuilt) override {
+    int c[2] = {0, 0};
+    int rc = hip_check(hipMemcpyAsync(c, S.sort_stats, sizeof c, hipMemcpyDeviceToHost, stream), "sort counts");
+    if (rc || (rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
+    *incremental = c[0];
+    *rebuilt = c[1];
+    return ENVPIC_OK;
+  }
+
   int check_err() override {
     int e = 0;
     int rc = hip_check(hipMemcpyAsync(&e, S.err, sizeof(int), hipMemcpyDeviceToHost, stream), "read error word");
@@ -592,6 +640,7 @@ template <class R> struct SimT : envpic_sim {
     if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
     if (e & ERR_CAPACITY) return fail(ENVPIC_ENOMEM, "particle capacity exceeded");
     if (e & ERR_ITEMS) return fail(ENVPIC_ENOMEM, "work-item list overflow");
+    if (e & ERR_LAYOUT) return fail(ENVPIC_EDEVICE, "a sort met more particles changing tile than its scan counted");
     if (e & ERR_HALO) return fail(ENVPIC_ENUMERIC, "a particle moved beyond its tile halo (non-finite or super-luminal state)");
     return ENVPIC_OK;
   }
@@ -603,14 +652,19 @@ template <class R> struct SimT : envpic_sim {
     // re-sort when the particles have had sort_every() steps to drift from
     // their tiles; in between, p is updated in place
     const bool scatter = n - sorted_at >= sort_every();
-    // every CELL_SORT_EVERY-th sort orders the tiles by cell again
+    // every CELL_SORT_EVERY-th sort orders the tiles by cell again (into the
+    // other buffer); the others move only the particles that changed tile
     const int mode = !scatter ? SCAT_NONE : (n_sorts % CELL_SORT_EVERY == 0 ? SCAT_CELL : SCAT_TILE);
     const KEvents ev = tick_events();
-    launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[cur], S.lay[1 - cur], S.ccur,
+    launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[lay], S.lay[1 - lay], S.ccur,
                        S.scr.w, S.err, sz.max_items, defer, mode, stream, ev);
     tick_end(0, ev);
     if (scatter) {
-      cur = 1 - cur;
+      if (mode == SCAT_CELL) {
+        cur = 1 - cur;
+        n_cell_sorts += 1;
+      }
+      lay = 1 - lay;
       sorted_at = n;
       n_sorts += 1;
     }
@@ -626,10 +680,10 @@ template <class R> struct SimT : envpic_sim {
     const int d = (int)(n & 1);
     if (what == ENVPIC_CHI) {
       if (stage != 1 || !deferred || deposit_done) return fail(ENVPIC_EORDER, "chi deposit needs a deferred momentum stage");
-      launch_deposit_chi<R>(g, S.dep[d].chi, S.parts[cur], S.lay[cur], S.scr.w, S.err, sz.max_items, stream);
+      launch_deposit_chi<R>(g, S.dep[d].chi, S.parts[cur], S.lay[lay], S.scr.w, S.err, sz.max_items, stream);
     } else if (what == ENVPIC_J) {
       if (stage != 3 || !deferred || deposit_done) return fail(ENVPIC_EORDER, "J deposit needs a deferred position stage");
-      launch_deposit_J<R>(g, S.dep[d], S.parts[cur], S.lay[cur], shift_due() ? 1 : 0, S.scr, S.err, sz.max_items, stream);
+      launch_deposit_J<R>(g, S.dep[d], S.parts[cur], S.lay[lay], shift_due() ? 1 : 0, S.scr, S.err, sz.max_items, stream);
     } else {
       return fail(ENVPIC_EINVAL, "project_chi_J: what must be ENVPIC_CHI or ENVPIC_J");
     }
@@ -665,8 +719,9 @@ template <class R> struct SimT : envpic_sim {
     inj.pending = S.pending;
     inj.blocks = (shifting && p.profile != ENVPIC_PROFILE_NONE) ? inject_blocks<R>(inj.gn) : 0;
     const KEvents ev = tick_events();
-    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[cur], S.ccount, shifting ? 1 : 0,
-                       presort() ? 1 : 0, S.scr, S.err, sz.max_items, defer, inj, stream, ev);
+    const SortCounts sc{next_sort(), S.ccount, S.hist, S.arr};
+    launch_position<R>(g, S.grids, S.dep[n & 1], S.parts[cur], S.lay[lay], sc, shifting ? 1 : 0, S.scr, S.err,
+                       sz.max_items, defer, inj, stream, ev);
     tick_end(2, ev);
     stage = 3;
     deferred = defer;
@@ -678,25 +733,29 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 3 || !deposit_done) return fail(ENVPIC_EORDER, "field stage out of order");
     const KEvents ev = tick_events();
     const Geo g = geo();
-    const bool shifting = shift_due(), pre = presort();
+    const bool shifting = shift_due();
+    const int pre = next_sort();
     if (shifting) shift += 1;
     const Geo gn = geo();
     FieldArgs fa{};
     fa.gn = gn;
     fa.shifting = shifting ? 1 : 0;
     fa.fp64_rows = fp64_rows ? 1 : 0;
-    fa.presort = pre ? 1 : 0;
+    fa.presort = pre;
     fa.ccount = S.ccount;
     fa.ccur = S.ccur;
     fa.hist = S.hist;
-    fa.out = S.lay[1 - cur];
+    fa.arr = S.arr;
+    fa.in = S.lay[lay];
+    fa.out = S.lay[1 - lay];
     fa.capacity = sz.capacity;
     fa.inj_max = p.nr * sz.ppc;
+    fa.reserve = slot_reserve(p, sz);
+    fa.entering = (p.moving_window && p.profile != ENVPIC_PROFILE_NONE) ? ENTERING_TILES : 0;
     fa.max_items = sz.max_items;
-    fa.bump_items = S.lay[cur].n_items;
-    fa.bump_fill = S.lay[cur].fill;
     fa.pending = S.pending;
     fa.err = S.err;
+    fa.stats = S.sort_stats;
     DepositBufs<R> din = S.dep[n & 1];
     if (p.filter_passes > 0) {
       // the field update reads the filtered current
@@ -842,23 +901,28 @@ template <class R> struct SimT : envpic_sim {
     return hip_check(hipStreamSynchronize(stream), "set_field sync");
   }
 
-  // slots of P[cur] covered by work items
-  int used_slots(int& used) {
+  // the slots of P[cur] that work items cover (the free slots of the
+  // tiles' segments hold stale records): [0, used) and a flag per slot
+  int used_slots(int& used, std::vector<char>& covered) {
     int ni = 0;
-    int rc = hip_check(hipMemcpyAsync(&ni, S.lay[cur].n_items, sizeof(int), hipMemcpyDeviceToHost, stream), "n_items");
+    int rc = hip_check(hipMemcpyAsync(&ni, S.lay[lay].n_items, sizeof(int), hipMemcpyDeviceToHost, stream), "n_items");
     if (rc) return rc;
     if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
     std::vector<int4> items(ni);
-    if (ni && (rc = hip_check(hipMemcpyAsync(items.data(), S.lay[cur].items, ni * sizeof(int4), hipMemcpyDeviceToHost, stream), "items"))) return rc;
+    if (ni && (rc = hip_check(hipMemcpyAsync(items.data(), S.lay[lay].items, ni * sizeof(int4), hipMemcpyDeviceToHost, stream), "items"))) return rc;
     if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
     used = 0;
     for (const int4& it : items) used = std::max(used, it.y + it.z);
+    covered.assign(used, 0);
+    for (const int4& it : items)
+      for (int k = it.y; k < it.y + it.z; ++k) covered[k] = 1;
     return ENVPIC_OK;
   }
 
   int get_particles(std::vector<double>* cols, std::vector<uint32_t>* ids) override {
     int used = 0;
-    int rc = used_slots(used);
+    std::vector<char> covered;
+    int rc = used_slots(used, covered);
     if (rc) return rc;
     const Parts<R>& P = S.parts[cur];
     std::vector<unsigned> cell(used);
@@ -876,7 +940,7 @@ template <class R> struct SimT : envpic_sim {
     if ((rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
     std::vector<int> order;
     for (int k = 0; k < used; ++k)
-      if (cell[k] != kDead) order.push_back(k);
+      if (covered[k] && cell[k] != kDead) order.push_back(k);
     std::sort(order.begin(), order.end(), [&](int u, int v) { return id[u] < id[v]; });
     for (int c = 0; c < 7; ++c) cols[c].resize(order.size());
     ids->resize(order.size());
@@ -943,7 +1007,8 @@ template <class R> struct SimT : envpic_sim {
       wmax = std::max(wmax, std::fabs((double)h[6][d]));
     }
     int rc;
-    if ((rc = upload_layout(cur, counts))) return rc;
+    lay = cur;
+    if ((rc = upload_layout(lay, counts))) return rc;
     Parts<R>& P = S.parts[cur];
     R* dst[7] = {P.fx, P.fr, P.th, P.px, P.py, P.pz, P.w};
     if (np) {
@@ -958,7 +1023,7 @@ template <class R> struct SimT : envpic_sim {
 
   int diagnostics(double* out) override {
     const Geo g = geo();
-    launch_diag<R>(g, S.parts[cur], S.lay[cur], S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0, S.diag_scratch,
+    launch_diag<R>(g, S.parts[cur], S.lay[lay], S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0, S.diag_scratch,
                    S.diag_out, stream);
     int rc = launched("diagnostics");
     if (rc) return rc;
@@ -973,7 +1038,7 @@ template <class R> struct SimT : envpic_sim {
     if (!diag_static) return fail(ENVPIC_EDEVICE, "the static diagnostics scratch is not available on this device");
     if ((size_t)diag_scratch_doubles() > diag_static_doubles)
       return fail(ENVPIC_EINVAL, "diagnostics partial sums exceed the static scratch");
-    launch_diag<R>(geo(), S.parts[cur], S.lay[cur], S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0, diag_static,
+    launch_diag<R>(geo(), S.parts[cur], S.lay[lay], S.grids, S.dep[chi_last].chi, fp64_rows ? 1 : 0, diag_static,
                    dev_out, stream);
     return launched("diagnostics (static scratch)");
   }
@@ -987,7 +1052,7 @@ template <class R> struct SimT : envpic_sim {
     // fixed-point histogram: a power of two with capacity * w_max * scale <= 2^61
     const double wb = std::max(wmax, 1e-300) * (double)sz.capacity;
     a.scale = std::ldexp(1.0, std::min(1000, (int)std::floor(std::log2(std::ldexp(1.0, 61) / wb))));
-    launch_beam<R>(geo(), S.parts[cur], S.lay[cur], sz.max_items, a, S.beam, stream);
+    launch_beam<R>(geo(), S.parts[cur], S.lay[lay], sz.max_items, a, S.beam, stream);
     int rc = launched("beam diagnostics");
     if (rc) return rc;
     if ((rc = hip_check(hipMemcpyAsync(out, S.beam.out, ENVPIC_NBEAM * sizeof(double), hipMemcpyDeviceToHost, stream), "beam read"))) return rc;
@@ -1000,7 +1065,7 @@ template <class R> struct SimT : envpic_sim {
             double* resid) override {
     int it = 0;
     double res = 0.0;
-    if (bunch_solve<R>(geo(), S.parts[cur], S.lay[cur], sz.max_items, S.grids, id_lo, id_hi, beta, tol, max_iter,
+    if (bunch_solve<R>(geo(), S.parts[cur], S.lay[lay], sz.max_items, S.grids, id_lo, id_hi, beta, tol, max_iter,
                        S.cg, stream, &it, &res)) {
       const int rc = launched("bunch fields");
       return rc ? rc : fail(ENVPIC_EDEVICE, "bunch fields: residual transfer failed");
@@ -1198,6 +1263,12 @@ int envpic_get_field(const envpic_sim* s, int field, double* out) {
 int envpic_set_field(envpic_sim* s, int field, const double* in) {
   if (!s || !in) return fail(ENVPIC_EINVAL, "NULL argument");
   return s->set_field(field, in);
+}
+
+int envpic_sort_stats(const envpic_sim* s, int64_t* out) {
+  if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
+  out[0] = s->n_cell_sorts;
+  return const_cast<envpic_sim*>(s)->sort_counts(&out[1], &out[2]);
 }
 
 int envpic_state(const envpic_sim* s, int64_t* n, int64_t* shift, int64_t* n_particles) {

@@ -7,8 +7,14 @@
 //     no data;
 //   * particles: structure of arrays, cell word (lab column, radial row),
 //     offsets in the cell along x and r, azimuth, momenta, weight (R), id
-//     (uint32); two buffers ping-pong through the counting sort by tile,
-//     which runs every third step (every second with quadratic shapes);
+//     (uint32), grouped by tile: each tile owns a segment of a buffer (the
+//     tiles a moving window is about to enter, room for a full tile).  The
+//     sort by tile runs every third step (every second with quadratic
+//     shapes); it moves only the particles that changed tile (into free
+//     slots of their new tile's segment, or into an overflow range of that
+//     tile past all segments), and every CELL_SORT_EVERY-th sort rebuilds
+//     the whole layout, ordered by cell, in the second buffer (the two
+//     buffers ping-pong at those sorts);
 //   * the envelope rows j = 0, 1 additionally in FP64 (FP32 mode).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -33,10 +39,21 @@ constexpr int LN = LX * LR; // nodes of an LDS tile region
 // SORT_EVERY on each side): the per-cell counts of a work item live here
 constexpr int CR = TX + 2 * SORT_EVERY;
 constexpr int CRN = CR * CR;
-// how a sort moves the particles: by tile keeping their order, or by cell
-// with the placement of loading (every CELL_SORT_EVERY-th sort)
+// how a sort moves the particles: by tile (only the particles that changed
+// tile move; if the layout has no room for them, every particle is
+// scattered into the other buffer and copied back), or by cell with the
+// placement of loading (every CELL_SORT_EVERY-th sort, into the other
+// buffer)
 constexpr int SCAT_NONE = 0, SCAT_TILE = 1, SCAT_CELL = 2;
 constexpr int CELL_SORT_EVERY = 8;
+// the layout a scan produced for a tile sort: incremental, or every particle
+// scattered (not enough free slots, overflow room or work items)
+constexpr int LAYOUT_MOVE = 0, LAYOUT_FULL = 1;
+// Tile columns ahead of a moving window whose segments get room for a full
+// tile when the layout is rebuilt (the window enters at most one column per
+// step, SORT_EVERY * CELL_SORT_EVERY steps between rebuilds), with the tile
+// column the window's front is in
+constexpr int ENTERING_TILES = (SORT_EVERY * CELL_SORT_EVERY + TX - 1) / TX + 1;
 constexpr int WG = 512;     // work-group size of the particle kernels
 constexpr int CHUNK = 4096; // largest work item (particles); small runs use smaller items
 // particle buffers at least this large (one buffer's records) stream past the
@@ -59,6 +76,7 @@ __host__ __device__ inline int cell_jr(unsigned c) { return (int)(c & JR_MASK); 
 constexpr int ERR_HALO = 1;      // a particle left the LDS halo of its tile
 constexpr int ERR_CAPACITY = 2;  // particle buffer capacity exceeded
 constexpr int ERR_ITEMS = 4;     // work-item list overflow
+constexpr int ERR_LAYOUT = 8;    // a sort met more arrivals at a tile than its scan counted
 
 template <class R> struct cplx_of;
 template <> struct cplx_of<float> { using type = float2; };
@@ -109,12 +127,21 @@ template <class R> struct Grids {
   C *ex1_n, *er1_n, *et1_n, *bx1_n, *br1_n, *bt1_n;
 };
 
+// A layout of one particle buffer.  Tile t owns the segment
+// [offsets[t], offsets[t + 1]) and uses its first ext[t] slots (live or
+// removed particles); slots from offsets[ntiles] to *fill hold the columns
+// injected since the layout was built and particles that found no room in
+// their tile's segment (work items of their own, keyed by their tile).
 struct Layout {
   int* offsets;  // [ntiles + 1]
-  int* cursor;   // [ntiles]
+  int* ext;      // [ntiles] slots in use at the start of each segment
+  int* cursor;   // [ntiles] scatter cursors (full) or arrival tickets (incremental)
+  int* ovb;      // [ntiles] first overflow slot of each tile's arrivals (incremental)
+  int* ovn;      // [ntiles] arrivals of each tile that go to its overflow range (incremental)
   int4* items;   // {key, start, count, 0}
   int* n_items;  // scalar
   int* fill;     // scalar: end of the used slots (injected columns are appended here)
+  int* mode;     // scalar: LAYOUT_MOVE or LAYOUT_FULL (tile sorts)
 };
 
 struct Plasma {

@@ -357,13 +357,8 @@ __global__ __launch_bounds__(MW_T) void k_field(Geo g, Grids<R> f, DepositBufs<R
   __shared__ MwShared<R, M1> sm;
   __shared__ int s_a[MW_T];
   const int blk = blockIdx.x;
-  if (!fa.presort && blk == 0 && threadIdx.x == 0 && fa.pending[0] != 0) {
-    // an injected column's items and slots join the layout in use
-    *fa.bump_items += fa.pending[0];
-    *fa.bump_fill += fa.pending[1];
-    fa.pending[0] = 0;
-    fa.pending[1] = 0;
-  }
+  // an injected column's items and slots join the layout in use
+  if (!fa.presort && blk == 0) bump_pending(fa.gn, fa.in, fa.pending);
   if (blk < fa.nb_mw) {
     maxwell_tile<R, M1>(g, f, din, dnext, (blk / fa.nbx_mw) * MW_TI, (blk % fa.nbx_mw) * MW_TJ, fa.shifting != 0, sm);
   } else if (blk < fa.nb_mw + fa.nb_win) {
@@ -376,12 +371,19 @@ __global__ __launch_bounds__(MW_T) void k_field(Geo g, Grids<R> f, DepositBufs<R
 }
 
 // before a sort: the injected column's items and slots added to the layout
-// in use, then the scan of all tile totals into the next layout (one group)
+// in use, then the next layout (one group): rebuilt from the tile totals
+// before a cell sort, from the arrivals before a tile sort
 constexpr int SCAN_T = 1024;
 __global__ __launch_bounds__(SCAN_T) void k_layout_scan(FieldArgs fa) {
-  __shared__ int s_a[SCAN_T], s_b[SCAN_T];
-  layout_scan<SCAN_T>(fa.gn, fa.hist, fa.out, fa.capacity, fa.inj_max, fa.max_items, fa.bump_items, fa.bump_fill,
-                      fa.pending, fa.err, fa.presort, s_a, s_b);
+  __shared__ int s_w[SCAN_T / 64];
+  bump_pending(fa.gn, fa.in, fa.pending);
+  __syncthreads();
+  if (fa.presort == SCAT_CELL)
+    full_layout<SCAN_T>(fa.gn, fa.hist, fa.out, fa.capacity, fa.inj_max, fa.reserve, fa.entering, fa.max_items,
+                        fa.err, s_w);
+  else
+    move_layout<SCAN_T>(fa.gn, fa.hist, fa.arr, fa.in, fa.out, fa.capacity, fa.inj_max, fa.reserve, fa.entering,
+                        fa.max_items, fa.err, fa.stats, s_w);
 }
 
 // ---------------------------------------------------- initial envelope --
@@ -444,7 +446,7 @@ void launch_field(const Geo& g, const Grids<R>& f, const DepositBufs<R>& din, co
   fa.nbx_mw = (g.nr + 1 + MW_TJ - 1) / MW_TJ;
   fa.nb_mw = fa.nbx_mw * ((g.nx + 1 + MW_TI - 1) / MW_TI);
   fa.nb_win = fa.shifting ? (g.nr + 1 + MW_T - 1) / MW_T : 0;
-  const int nb_cs = fa.presort ? (g.ntiles + 1) / 2 : 0;
+  const int nb_cs = fa.presort == SCAT_CELL ? (g.ntiles + 1) / 2 : 0;
   const int grid = fa.nb_mw + fa.nb_win + nb_cs;
   // the stage's stop event goes on its last kernel
   const KEvents ev_field{ev.start, fa.presort ? nullptr : ev.stop};

@@ -45,10 +45,19 @@ struct InjectArgs {
   int* pending;  // items and slots appended, added to the layout by the field stage
   int blocks;
 };
-// count_cells: add the particles' new cells into ccount (before a sort)
+// What a position pass counts for the sort at the next step: nothing
+// (mode 0); the particles per cell of x^{n+1} into ccount (SCAT_CELL); or
+// the particles per tile into hist and the arrivals (particles of another
+// tile's work item) per tile into arr (SCAT_TILE).
+struct SortCounts {
+  int mode;
+  int* ccount;
+  int* hist;
+  int* arr;
+};
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
-                     int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
+                     const SortCounts& sc, int vacate, const Parts<R>& scr, int* err, int grid, bool defer,
                      const InjectArgs& inj, hipStream_t st, const KEvents& ev = KEvents{});
 template <class R> int inject_blocks(const Geo& g);
 template <class R>
@@ -71,18 +80,22 @@ void launch_filter(const Geo& g, const DepositBufs<R>& din, const DepositBufs<R>
 // arguments of the field-stage kernel besides the grids and deposits
 struct FieldArgs {
   Geo gn;                      // geometry after the window shift (as before it when there is none)
-  int shifting, fp64_rows, presort;
+  int shifting, fp64_rows;
+  int presort;                 // before a sort: 0 none, SCAT_CELL (cell scans, rebuilt layout), SCAT_TILE (arrivals)
   int nb_mw, nbx_mw, nb_win;   // work-group roles (set by the launcher)
   int* ccount;                 // per-cell counts -> cursors (ccur), tile totals (hist)
   int* ccur;
-  int* hist;
+  int* hist;                   // particles per tile after the sort
+  int* arr;                    // arrivals per tile (tile sorts)
+  Layout in;                   // the layout in use
   Layout out;                  // the next layout
   long long capacity;
+  long long reserve;           // slots kept free past the segments when a layout is rebuilt
+  int entering;                // tile columns ahead of the window given a full tile of slots when it is rebuilt
   int inj_max, max_items;
-  int* bump_items;             // the layout in use: items and fill raised by an injection
-  int* bump_fill;
   int* pending;
   int* err;
+  int* stats;                  // [incremental, rebuilt] tile-sort layouts
 };
 // E^{n+1}, B^{n+3/2}, Bbar^{n+1} into the second E/B copies (the caller
 // swaps them), the next deposits cleared, the window's column resets (if

@@ -329,6 +329,12 @@ __device__ inline int item_of(int b, int n) {
   return ((q / XG) * XCDS + x) * XG + (q - (q / XG) * XG);
 }
 
+// sum over the 64 lanes of a wavefront (every lane active)
+__device__ inline int wave_sum_i(int v) {
+  for (int m = 32; m >= 1; m >>= 1) v += __shfl_xor(v, m, 64);
+  return v;
+}
+
 // Rank of this lane among the lanes of its wavefront with the same slot
 // (slot < 0: none), added to a counter per slot with one LDS atomic per
 // distinct slot in the wavefront.  The lanes of a wavefront mostly share
@@ -353,12 +359,18 @@ __device__ inline int wave_slot_rank(int slot, int* counters) {
   return rank;
 }
 
-// SCAT: SCAT_NONE updates p in place and keeps the layout; otherwise every
-// particle moves into the next layout (the tiles of x^n).  SCAT_TILE keeps
-// the particles' relative order (coalesced writes); SCAT_CELL orders each
-// tile by cell and places every work item as at loading, so that the lanes
-// of a wavefront hold particles of distinct cells again (the deposits'
-// LDS atomics do not collide), at the price of strided writes.
+// SCAT: SCAT_NONE updates p in place and keeps the layout.  SCAT_TILE
+// re-sorts by tile into the next layout (the tiles of x^n), as its scan
+// made it: incrementally (LAYOUT_MOVE: a particle that stays in its tile
+// keeps its slot and has p updated in place; one that changed tile is
+// written, whole, to a free slot of its new tile's segment or to that
+// tile's overflow range, and its old slot is marked removed), or, when the
+// scan found no room (LAYOUT_FULL), every particle is written into the other
+// buffer keeping the particles' relative order (coalesced writes), from where
+// k_settle copies the layout back.  SCAT_CELL orders each tile by cell and
+// places every work item as at loading, so that the lanes of a wavefront
+// hold particles of distinct cells again (the deposits' LDS atomics do not
+// collide), at the price of strided writes.
 // O: particle shape order (1 linear, 2 quadratic; order 2 re-sorts every
 // second step, so its wider stencil stays inside the same halo).
 // Waves per SIMD the compiler must allow: the FP32 linear in-place pass fits
@@ -457,6 +469,11 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
   // ---- destination (tile of the 3 x 3 neighbourhood, or cell) and rank
   // of each particle, kept in registers (the loops over a thread's
   // particles are unrolled).  Without the scatter only the live flag is kept.
+  // An incremental tile sort ranks the particles that change tile only.
+  const bool move = SCAT == SCAT_TILE && *Ld.mode == LAYOUT_MOVE;
+  // the particles of an item past the segments all join their tiles' segments
+  const bool fill_item = start >= Ls.offsets[g.ntiles];
+  constexpr int STAY = 1 << 30;  // slot_rank of a particle that keeps its slot
   int slot_rank[PPT];
   bool bad = false;
 #pragma unroll
@@ -471,6 +488,10 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
           const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
           const int dtr = clampi(cell_jr(cw) / TR - q.tcr, -1, 1, bad);
           tslot = (dtx + 1) * 3 + (dtr + 1);
+          if (move && tslot == 4 && !fill_item) {
+            slot_rank[u] = STAY;
+            tslot = -1;
+          }
         } else if (SCAT == SCAT_CELL) {
           const int sx = clampi(cell_ix(cw) - (q.T * TX - SORT_EVERY), 0, CR - 1, bad);
           const int sr = clampi(cell_jr(cw) - (q.tcr * TR - SORT_EVERY), 0, CR - 1, bad);
@@ -488,7 +509,9 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
   }
   __syncthreads();
   // one reservation per destination tile, or per destination cell (its
-  // slots in cell order)
+  // slots in cell order).  An incremental sort reserves arrival tickets and
+  // keeps, per destination, where its free slots and overflow range start
+  // and how many each holds.
   if (SCAT == SCAT_TILE) {
     if (threadIdx.x < 9) {
       const int c = sm.ccell[threadIdx.x];
@@ -497,7 +520,19 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
         if (tx2 < 0) tx2 += g.ntxa;
         if (tx2 >= g.ntxa) tx2 -= g.ntxa;
         const int tr2 = q.tcr + threadIdx.x % 3 - 1;
-        sm.ccell[threadIdx.x] = atomicAdd(&Ld.cursor[tx2 * g.ntr + tr2], c);
+        const int key = tx2 * g.ntr + tr2;
+        if (tr2 < 0 || tr2 >= g.ntr) {
+          sm.ccell[threadIdx.x] = -1;  // no cell lies there: its particles are flagged, not written
+        } else {
+          sm.ccell[threadIdx.x] = atomicAdd(&Ld.cursor[key], c);
+        }
+        if (move && sm.ccell[threadIdx.x] >= 0) {
+          int* pl = &sm.ccell[9 + 4 * threadIdx.x];
+          pl[0] = Ls.offsets[key] + Ls.ext[key];
+          pl[1] = Ld.ext[key] - Ls.ext[key];
+          pl[2] = Ld.ovb[key];
+          pl[3] = Ld.ovn[key];
+        }
       }
     }
     __syncthreads();
@@ -515,14 +550,31 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
   }
 
   // ---- gather, push, deposit, scatter
+  bool lost = false;
 #pragma unroll
   for (int u = 0; u < PPT; ++u) {
     if (slot_rank[u] < 0) continue;
     const int p = start + threadIdx.x + u * WG;
     const unsigned cw = pld<NT>(&src.cell[p]);  // its second read (the first above)
     int d = p;
-    if (SCAT == SCAT_TILE) {
-      d = sm.ccell[slot_rank[u] >> 16] + (slot_rank[u] & 0xFFFF);
+    const bool stay = SCAT == SCAT_TILE && slot_rank[u] == STAY;
+    if (SCAT == SCAT_TILE && !stay) {
+      const int sl = slot_rank[u] >> 16;
+      if (sm.ccell[sl] < 0) {
+        bad = true;
+        continue;
+      }
+      const int tk = sm.ccell[sl] + (slot_rank[u] & 0xFFFF);
+      d = tk;
+      if (move) {
+        // ticket tk of the destination: its free slots, then its overflow
+        const int* pl = &sm.ccell[9 + 4 * sl];
+        d = tk < pl[1] ? pl[0] + tk : (tk - pl[1] < pl[3] ? pl[2] + tk - pl[1] : -1);
+        if (d < 0) {  // more arrivals than the scan counted: never written
+          lost = true;
+          continue;
+        }
+      }
       if ((long long)d >= g.cap) {  // the scan has flagged the overflow
         bad = true;
         continue;
@@ -533,7 +585,7 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
       // placement inside its work item (as at loading)
       const int r = sm.ccell[slot_rank[u] >> 16] + (slot_rank[u] & 0xFFFF);
       const int key = tile_key(g, cell_ix(cw), cell_jr(cw));
-      const int off = Ld.offsets[key], v = Ld.offsets[key + 1] - off;
+      const int off = Ld.offsets[key], v = Ld.ext[key];
       if (r >= v) {  // counts and particles disagree: flagged, never written
         bad = true;
         continue;
@@ -649,16 +701,20 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
           Acc0<R>::add_prod(&sm.chi[(Px.i + aa) * RL + Pr.i + bb], wa, (double)(bb ? Pr.b : Pr.a));
       }
     }
-    if (SCAT != SCAT_NONE) {
-      pst<NT>(&dst.cell[d], cw);
-      pst<NT>(&dst.fx[d], fx);
-      pst<NT>(&dst.fr[d], fr);
-      pst<NT>(&dst.th[d], th);
-      pst<NT>(&dst.px[d], pv[0]);
-      pst<NT>(&dst.py[d], pv[1]);
-      pst<NT>(&dst.pz[d], pv[2]);
-      pst<NT>(&dst.w[d], w);
-      pst<NT>(&dst.id[d], pld<NT>(&src.id[p]));
+    if (SCAT != SCAT_NONE && !stay) {
+      // an incremental sort writes within the same buffer, into slots no
+      // work item of this pass reads (free or overflow slots)
+      const Parts<R>& out = move ? src : dst;
+      pst<NT>(&out.cell[d], cw);
+      pst<NT>(&out.fx[d], fx);
+      pst<NT>(&out.fr[d], fr);
+      pst<NT>(&out.th[d], th);
+      pst<NT>(&out.px[d], pv[0]);
+      pst<NT>(&out.py[d], pv[1]);
+      pst<NT>(&out.pz[d], pv[2]);
+      pst<NT>(&out.w[d], w);
+      pst<NT>(&out.id[d], pld<NT>(&src.id[p]));
+      if (move && !fill_item) src.cell[p] = kDead;  // its old slot
     } else {
       pst<NT>(&src.px[p], pv[0]);
       pst<NT>(&src.py[p], pv[1]);
@@ -666,6 +722,7 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
     }
   }
   if (bad) atomicOr(err, ERR_HALO);
+  if (lost) atomicOr(err, ERR_LAYOUT);
   if (DEFER) return;
   __syncthreads();
   for (int k = threadIdx.x; k < RN; k += WG) {
@@ -707,7 +764,8 @@ template <class R, bool M1> struct SmemPos {
   typename Acc0<R>::T jx[LN], jr[LN];
   Acc1Grid<R, M1 ? LN : 1> jx1, jr1, jt1;
   R iax[LR], iar[LR], ivn[LR], ivh[LR];
-  int ccell[CRN];  // before a sort: particles per cell of x^{n+1}
+  int ccell[CRN];  // before a cell sort: particles per cell of x^{n+1}
+  int tcnt[11];    // per-tile counts of the work item (flush_tiles)
 };
 
 // one particle's move: old and new cells/offsets, transverse displacement
@@ -1051,6 +1109,7 @@ __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
     }
   }
   for (int k = threadIdx.x; k < CRN; k += WG) sm.ccell[k] = 0;
+  if (threadIdx.x < 11) sm.tcnt[threadIdx.x] = 0;
 }
 
 // a + sg b of two mode-1 accumulator words (exact for the fixed point)
@@ -1136,6 +1195,38 @@ __device__ inline void flush_cells(const int* cc, const Region& q, const Geo& g,
   }
 }
 
+// The per-tile counts of a work item, t[d] for d = 3 (dx + 1) + (dr + 1)
+// the particles that moved to the neighbouring tile (dx, dr) (counted
+// before a tile sort), t[9] the particles removed, t[10] the live ones at
+// the start of a fill item.  hist (particles per tile, kept current from
+// step to step) loses the removed and moved ones and gains the moved ones
+// at their new tiles; before a tile sort, arr gains the moved ones, and
+// every particle of a fill item that stays in its tile.
+__device__ inline void flush_tiles(const int* t, const Region& q, const Geo& g, const SortCounts& sc, bool fill_item) {
+  if (threadIdx.x >= 9) return;
+  const int d = threadIdx.x;
+  int v = t[d];
+  if (d == 4) {
+    int moved = 0;
+    for (int e = 0; e < 9; ++e) moved += e == 4 ? 0 : t[e];
+    const int key = q.tcx * g.ntr + q.tcr;
+    if (t[9] + moved != 0) atomicAdd(&sc.hist[key], -(t[9] + moved));
+    if (sc.mode == SCAT_TILE && fill_item) {
+      const int stay = t[10] - t[9] - moved;
+      if (stay != 0) atomicAdd(&sc.arr[key], stay);
+    }
+    return;
+  }
+  if (v == 0) return;
+  int tx = q.tcx + d / 3 - 1;
+  if (tx < 0) tx += g.ntxa;
+  if (tx >= g.ntxa) tx -= g.ntxa;
+  const int tr = q.tcr + d % 3 - 1;
+  if (tr < 0 || tr >= g.ntr) return;  // (no cell lies there)
+  atomicAdd(&sc.hist[tx * g.ntr + tr], v);
+  atomicAdd(&sc.arr[tx * g.ntr + tr], v);
+}
+
 // ============================================== loading / injection ==
 // Plasma of lab cell column `col`, radial cell j: regular in x and r, one
 // SplitMix64 angle per cell with equally spaced angles inside the cell,
@@ -1177,66 +1268,102 @@ __device__ inline int load_particle(const Geo& g, const Plasma& pl, Parts<R> P, 
 }
 
 // One work group (WG threads, group index blk) of the injection: the
-// plasma of lab column gn.shift + nx - 1 appended at the layout's fill
-// pointer, tile by tile, with one work item per tile; s_cnt holds WG + 1 ints.
+// plasma of lab column gn.shift + nx - 1, tile by tile, with one work item
+// per tile.  A row tile goes to the end of its tile's segment when the free
+// slots hold it, else past the used slots (after the row tiles before it
+// that went there); every group of the injection finds the same placement
+// (the layout does not change during the pass).  s_cnt holds WG + 1 ints,
+// s_base ntr + 1.  The field stage adds the items to the layout (and their
+// slots to the segments or the fill pointer).
 template <class R>
-__device__ void inject_block(const InjectArgs& ia, Parts<R> P, const Layout& L, int* __restrict__ ccount,
-                             int count_cells, int* err, int blk, int* s_cnt) {
+__device__ void inject_block(const InjectArgs& ia, Parts<R> P, const Layout& L, const SortCounts& sc, int* err,
+                             int blk, int* s_cnt, int* s_base) {
   const Geo& g = ia.gn;
   const long long col = g.shift + g.nx - 1;
   const int ppc = g.ppc_x * g.ppc_r * g.ppc_t;
   const int total = *L.fill;  // end of the used slots
   const int base_items = *L.n_items;
+  const int seg_end = L.offsets[g.ntiles];
   if ((long long)total + (long long)g.nr * ppc > ia.capacity || base_items + g.ntr > ia.max_items || col > COL_MAX) {
     if (blk == 0 && threadIdx.x == 0) atomicOr(err, ERR_CAPACITY);
     return;
   }
+  // first slot of each row tile: its segment's end (>= 0) or, for now, the
+  // negated slot count of a row tile that goes past the used slots
+  for (int t = threadIdx.x; t < g.ntr; t += WG) {
+    const int key = tile_key(g, col, t * TR), n = min(TR, g.nr - t * TR) * ppc;
+    const int off = L.offsets[key], e = L.ext[key];
+    s_base[t] = e + n <= L.offsets[key + 1] - off ? off + e : -n;
+  }
+  for (int k = threadIdx.x; k < WG + 1; k += WG) s_cnt[k] = 0;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int fill = total;
+    for (int t = 0; t < g.ntr; ++t)
+      if (s_base[t] < 0) {
+        const int n = -s_base[t];
+        s_base[t] = fill;
+        fill += n;
+      }
+    s_base[g.ntr] = fill - total;  // slots past the used ones
+  }
+  __syncthreads();
   // live particles per cell (one cell = ppc consecutive threads), counted in
   // LDS first: a group spans WG / ppc + 1 rows at most
   const int idx = blk * WG + threadIdx.x;
   const int j_first = (blk * WG) / ppc;
-  for (int k = threadIdx.x; k < WG + 1; k += WG) s_cnt[k] = 0;
-  __syncthreads();
   if (idx < g.nr * ppc) {
     const int j = idx / ppc, k = idx - (idx / ppc) * ppc;
     const int t = j / TR, trt = min(TR, g.nr - t * TR);
-    if (load_particle<R>(g, ia.pl, P, total + t * TR * ppc, (j - t * TR) * ppc, trt * ppc, col, j, k))
+    if (load_particle<R>(g, ia.pl, P, s_base[t], (j - t * TR) * ppc, trt * ppc, col, j, k))
       atomicAdd(&s_cnt[j - j_first], 1);
   }
   __syncthreads();
-  if (count_cells) {
+  if (sc.mode == SCAT_CELL) {
     const int pc = phys_col(g, g.nx - 1);
     for (int k = threadIdx.x; k < WG + 1; k += WG)
-      if (s_cnt[k] > 0 && j_first + k < g.nr) atomicAdd(&ccount[(size_t)pc * g.pitch + j_first + k], s_cnt[k]);
+      if (s_cnt[k] > 0 && j_first + k < g.nr) atomicAdd(&sc.ccount[(size_t)pc * g.pitch + j_first + k], s_cnt[k]);
   }
+  // the particles per tile, kept current; before a tile sort the particles
+  // of a row tile placed past the segments also arrive in their tile's
+  // segment
+  for (int k = threadIdx.x; k < WG + 1; k += WG)
+    if (s_cnt[k] > 0 && j_first + k < g.nr) {
+      const int j = j_first + k;
+      const int key = tile_key(g, col, j);
+      atomicAdd(&sc.hist[key], s_cnt[k]);
+      if (sc.mode == SCAT_TILE && s_base[j / TR] >= seg_end) atomicAdd(&sc.arr[key], s_cnt[k]);
+    }
   if (idx < g.ntr) {
     const int trt = min(TR, g.nr - idx * TR);
-    L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), total + idx * TR * ppc, trt * ppc, 0);
+    L.items[base_items + idx] = make_int4(tile_key(g, col, idx * TR), s_base[idx], trt * ppc, 0);
   }
   if (idx == 0) {
-    ia.pending[0] = g.ntr;       // items appended
-    ia.pending[1] = g.nr * ppc;  // slots appended
+    ia.pending[0] = g.ntr;           // items appended
+    ia.pending[1] = s_base[g.ntr];   // slots appended past the used ones
   }
 }
 
 // vacate: 1 when the window moves after this step (particles whose new
-// column is the window's first one are dropped after depositing);
-// count_cells: 1 when the particles are re-sorted at the next step (their
-// new cells are counted into ccount)
+// column is the window's first one are dropped after depositing); sc: what
+// to count for a sort at the next step (SortCounts)
 template <class R, bool M1, bool DEFER, int O, bool NT>
 __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restrict__ jx_out,
                                                  R* __restrict__ jr_out,
                                                  typename cplx_of<R>::type* __restrict__ jx1_out,
                                                  typename cplx_of<R>::type* __restrict__ jr1_out,
                                                  typename cplx_of<R>::type* __restrict__ jt1_out,
-                                                 Parts<R> P, Layout L, int* __restrict__ ccount, int vacate,
-                                                 int count_cells, Parts<R> scr, int* err, int item_blocks,
+                                                 Parts<R> P, Layout L, SortCounts sc, int vacate,
+                                                 Parts<R> scr, int* err, int item_blocks,
                                                  InjectArgs inj) {
   __shared__ SmemPos<R, M1> sm;
   if ((int)blockIdx.x >= item_blocks) {
-    // the phi staging area is free in these groups: it holds the row counts
+    // the phi staging area and the J_x accumulators are free in these
+    // groups: they hold the row counts and the row tiles' first slots
     static_assert(sizeof(sm.phh) >= (WG + 1) * sizeof(int), "row counts do not fit");
-    inject_block<R>(inj, P, L, ccount, count_cells, err, blockIdx.x - item_blocks, reinterpret_cast<int*>(sm.phh));
+    static_assert(sizeof(sm.jx) >= (NR_MAX / TR + 2) * sizeof(int), "row tile slots do not fit");
+    inject_block<R>(inj, P, L, sc, err, blockIdx.x - item_blocks, reinterpret_cast<int*>(sm.phh),
+                    reinterpret_cast<int*>(sm.jx));
     return;
   }
   const int item = item_of(blockIdx.x, item_blocks);
@@ -1261,6 +1388,17 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
   stage_pos_constants(sm, q, g);
   zero_pos_acc(sm);
   __syncthreads();
+  // Before a tile sort, the particles of an item past the tiles' segments
+  // (an injected column, an overflow range) all join their tiles'
+  // segments: their live count, taken before the pass removes any
+  const bool fill_item = start >= L.offsets[g.ntiles];
+  if (sc.mode == SCAT_TILE && fill_item) {
+    int c = 0;
+    for (int k = threadIdx.x; k < count; k += WG) c += P.cell[start + k] != kDead ? 1 : 0;
+    c = wave_sum_i(c);
+    if (__lane_id() == 0 && c != 0) atomicAdd(&sm.tcnt[10], c);
+    __syncthreads();
+  }
 
   bool bad = false;
   // the next particle's record is loaded before this one is processed
@@ -1313,6 +1451,7 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
     const long long reln = (long long)mv.ix1 - g.shift;
     if (reln < 0 || reln >= g.nx) {
       P.cell[p] = kDead;  // left the window: removed without deposit
+      atomicAdd(&sm.tcnt[9], 1);
       continue;
     }
     if (DEFER) {
@@ -1332,18 +1471,25 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
     pst<NT>(&P.th[p], mv.th1);
     if (vacate && reln < 1) {
       if (!DEFER) P.cell[p] = kDead;  // vacated column: dropped after depositing
+      atomicAdd(&sm.tcnt[9], 1);
       continue;
     }
-    if (count_cells) {
+    if (sc.mode == SCAT_CELL) {
       const int sx = clampi(mv.ix1 - (q.T * TX - SORT_EVERY), 0, CR - 1, bad);
       const int sr = clampi(mv.jr1 - (q.tcr * TR - SORT_EVERY), 0, CR - 1, bad);
       atomicAdd(&sm.ccell[sx * CR + sr], 1);
+    } else if (sc.mode == SCAT_TILE) {
+      // a particle that changes tile (rare) counts for its new tile
+      const int dtx = clampi(mv.ix1 / TX - q.T, -1, 1, bad);
+      const int dtr = clampi(mv.jr1 / TR - q.tcr, -1, 1, bad);
+      if (dtx != 0 || dtr != 0) atomicAdd(&sm.tcnt[(dtx + 1) * 3 + dtr + 1], 1);
     }
   }
   if (bad) atomicOr(err, ERR_HALO);
   __syncthreads();
   if (!DEFER) flush_current<R, M1, O>(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
-  if (count_cells) flush_cells(sm.ccell, q, g, ccount);
+  if (sc.mode == SCAT_CELL) flush_cells(sm.ccell, q, g, sc.ccount);
+  flush_tiles(sm.tcnt, q, g, sc, fill_item);
 }
 
 // ============================= deferred deposits (stage-by-stage API) ==
@@ -1434,6 +1580,28 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
   flush_current<R, M1, 1>(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
 }
 
+// After a tile sort: when its scan had to rebuild the layout (LAYOUT_FULL),
+// the sort wrote every particle into the other buffer; copy the used slots
+// back, so that the particles stay in the buffer they were in.  Nothing to
+// do after an incremental sort.
+constexpr int SETTLE_GROUPS = 256;
+template <class R>
+__global__ __launch_bounds__(256) void k_settle(Parts<R> to, Parts<R> from, Layout L, long long cap) {
+  if (*L.mode != LAYOUT_FULL) return;
+  const long long n = min((long long)*L.fill, cap);
+  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
+    to.cell[i] = from.cell[i];
+    to.fx[i] = from.fx[i];
+    to.fr[i] = from.fr[i];
+    to.th[i] = from.th[i];
+    to.px[i] = from.px[i];
+    to.py[i] = from.py[i];
+    to.pz[i] = from.pz[i];
+    to.w[i] = from.w[i];
+    to.id[i] = from.id[i];
+  }
+}
+
 // initial loading of window cells in tile-major order (offsets per tile
 // from the host, cells of a tile column-major inside the tile)
 template <class R>
@@ -1451,19 +1619,26 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
 }
 
 // ============================================================ launchers ==
+template <class R, bool M1, bool DEFER, int SCAT, int O, bool NT>
+static void launch_momentum_k(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
+                              const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int max_items,
+                              hipStream_t st, const KEvents& ev) {
+  launch_k(k_momentum<R, M1, DEFER, SCAT, O, NT>, dim3(max_items), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
+           ccur, gscr, err);
+}
 template <class R, bool M1, bool DEFER, int O, bool NT>
 static void launch_momentum_nt(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                                const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
                                int scatter, hipStream_t st, const KEvents& ev) {
-  if (scatter == SCAT_TILE)
-    launch_k(k_momentum<R, M1, DEFER, SCAT_TILE, O, NT>, dim3(grid), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
-             ccur, gscr, err);
-  else if (scatter == SCAT_CELL)
-    launch_k(k_momentum<R, M1, DEFER, SCAT_CELL, O, NT>, dim3(grid), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
-             ccur, gscr, err);
-  else
-    launch_k(k_momentum<R, M1, DEFER, SCAT_NONE, O, NT>, dim3(grid), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
-             ccur, gscr, err);
+  if (scatter == SCAT_TILE) {
+    launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st,
+                                                      KEvents{ev.start, nullptr});
+    launch_k(k_settle<R>, dim3(SETTLE_GROUPS), dim3(256), st, KEvents{nullptr, ev.stop}, src, dst, Ld, g.cap);
+  } else if (scatter == SCAT_CELL) {
+    launch_momentum_k<R, M1, DEFER, SCAT_CELL, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
+  } else {
+    launch_momentum_k<R, M1, DEFER, SCAT_NONE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
+  }
 }
 // non-temporal record access for the fused passes of large runs only
 template <class R, bool M1, bool DEFER, int O>
@@ -1505,38 +1680,43 @@ template <class R> int inject_blocks(const Geo& g) {
   return (n + WG - 1) / WG;
 }
 
+template <class R, bool M1, bool DEFER, int O, bool NT>
+static void launch_position_nt(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P,
+                               const Layout& L, const SortCounts& sc, int vacate, const Parts<R>& scr, int* err,
+                               int max_items, const InjectArgs& inj, hipStream_t st, const KEvents& ev) {
+  launch_k(k_position<R, M1, DEFER, O, NT>, dim3(max_items + inj.blocks), dim3(WG), st, ev, g, f, d.jx, d.jr, d.jx1,
+           d.jr1, d.jt1, P, L, sc, vacate, scr, err, max_items, inj);
+}
 template <class R, bool M1, bool DEFER, int O>
 static void launch_position_k(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P,
-                              const Layout& L, int* ccount, int vacate, int count_cells, const Parts<R>& scr,
-                              int* err, int grid, const InjectArgs& inj, hipStream_t st, const KEvents& ev) {
+                              const Layout& L, const SortCounts& sc, int vacate, const Parts<R>& scr, int* err,
+                              int grid, const InjectArgs& inj, hipStream_t st, const KEvents& ev) {
   if (!DEFER && g.stream_parts)
-    launch_k(k_position<R, M1, DEFER, O, true>, dim3(grid + inj.blocks), dim3(WG), st, ev, g, f, d.jx, d.jr, d.jx1,
-             d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+    launch_position_nt<R, M1, DEFER, O, true>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
   else
-    launch_k(k_position<R, M1, DEFER, O, false>, dim3(grid + inj.blocks), dim3(WG), st, ev, g, f, d.jx, d.jr, d.jx1,
-             d.jr1, d.jt1, P, L, ccount, vacate, count_cells, scr, err, grid, inj);
+    launch_position_nt<R, M1, DEFER, O, false>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
 }
 
 template <class R>
 void launch_position(const Geo& g, const Grids<R>& f, const DepositBufs<R>& d, const Parts<R>& P, const Layout& L,
-                     int* ccount, int vacate, int count_cells, const Parts<R>& scr, int* err, int grid, bool defer,
+                     const SortCounts& sc, int vacate, const Parts<R>& scr, int* err, int grid, bool defer,
                      const InjectArgs& inj, hipStream_t st, const KEvents& ev) {
   if (grid <= 0) return;
   if (g.order == 2) {
     if (g.modes >= 2)
-      launch_position_k<R, true, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
+      launch_position_k<R, true, false, 2>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
     else
-      launch_position_k<R, false, false, 2>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
+      launch_position_k<R, false, false, 2>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
   } else if (g.modes >= 2) {
     if (defer)
-      launch_position_k<R, true, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
+      launch_position_k<R, true, true, 1>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
     else
-      launch_position_k<R, true, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
+      launch_position_k<R, true, false, 1>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
   } else {
     if (defer)
-      launch_position_k<R, false, true, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
+      launch_position_k<R, false, true, 1>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
     else
-      launch_position_k<R, false, false, 1>(g, f, d, P, L, ccount, vacate, count_cells, scr, err, grid, inj, st, ev);
+      launch_position_k<R, false, false, 1>(g, f, d, P, L, sc, vacate, scr, err, grid, inj, st, ev);
   }
 }
 
@@ -1571,7 +1751,7 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
                                    const Layout&, const Layout&, int*, R*, int*, int, bool, int, hipStream_t,   \
                                    const KEvents&);                                                             \
   template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
-                                   const Layout&, int*, int, int, const Parts<R>&, int*, int, bool,             \
+                                   const Layout&, const SortCounts&, int, const Parts<R>&, int*, int, bool,     \
                                    const InjectArgs&, hipStream_t, const KEvents&);                             \
   template int inject_blocks<R>(const Geo&);                                                                    \
   template void launch_deposit_chi<R>(const Geo&, R*, const Parts<R>&, const Layout&, const R*, int*, int,      \

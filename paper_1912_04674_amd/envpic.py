@@ -68,7 +68,7 @@ EXPORTS = [
     "envpic_get_particles", "envpic_set_particles", "envpic_diagnostics", "envpic_save",
     "envpic_load", "envpic_debug_poison", "envpic_sim_destroy", "envpic_last_error",
     "envpic_set_timing", "envpic_get_timing", "envpic_set_graph", "envpic_beam_diagnostics",
-    "envpic_bunch_fields", "envpic_stream_copy", "envpic_diagnostics_noalloc",
+    "envpic_bunch_fields", "envpic_stream_copy", "envpic_diagnostics_noalloc", "envpic_sort_stats",
 ]
 
 
@@ -99,6 +99,7 @@ def lib():
     L.envpic_get_field.argtypes = [vp, ctypes.c_int, dp]
     L.envpic_set_field.argtypes = [vp, ctypes.c_int, dp]
     L.envpic_state.argtypes = [vp, i64p, i64p, i64p]
+    L.envpic_sort_stats.argtypes = [vp, i64p]
     L.envpic_get_particles.argtypes = [vp] + [dp] * 7 + [up]
     L.envpic_set_particles.argtypes = [vp, ctypes.c_int64] + [dp] * 7 + [up]
     L.envpic_diagnostics.argtypes = [vp, dp]
@@ -234,6 +235,15 @@ class Sim:
         n, s, npart = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
         _check(lib().envpic_state(self._h, ctypes.byref(n), ctypes.byref(s), ctypes.byref(npart)))
         return n.value, s.value, npart.value
+
+    def sort_stats(self):
+        """How the particle sorts ran: {"cell": sorts that rebuilt the layout
+        ordered by cell, "incremental": tile sorts that moved only the
+        particles that changed tile, "rebuilt": tile sorts that found no room
+        and rebuilt the layout}."""
+        out = (ctypes.c_int64 * 3)()
+        _check(lib().envpic_sort_stats(self._h, out))
+        return {"cell": out[0], "incremental": out[1], "rebuilt": out[2]}
 
     def get_field(self, name):
         shape = (self.nx + 1, self.nr + 1)

@@ -261,6 +261,36 @@ def test_window_modes01_parity(E, oracle_mod, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+@pytest.mark.parametrize("room", ["default", "tight"])
+def test_incremental_and_rebuilt_tile_sorts(E, oracle_mod, room, prec, tf, tp):
+    """The window run (injection every step, modes 0 and 1) through both
+    kinds of tile sort: with the default capacity every tile sort moves only
+    the particles that changed tile; with the least capacity allowed (one
+    window of slots plus the three columns injected between sorts: no free
+    slots in the segments, no overflow room) every tile sort rebuilds the
+    layout instead.  Both match the oracle after 100 steps."""
+    window = C2_SMALL["nx"] * C2_SMALL["nr"] * int(np.prod(C2_SMALL["ppc"]))
+    column = C2_SMALL["nr"] * int(np.prod(C2_SMALL["ppc"]))
+    cfg = C2_SMALL if room == "default" else dict(C2_SMALL, capacity=window + 3 * column + 64)
+    say("tile sorts", room, prec)
+    g = E.Sim(cfg, _prec(E, prec))
+    r = oracle_mod.OracleSim(C2_SMALL)
+    g.step(100)
+    r.step(100)
+    st = g.sort_stats()
+    say("sort stats", st)
+    # a sort every third step: 33 in 100 steps, every eighth of them by cell
+    assert st["cell"] == 5 and st["cell"] + st["incremental"] + st["rebuilt"] == 33
+    if room == "default":
+        assert st["incremental"] == 28 and st["rebuilt"] == 0
+    else:
+        assert st["rebuilt"] == 28
+    assert g.state()[2] == r.state()[2]
+    compare_fields(g, r, tf, modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
 DIAG_KEYS = ("count", "charge", "chi_v", "kin", "uem", "env2_v", "lx", "px", "nonfinite")
 
 
