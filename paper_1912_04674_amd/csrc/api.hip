@@ -298,6 +298,7 @@ struct envpic_sim {
   int64_t sorted_at = 0;  // step whose positions the layout of P[cur] is sorted by
   int64_t n_sorts = 0;    // sorts so far (selects tile or cell order)
   int64_t n_cell_sorts = 0;
+  bool settle_due = false;  // the envelope stage carries the copy back of this step's tile sort
   bool deferred = false, deposit_done = true;
   int chi_last = 0;  // deposit buffer of the last momentum stage
   bool jf_valid = false;  // the filtered copy holds the current of the last field stage
@@ -664,6 +665,7 @@ template <class R> struct SimT : envpic_sim {
         cur = 1 - cur;
         n_cell_sorts += 1;
       }
+      settle_due = mode == SCAT_TILE && !defer;  // (the deferred form copies back at once)
       lay = 1 - lay;
       sorted_at = n;
       n_sorts += 1;
@@ -695,7 +697,13 @@ template <class R> struct SimT : envpic_sim {
     if (stage != 1 || !deposit_done) return fail(ENVPIC_EORDER, "envelope stage out of order");
     const Geo g = geo();
     const KEvents ev = tick_events();
-    launch_envelope<R>(g, S.grids, S.dep[n & 1].chi, fp64_rows ? 1 : 0, stream, ev);
+    // a tile sort of this step that rebuilt its layout is copied back here
+    SettleArgs<R> sa{};
+    if (settle_due) {
+      sa = SettleArgs<R>{S.parts[cur], S.parts[1 - cur], S.lay[lay], sz.capacity, SETTLE_BLOCKS};
+      settle_due = false;
+    }
+    launch_envelope<R>(g, S.grids, S.dep[n & 1].chi, fp64_rows ? 1 : 0, sa, stream, ev);
     tick_end(1, ev);
     std::swap(S.grids.env, S.grids.envp);
     std::swap(S.grids.ax, S.grids.axp);

@@ -144,6 +144,17 @@ struct Layout {
   int* mode;     // scalar: LAYOUT_MOVE or LAYOUT_FULL (tile sorts)
 };
 
+// The copy back after a tile sort that rebuilt its layout (settle_copy):
+// from the other buffer into the one in use, over the used slots of L, by
+// `blocks` extra groups of the launch that carries it (none: 0)
+constexpr int SETTLE_BLOCKS = 256;
+template <class R> struct SettleArgs {
+  Parts<R> to, from;
+  Layout L;
+  long long cap;
+  int blocks;
+};
+
 struct Plasma {
   int profile;
   double n0, ramp_len, perturb, bump_x, bump_w;

@@ -29,8 +29,13 @@ __device__ inline double recip_r(double x) { return 1.0 / x; }
 __device__ inline float recip_r(float x) { return __builtin_amdgcn_rcpf(x); }
 
 template <class R>
-__global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp64_rows) {
+__global__ void k_envelope(Geo g, Grids<R> f, const R* __restrict__ chi, int fp64_rows, SettleArgs<R> sa) {
   using C = typename cplx_of<R>::type;
+  const int node_groups = (int)gridDim.x - sa.blocks;
+  if ((int)blockIdx.x >= node_groups) {  // the copy back of a rebuilt tile sort
+    settle_copy(sa, (int)blockIdx.x - node_groups, sa.blocks);
+    return;
+  }
   const int nr1 = g.nr + 1;
   const int idx = (int)(blockIdx.x * blockDim.x + threadIdx.x);  // nodes < 2^31
   if (idx >= (g.nx + 1) * nr1) return;
@@ -434,9 +439,9 @@ static inline int node_blocks(const Geo& g) {
 }
 
 template <class R>
-void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st,
-                     const KEvents& ev) {
-  launch_k(k_envelope<R>, dim3(node_blocks(g)), dim3(256), st, ev, g, f, chi, fp64_rows);
+void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, const SettleArgs<R>& sa,
+                     hipStream_t st, const KEvents& ev) {
+  launch_k(k_envelope<R>, dim3(node_blocks(g) + sa.blocks), dim3(256), st, ev, g, f, chi, fp64_rows, sa);
 }
 
 template <class R>
@@ -590,7 +595,8 @@ void launch_init_envelope(const Geo& g, const Grids<R>& f, const Laser& L, int f
 }
 
 #define ENVPIC_INST(R)                                                                                      \
-  template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, hipStream_t, const KEvents&); \
+  template void launch_envelope<R>(const Geo&, const Grids<R>&, const R*, int, const SettleArgs<R>&,        \
+                                   hipStream_t, const KEvents&);                                            \
   template void launch_field<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const DepositBufs<R>&,   \
                                 const DepositBufs<R>&, const DepositBufs<R>&, FieldArgs, hipStream_t,       \
                                 const KEvents&);                                                            \

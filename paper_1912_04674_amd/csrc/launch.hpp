@@ -69,8 +69,11 @@ void launch_deposit_J(const Geo& g, const DepositBufs<R>& d, const Parts<R>& P, 
 template <class R>
 void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, const int* offsets, hipStream_t st);
 
+// sa: the copy back of a tile sort that rebuilt its layout, run by extra
+// groups of the same launch (it reads no grid the update writes)
 template <class R>
-void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, hipStream_t st,
+void launch_envelope(const Geo& g, const Grids<R>& f, const R* chi, int fp64_rows, const SettleArgs<R>& sa,
+                     hipStream_t st,
                      const KEvents& ev = KEvents{});
 // `passes` passes of the binomial filter on the currents of din into dout
 // (chi is not touched)

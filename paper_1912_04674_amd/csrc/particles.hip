@@ -23,6 +23,7 @@
 #include "common.hpp"
 #include "cplx.hpp"
 #include "launch.hpp"
+#include "scan.hpp"
 
 namespace envpic {
 
@@ -367,10 +368,10 @@ __device__ inline int wave_slot_rank(int slot, int* counters) {
 // tile's overflow range, and its old slot is marked removed), or, when the
 // scan found no room (LAYOUT_FULL), every particle is written into the other
 // buffer keeping the particles' relative order (coalesced writes), from where
-// k_settle copies the layout back.  SCAT_CELL orders each tile by cell and
-// places every work item as at loading, so that the lanes of a wavefront
-// hold particles of distinct cells again (the deposits' LDS atomics do not
-// collide), at the price of strided writes.
+// settle_copy copies them back (in the envelope stage's launch).  SCAT_CELL
+// orders each tile by cell and places every work item as at loading, so that
+// the lanes of a wavefront hold particles of distinct cells again (the
+// deposits' LDS atomics do not collide), at the price of strided writes.
 // O: particle shape order (1 linear, 2 quadratic; order 2 re-sorts every
 // second step, so its wider stencil stays inside the same halo).
 // Waves per SIMD the compiler must allow: the FP32 linear in-place pass fits
@@ -1580,26 +1581,12 @@ __global__ __launch_bounds__(WG) void k_deposit_J(Geo g, R* __restrict__ jx_out,
   flush_current<R, M1, 1>(sm, q, g, jx_out, jr_out, jx1_out, jr1_out, jt1_out);
 }
 
-// After a tile sort: when its scan had to rebuild the layout (LAYOUT_FULL),
-// the sort wrote every particle into the other buffer; copy the used slots
-// back, so that the particles stay in the buffer they were in.  Nothing to
-// do after an incremental sort.
-constexpr int SETTLE_GROUPS = 256;
+// The copy back of a tile sort whose scan rebuilt the layout, as a launch of
+// its own (the deferred-deposit stages, which read the particles before the
+// envelope stage that otherwise carries it).
 template <class R>
-__global__ __launch_bounds__(256) void k_settle(Parts<R> to, Parts<R> from, Layout L, long long cap) {
-  if (*L.mode != LAYOUT_FULL) return;
-  const long long n = min((long long)*L.fill, cap);
-  for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long long)gridDim.x * 256) {
-    to.cell[i] = from.cell[i];
-    to.fx[i] = from.fx[i];
-    to.fr[i] = from.fr[i];
-    to.th[i] = from.th[i];
-    to.px[i] = from.px[i];
-    to.py[i] = from.py[i];
-    to.pz[i] = from.pz[i];
-    to.w[i] = from.w[i];
-    to.id[i] = from.id[i];
-  }
+__global__ __launch_bounds__(256) void k_settle(SettleArgs<R> sa) {
+  settle_copy(sa, blockIdx.x, gridDim.x);
 }
 
 // initial loading of window cells in tile-major order (offsets per tile
@@ -1630,10 +1617,15 @@ template <class R, bool M1, bool DEFER, int O, bool NT>
 static void launch_momentum_nt(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
                                const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
                                int scatter, hipStream_t st, const KEvents& ev) {
-  if (scatter == SCAT_TILE) {
+  if (scatter == SCAT_TILE && DEFER) {
+    // the deferred chi deposit reads the particles before the envelope stage
     launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st,
                                                       KEvents{ev.start, nullptr});
-    launch_k(k_settle<R>, dim3(SETTLE_GROUPS), dim3(256), st, KEvents{nullptr, ev.stop}, src, dst, Ld, g.cap);
+    launch_k(k_settle<R>, dim3(SETTLE_BLOCKS), dim3(256), st, KEvents{nullptr, ev.stop},
+             SettleArgs<R>{src, dst, Ld, g.cap, SETTLE_BLOCKS});
+  } else if (scatter == SCAT_TILE) {
+    // (the envelope stage carries the copy back)
+    launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
   } else if (scatter == SCAT_CELL) {
     launch_momentum_k<R, M1, DEFER, SCAT_CELL, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
   } else {

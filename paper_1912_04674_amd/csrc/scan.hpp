@@ -233,4 +233,25 @@ __device__ inline void move_layout(const Geo& g, int* hist, int* arr, Layout in,
   }
 }
 
+// After a tile sort whose scan rebuilt the layout (LAYOUT_FULL), the sort
+// wrote every particle into the other buffer: copy the used slots back (b of
+// nb groups of 256 threads), so that the particles stay in the buffer they
+// were in.  Nothing to do after an incremental sort.
+template <class R>
+__device__ inline void settle_copy(const SettleArgs<R>& sa, int b, int nb) {
+  if (*sa.L.mode != LAYOUT_FULL) return;
+  const long long n = min((long long)*sa.L.fill, sa.cap);
+  for (long long i = (long long)b * 256 + threadIdx.x; i < n; i += (long long)nb * 256) {
+    sa.to.cell[i] = sa.from.cell[i];
+    sa.to.fx[i] = sa.from.fx[i];
+    sa.to.fr[i] = sa.from.fr[i];
+    sa.to.th[i] = sa.from.th[i];
+    sa.to.px[i] = sa.from.px[i];
+    sa.to.py[i] = sa.from.py[i];
+    sa.to.pz[i] = sa.from.pz[i];
+    sa.to.w[i] = sa.from.w[i];
+    sa.to.id[i] = sa.from.id[i];
+  }
+}
+
 }  // namespace envpic
