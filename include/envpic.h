@@ -88,7 +88,7 @@ typedef struct envpic_params {
   double dx, dr, dt;
   double a0, w0, tau, x_c, x_f;
   double n0, ramp_len, perturb, bump_x, bump_w;
-  int64_t capacity;        /* particle slots per buffer (0: derived) */
+  int64_t capacity;        /* particle slots per buffer (0: derived; at most 2^30 - 1) */
   int32_t filter_passes;   /* passes of the 1-2-1 binomial filter on J (0: none, at most
                               ENVPIC_FILTER_MAX, below nx/2 and nr/2); each pass
                               smooths along x, then r */

@@ -120,7 +120,8 @@ int validate(const envpic_params* p) {
     return fail(ENVPIC_EINVAL, "perturb must be in [0, 1] (a non-negative density)");
   if (p->a0 < 0 || (p->a0 > 0 && !(p->w0 > 0 && p->tau > 0))) return fail(ENVPIC_EINVAL, "bad laser parameters");
   const Sizes s = sizes_of(*p);
-  if (s.capacity >= (1LL << 31) - 1) return fail(ENVPIC_EINVAL, "too many particles for int32 slots");
+  // slots < 2^30: the particle passes form 4-byte records' byte offsets in 32 bits
+  if (s.capacity >= (1LL << 30)) return fail(ENVPIC_EINVAL, "too many particles: at most 2^30 - 1 slots");
   if (s.capacity < (long long)p->nx * p->nr * s.ppc + (long long)SORT_EVERY * p->nr * s.ppc)
     return fail(ENVPIC_EINVAL, "capacity below one window of particles plus the columns injected between sorts");
   return ENVPIC_OK;
@@ -518,14 +519,14 @@ template <class R> struct SimT : envpic_sim {
     g.order = p.shape_order == 2 ? 2 : 1;
     // one buffer's records: cell word and id, six reals and the weight
     g.stream_parts = sz.capacity * (long long)(8 + 7 * sizeof(R)) >= STREAM_PARTS_BYTES ? 1 : 0;
-    // fixed-point scale of the mode-1 current sums: 2^49 over the largest
+    // fixed-point scale of the mode-1 current sums: 2^32 over the largest
     // |2 q w v S / V| = 2 w_max / V_0, V_0 = pi dr^2 dx / 4
     const double cmax = 2.0 * wmax * 4.0 / (3.14159265358979323846 * p.dr * p.dr * p.dx);
-    const double fix = cmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 49) / cmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
+    const double fix = cmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 32) / cmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
     g.fix = (float)fix;
     g.unfix = 1.0 / (double)g.fix;
-    // the chi and mode-0 current sums: 2^49 over the largest |w S| = w_max
-    const double fix0 = wmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 49) / wmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
+    // the chi and mode-0 current sums: 2^32 over the largest |w S| = w_max
+    const double fix0 = wmax > 0.0 ? std::min(std::max(std::ldexp(1.0, 32) / wmax, std::ldexp(1.0, -100)), std::ldexp(1.0, 100)) : 1.0;
     g.fix0 = (float)fix0;
     g.unfix0 = 1.0 / (double)g.fix0;
     return g;

@@ -91,27 +91,34 @@ __device__ inline C interp3c(const C* a, const Quad<R>& sx, const Quad<R>& sr) {
   return mk<C>(re, im);
 }
 
+// v clamped to [lo, hi]; bad is set when it was outside (one min/max and one
+// compare)
 __device__ inline int clampi(int v, int lo, int hi, bool& bad) {
-  if (v < lo) { bad = true; return lo; }
-  if (v > hi) { bad = true; return hi; }
-  return v;
+  const int c = min(max(v, lo), hi);
+  bad |= c != v;
+  return c;
 }
 
 __device__ inline void lds_add(float* a, float v) { atomicAdd(a, v); }
 __device__ inline void lds_add(double* a, double v) { atomicAdd(a, v); }
 
 // Mode-1 current accumulators.  The FP64 path sums in FP64 LDS words.  The
-// FP32 path sums 64-bit fixed-point integers: on gfx950 integer LDS atomics
-// issue faster than FP64 ones (and FP32 LDS atomics are far slower than
-// either, measured), and an integer sum is exact and independent of the
-// order in which the lanes land.  Each contribution is scaled by g.fix =
-// 2^49 / (2 w_max / V_0), the bound of any |2 q w v S / V| (|v| < 1, S <= 1,
-// V_0 the smallest node volume), so one contribution is at most 2^49 in
-// magnitude and the <= 2 CHUNK contributions of a work item to one node stay
-// below 2^63.  The float -> int64 conversion adds 1.5 2^52 in FP64 and reads
-// the mantissa bits (round to nearest, exact for |x| < 2^51).
-// add_prod(a, u, x, y) adds u x and u y, formed in FP64 (the float -> int64
-// conversion then costs one FMA with the magic constant and one subtract).
+// FP32 path sums fixed-point integers in 64-bit LDS words: on gfx950 integer
+// LDS atomics issue faster than FP64 ones (and FP32 LDS atomics are far
+// slower than either, measured), and an integer sum is exact and independent
+// of the order in which the lanes land.  Each contribution is scaled by
+// g.fix = 2^32 / (2 w_max / V_0), the bound of any |2 q w v S / V| (|v| < 1,
+// S <= 1, V_0 the smallest node volume), so one contribution is at most 2^32
+// in magnitude and the <= 2 CHUNK contributions of a work item to one node
+// (and a fold of two such nodes) stay below 2^46.
+//
+// The float -> fixed conversion is one FP64 FMA: u x + 1.5 2^52 rounds u x
+// to the nearest integer v and its bit pattern is 0x4338 2^48 + v (exact for
+// |v| < 2^51).  The words add those patterns as they are; the constant parts
+// only reach bits 48..63, so the low 48 bits of a word hold the sum of the v
+// modulo 2^48, which is the sum itself, as |sum| < 2^47 (fixed_sum reads it).
+// On the hot path this saves the subtraction of the constant per atomic.
+// add_prod(a, u, x, y) adds u x and u y, formed in FP64.
 template <class R> struct Acc1;
 template <> struct Acc1<double> {
   using T = double2;
@@ -126,10 +133,14 @@ template <> struct Acc1<double> {
   __device__ static double re(const T& v, const Geo&) { return v.x; }
   __device__ static double im(const T& v, const Geo&) { return v.y; }
 };
-// nearest integer to u x (|u x| < 2^51): the mantissa bits of u x + 1.5 2^52
-__device__ inline long long fixed_prod(double u, double x) {
-  const double m = 6755399441055744.0;  // 1.5 * 2^52
-  return __double_as_longlong(fma(u, x, m)) - __double_as_longlong(m);
+// bit pattern of u x + 1.5 2^52: 0x4338 2^48 + the nearest integer to u x
+// (|u x| < 2^51)
+__device__ inline unsigned long long fixed_bits(double u, double x) {
+  return (unsigned long long)__double_as_longlong(fma(u, x, 6755399441055744.0));  // 1.5 * 2^52
+}
+// the sum held by a word of fixed_bits patterns: its low 48 bits, signed
+__device__ inline long long fixed_sum(long long w) {
+  return (long long)((unsigned long long)w << 16) >> 16;
 }
 template <> struct Acc1<float> {
   using T = longlong2;
@@ -137,12 +148,12 @@ template <> struct Acc1<float> {
   __device__ static T zero() { return make_longlong2(0, 0); }
   __device__ static float scale(const Geo& g) { return g.fix; }
   template <class A> __device__ static void add_prod(A& a, int k, double u, double x, double y) {  // already scaled
-    atomicAdd((unsigned long long*)&a.re[k], (unsigned long long)fixed_prod(u, x));
-    atomicAdd((unsigned long long*)&a.im[k], (unsigned long long)fixed_prod(u, y));
+    atomicAdd((unsigned long long*)&a.re[k], fixed_bits(u, x));
+    atomicAdd((unsigned long long*)&a.im[k], fixed_bits(u, y));
   }
-  __device__ static bool nonzero(const T& v) { return v.x != 0 || v.y != 0; }
-  __device__ static float re(const T& v, const Geo& g) { return (float)((double)v.x * g.unfix); }
-  __device__ static float im(const T& v, const Geo& g) { return (float)((double)v.y * g.unfix); }
+  __device__ static bool nonzero(const T& v) { return fixed_sum(v.x) != 0 || fixed_sum(v.y) != 0; }
+  __device__ static float re(const T& v, const Geo& g) { return (float)((double)fixed_sum(v.x) * g.unfix); }
+  __device__ static float im(const T& v, const Geo& g) { return (float)((double)fixed_sum(v.y) * g.unfix); }
 };
 
 // Mode-0 deposit accumulators (chi, and J_x, J_r of the Esirkepov scheme).
@@ -150,23 +161,24 @@ template <> struct Acc1<float> {
 // currents, a partial sum of shape differences in [-1, 1]) without the
 // inverse node volume or face area, which depend on the row only and are
 // applied once per node at the flush.  The FP64 path sums FP64 words; the
-// FP32 path sums 64-bit fixed point scaled by g.fix0 = 2^49 / w_max, so a
-// contribution is at most 2^49 and the <= CHUNK contributions of a work item
-// to one node stay below 2^63 (exact, order-independent sums).
+// FP32 path sums fixed point as the mode-1 accumulators do, scaled by g.fix0
+// = 2^32 / w_max, so a contribution is at most 2^32 and the <= 2 CHUNK
+// contributions of a work item to one node (and a fold of two such nodes)
+// stay below 2^46 (exact, order-independent sums).
 template <class R> struct Acc0;
 template <> struct Acc0<double> {
   using T = double;
   __device__ static double scale(const Geo&) { return 1.0; }
   __device__ static void add_prod(T* a, double u, double x) { atomicAdd(a, u * x); }
+  __device__ static bool nonzero(T v) { return v != 0.0; }
   __device__ static double val(T v, const Geo&) { return v; }
 };
 template <> struct Acc0<float> {
   using T = long long;
   __device__ static double scale(const Geo& g) { return g.fix0; }
-  __device__ static void add_prod(T* a, double u, double x) {
-    atomicAdd((unsigned long long*)a, (unsigned long long)fixed_prod(u, x));
-  }
-  __device__ static double val(T v, const Geo& g) { return (double)v * g.unfix0; }
+  __device__ static void add_prod(T* a, double u, double x) { atomicAdd((unsigned long long*)a, fixed_bits(u, x)); }
+  __device__ static bool nonzero(T v) { return fixed_sum(v) != 0; }
+  __device__ static double val(T v, const Geo& g) { return (double)fixed_sum(v) * g.unfix0; }
 };
 
 // Elementary functions.  The FP32 path uses the hardware reciprocal, square
@@ -248,6 +260,18 @@ template <bool NT, class T> __device__ inline T pld(const T* p) {
 template <bool NT, class T> __device__ inline void pst(T* p, T v) {
   if constexpr (NT) __builtin_nontemporal_store(v, p);
   else *p = v;
+}
+// Element i of a record array: for 4-byte elements the byte offset is formed
+// in 32 bits (slots < 2^30), so the access takes the array's address from
+// scalar registers and the 32-bit offset from a vector register, with no
+// 64-bit address arithmetic per lane.
+template <class T> __device__ inline T* elem(T* a, int i) {
+  if constexpr (sizeof(T) == 4) return (T*)((char*)a + (unsigned)i * 4u);
+  else return a + i;
+}
+template <class T> __device__ inline const T* elem(const T* a, int i) {
+  if constexpr (sizeof(T) == 4) return (const T*)((const char*)a + (unsigned)i * 4u);
+  else return a + i;
 }
 
 // Loading order inside a tile: the R particles of a tile, enumerated cell
@@ -483,7 +507,7 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
     slot_rank[u] = -1;
     int tslot = -1;  // SCAT_TILE: destination tile of the 3 x 3 neighbourhood
     if (k < count) {
-      const unsigned cw = src.cell[start + k];
+      const unsigned cw = *elem(src.cell, start + k);
       if (cw != kDead) {
         if (SCAT == SCAT_TILE) {
           const int dtx = clampi(cell_ix(cw) / TX - q.T, -1, 1, bad);
@@ -556,7 +580,7 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
   for (int u = 0; u < PPT; ++u) {
     if (slot_rank[u] < 0) continue;
     const int p = start + threadIdx.x + u * WG;
-    const unsigned cw = pld<NT>(&src.cell[p]);  // its second read (the first above)
+    const unsigned cw = pld<NT>(elem(src.cell, p));  // its second read (the first above)
     int d = p;
     const bool stay = SCAT == SCAT_TILE && slot_rank[u] == STAY;
     if (SCAT == SCAT_TILE && !stay) {
@@ -597,8 +621,8 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
         continue;
       }
     }
-    const R fx = pld<NT>(&src.fx[p]), fr = pld<NT>(&src.fr[p]), th = pld<NT>(&src.th[p]), w = pld<NT>(&src.w[p]);
-    R pv[3] = {pld<NT>(&src.px[p]), pld<NT>(&src.py[p]), pld<NT>(&src.pz[p])};
+    const R fx = pld<NT>(elem(src.fx, p)), fr = pld<NT>(elem(src.fr, p)), th = pld<NT>(elem(src.th, p)), w = pld<NT>(elem(src.w, p));
+    R pv[3] = {pld<NT>(elem(src.px, p)), pld<NT>(elem(src.py, p)), pld<NT>(elem(src.pz, p))};
     // the cell relative to the region: [1, RX - 3] for the linear stencils
     // (and the differences of Phi one node further out); order 2 keeps
     // [2, RX - 4], the range its position pass needs for the current
@@ -673,7 +697,7 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
     const R igb = rsqrt_r((R)1 + pm[0] * pm[0] + pm[1] * pm[1] + pm[2] * pm[2] + ph);
     const R tf = -hdt * igb;
     const R t[3] = {tf * B[0], tf * B[1], tf * B[2]};
-    const R sf = (R)2 / ((R)1 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
+    const R sf = (R)2 * rcp_r((R)1 + t[0] * t[0] + t[1] * t[1] + t[2] * t[2]);
     const R sv[3] = {sf * t[0], sf * t[1], sf * t[2]};
     const R pp[3] = {pm[0] + pm[1] * t[2] - pm[2] * t[1], pm[1] + pm[2] * t[0] - pm[0] * t[2],
                      pm[2] + pm[0] * t[1] - pm[1] * t[0]};
@@ -706,20 +730,20 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
       // an incremental sort writes within the same buffer, into slots no
       // work item of this pass reads (free or overflow slots)
       const Parts<R>& out = move ? src : dst;
-      pst<NT>(&out.cell[d], cw);
-      pst<NT>(&out.fx[d], fx);
-      pst<NT>(&out.fr[d], fr);
-      pst<NT>(&out.th[d], th);
-      pst<NT>(&out.px[d], pv[0]);
-      pst<NT>(&out.py[d], pv[1]);
-      pst<NT>(&out.pz[d], pv[2]);
-      pst<NT>(&out.w[d], w);
-      pst<NT>(&out.id[d], pld<NT>(&src.id[p]));
-      if (move && !fill_item) src.cell[p] = kDead;  // its old slot
+      pst<NT>(elem(out.cell, d), cw);
+      pst<NT>(elem(out.fx, d), fx);
+      pst<NT>(elem(out.fr, d), fr);
+      pst<NT>(elem(out.th, d), th);
+      pst<NT>(elem(out.px, d), pv[0]);
+      pst<NT>(elem(out.py, d), pv[1]);
+      pst<NT>(elem(out.pz, d), pv[2]);
+      pst<NT>(elem(out.w, d), w);
+      pst<NT>(elem(out.id, d), pld<NT>(elem(src.id, p)));
+      if (move && !fill_item) *elem(src.cell, p) = kDead;  // its old slot
     } else {
-      pst<NT>(&src.px[p], pv[0]);
-      pst<NT>(&src.py[p], pv[1]);
-      pst<NT>(&src.pz[p], pv[2]);
+      pst<NT>(elem(src.px, p), pv[0]);
+      pst<NT>(elem(src.py, p), pv[1]);
+      pst<NT>(elem(src.pz, p), pv[2]);
     }
   }
   if (bad) atomicOr(err, ERR_HALO);
@@ -732,7 +756,7 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
     typename Acc0<R>::T v = sm.chi[k];
     // order 2: the row below the axis (two LDS rows down) belongs to row 1
     if (O == 2 && j == 1 && b >= 2) v += sm.chi[k - 2];
-    if (v == 0) continue;
+    if (!Acc0<R>::nonzero(v)) continue;
     if (rel < 0 || rel > g.nx || j < 0 || j > g.nr) continue;
     atomicAdd(&chi_out[(size_t)phys_col(g, rel) * g.pitch + j], (R)(Acc0<R>::val(v, g) * sm.ivol[b]));
   }
@@ -1113,7 +1137,8 @@ __device__ inline void zero_pos_acc(SmemPos<R, M1>& sm) {
   if (threadIdx.x < 11) sm.tcnt[threadIdx.x] = 0;
 }
 
-// a + sg b of two mode-1 accumulator words (exact for the fixed point)
+// a + sg b of two mode-1 accumulator words (exact for the fixed point, whose
+// words add modulo 2^64)
 template <class T> __device__ inline T acc_axpy(T a, const T& b, int sg) {
   a.x += sg * b.x;
   a.y += sg * b.y;
@@ -1140,8 +1165,8 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
       typename Acc0<R>::T vjx = sm.jx[k], vjr = sm.jr[k];
       if (fold_row) vjx += sm.jx[k - 2];
       if (fold_face) vjr -= sm.jr[k - 1];
-      if (dxok && vjx != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(vjx, g) * sm.iax[b]));
-      if (drok && vjr != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(vjr, g) * sm.iar[b]));
+      if (dxok && Acc0<R>::nonzero(vjx)) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(vjx, g) * sm.iax[b]));
+      if (drok && Acc0<R>::nonzero(vjr)) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(vjr, g) * sm.iar[b]));
       if (M1) {
         using A = Acc1<R>;
         typename A::T v1x = sm.jx1[k], v1t = sm.jt1[k];
@@ -1163,8 +1188,8 @@ __device__ inline void flush_current(SmemPos<R, M1>& sm, const Region& q, const 
         }
       }
     } else {
-      if (dxok && sm.jx[k] != 0) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(sm.jx[k], g) * sm.iax[b]));
-      if (drok && sm.jr[k] != 0) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(sm.jr[k], g) * sm.iar[b]));
+      if (dxok && Acc0<R>::nonzero(sm.jx[k])) atomicAdd(&jx_out[o], (R)(Acc0<R>::val(sm.jx[k], g) * sm.iax[b]));
+      if (drok && Acc0<R>::nonzero(sm.jr[k])) atomicAdd(&jr_out[o], (R)(Acc0<R>::val(sm.jr[k], g) * sm.iar[b]));
       if (M1) {
         using A = Acc1<R>;
         if (dxok && A::nonzero(sm.jx1[k])) {
@@ -1411,14 +1436,14 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
   auto fetch = [&](int k) {
     Rec r;
     const int p = start + k;
-    r.cw = pld<NT>(&P.cell[p]);
-    r.fx = pld<NT>(&P.fx[p]);
-    r.fr = pld<NT>(&P.fr[p]);
-    r.th = pld<NT>(&P.th[p]);
-    r.w = pld<NT>(&P.w[p]);
-    r.px = pld<NT>(&P.px[p]);
-    r.py = pld<NT>(&P.py[p]);
-    r.pz = pld<NT>(&P.pz[p]);
+    r.cw = pld<NT>(elem(P.cell, p));
+    r.fx = pld<NT>(elem(P.fx, p));
+    r.fr = pld<NT>(elem(P.fr, p));
+    r.th = pld<NT>(elem(P.th, p));
+    r.w = pld<NT>(elem(P.w, p));
+    r.px = pld<NT>(elem(P.px, p));
+    r.py = pld<NT>(elem(P.py, p));
+    r.pz = pld<NT>(elem(P.pz, p));
     return r;
   };
   Rec nxt;
@@ -1446,12 +1471,12 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
     Move<R> mv;
     push_position<R>(g, cw, fx, fr, th, py, pz, px * ig, py * ig, pz * ig, mv);
     if (mv.refl) {
-      P.py[p] = py;
-      P.pz[p] = pz;
+      *elem(P.py, p) = py;
+      *elem(P.pz, p) = pz;
     }
     const long long reln = (long long)mv.ix1 - g.shift;
     if (reln < 0 || reln >= g.nx) {
-      P.cell[p] = kDead;  // left the window: removed without deposit
+      *elem(P.cell, p) = kDead;  // left the window: removed without deposit
       atomicAdd(&sm.tcnt[9], 1);
       continue;
     }
@@ -1466,12 +1491,12 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
     } else {
       deposit_current<R, M1>(sm, q, g, mv, w, bad);
     }
-    pst<NT>(&P.cell[p], pack_cell(mv.ix1, mv.jr1));
-    pst<NT>(&P.fx[p], mv.fx1);
-    pst<NT>(&P.fr[p], mv.fr1);
-    pst<NT>(&P.th[p], mv.th1);
+    pst<NT>(elem(P.cell, p), pack_cell(mv.ix1, mv.jr1));
+    pst<NT>(elem(P.fx, p), mv.fx1);
+    pst<NT>(elem(P.fr, p), mv.fr1);
+    pst<NT>(elem(P.th, p), mv.th1);
     if (vacate && reln < 1) {
-      if (!DEFER) P.cell[p] = kDead;  // vacated column: dropped after depositing
+      if (!DEFER) *elem(P.cell, p) = kDead;  // vacated column: dropped after depositing
       atomicAdd(&sm.tcnt[9], 1);
       continue;
     }

@@ -67,6 +67,7 @@ def test_footprint_sizes(E):
     dict(a0=float("nan")),
     dict(profile="perturb", perturb=1.5),
     dict(capacity=-5),
+    dict(capacity=2**30),          # slots must stay below 2^30 (32-bit byte offsets)
 ])
 def test_validation_rejects(E, bad):
     from inputs import C1, scaled
