@@ -819,7 +819,7 @@ __device__ inline void push_position(const Geo& g, unsigned cw, R fx, R fr, R th
   mv.vy = vy;
   mv.vz = vz;
   mv.ix1 = mv.ix0;
-  mv.fx1 = fx + dt * vx * (R)(1.0 / g.dx);
+  mv.fx1 = fx + vx * (R)(g.dt / g.dx);
   carry(mv.ix1, mv.fx1);
   R s, c;
   sincos_r(th, &s, &c);
@@ -883,18 +883,20 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
   typename A0::T* jr = &sm.jr[amin * LR + bmin];
   const double hw = 0.5 * (double)w * A0::scale(g);
   const double cx0d = cx0, cx1d = cx1, cr0d = cr0, cr1d = cr1;
+  // the second partial sum is non-zero only when the particle changed
+  // column (row); a zero first one adds nothing
 #pragma unroll
   for (int bb = 0; bb < 3; ++bb) {
     const double sr = (double)(S0r[bb] + S1r[bb]) * hw;
-    if (cx0 != (R)0) A0::add_prod(&jx[bb], cx0d, sr);
-    if (cx1 != (R)0) A0::add_prod(&jx[LR + bb], cx1d, sr);
+    A0::add_prod(&jx[bb], cx0d, sr);
+    if (dxs != 0) A0::add_prod(&jx[LR + bb], cx1d, sr);
   }
   // J_r (i, j+1/2): flux accumulated along r
 #pragma unroll
   for (int aa = 0; aa < 3; ++aa) {
     const double sx = (double)(S0x[aa] + S1x[aa]) * hw;
-    if (cr0 != (R)0) A0::add_prod(&jr[aa * LR], cr0d, sx);
-    if (cr1 != (R)0) A0::add_prod(&jr[aa * LR + 1], cr1d, sx);
+    A0::add_prod(&jr[aa * LR], cr0d, sx);
+    if (drs != 0) A0::add_prod(&jr[aa * LR + 1], cr1d, sx);
   }
   if (M1) {
     // Cartesian mid-point of the old and new positions: in the frame of the
@@ -909,9 +911,10 @@ __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, cons
       R cd, sd;
       if (u > (R)0) {
         const R beta = v * rcp_r(u);
-        const R qq = sqrt_r((R)1 + beta * beta);
+        const R q2b = (R)1 + beta * beta;
+        cd = rsqrt_r(q2b);  // 1 / sqrt(1 + beta^2)
+        const R qq = q2b * cd;
         frm = mv.fr0 + ((R)0.5 * mv.a + u * beta * beta * rcp_r((R)1 + qq)) * (R)(1.0 / g.dr);
-        cd = rcp_r(qq);
         sd = beta * cd;
       } else {
         const R rm = sqrt_r(u * u + v * v);
@@ -1040,9 +1043,10 @@ __device__ inline void deposit_current2(SmemPos<R, M1>& sm, const Region& q, con
       R cd, sd;
       if (u > (R)0) {
         const R beta = v * rcp_r(u);
-        const R qq = sqrt_r((R)1 + beta * beta);
+        const R q2b = (R)1 + beta * beta;
+        cd = rsqrt_r(q2b);  // 1 / sqrt(1 + beta^2)
+        const R qq = q2b * cd;
         frm = mv.fr0 + ((R)0.5 * mv.a + u * beta * beta * rcp_r((R)1 + qq)) * (R)(1.0 / g.dr);
-        cd = rcp_r(qq);
         sd = beta * cd;
       } else {
         const R rm = sqrt_r(u * u + v * v);
@@ -1474,8 +1478,8 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
       *elem(P.py, p) = py;
       *elem(P.pz, p) = pz;
     }
-    const long long reln = (long long)mv.ix1 - g.shift;
-    if (reln < 0 || reln >= g.nx) {
+    const int reln = mv.ix1 - (int)g.shift;  // (lab columns stay below COL_MAX)
+    if ((unsigned)reln >= (unsigned)g.nx) {
       *elem(P.cell, p) = kDead;  // left the window: removed without deposit
       atomicAdd(&sm.tcnt[9], 1);
       continue;
