@@ -225,13 +225,16 @@ int envpic_set_field(envpic_sim* s, int field, const double* in);
 
 /* step counter, window shift (cells) and live particle count */
 int envpic_state(const envpic_sim* s, int64_t* n, int64_t* shift, int64_t* n_particles);
-/* How the particle sorts ran so far (synchronous), out[3]: the sorts that
+/* How the particle sorts ran so far (synchronous), out[4]: the sorts that
  * rebuilt the layout ordered by cell (every 8th sort, into the other
  * particle buffer); the tile sorts that moved only the particles that
  * changed tile; the tile sorts whose scan found too few free slots, too
  * little overflow room or too few work items and rebuilt the layout instead
- * (every particle scattered and copied back: correct, slower).  The counts
- * start at envpic_sim_init. */
+ * (every particle scattered and copied back: correct, slower); the cell
+ * sorts whose cell-ordered copy was gathered slot by slot after the momentum
+ * pass (chosen once the particles have moved enough that the pass's direct
+ * scatter writes partial cache lines; the same result).  The counts start at
+ * envpic_sim_init. */
 int envpic_sort_stats(const envpic_sim* s, int64_t* out);
 /* Particles ordered by id; each pointer may be NULL to skip that array;
  * arrays hold n_particles entries. */

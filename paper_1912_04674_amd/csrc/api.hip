@@ -51,11 +51,15 @@ Sizes sizes_of(const envpic_params& p) {
   s.ppc = p.ppc_x * p.ppc_r * p.ppc_t;
   const long long window = (long long)p.nx * p.nr * s.ppc;
   // one window of particles, overflow ranges for particles that change
-  // tile (1/16 of them), room for the tiles about to enter a moving window,
-  // and the columns injected until the layout is rebuilt
+  // tile (1/4 of them: an incremental sort moves the earlier overflow again
+  // with the new arrivals, so the ranges grow over the tile sorts between
+  // two cell sorts; with 1/16 the late LWFA wake ran out of them and rebuilt
+  // the layout about once per cell-sort cycle), room for the tiles about to
+  // enter a moving window, and the columns injected until the layout is
+  // rebuilt
   const long long column = (long long)p.nr * s.ppc;
   s.capacity = p.capacity > 0 ? p.capacity
-                              : window + window / 16 + (long long)(ENTERING_TILES + 1) * TX * column +
+                              : window + window / 4 + (long long)(ENTERING_TILES + 1) * TX * column +
                                     (SORT_EVERY * (CELL_SORT_EVERY + 1LL) + 1) * column + 1024;
   // work-item size: about four items per compute unit (256 of them) so that
   // small runs fill the device, at most CHUNK, a multiple of WG
@@ -148,7 +152,7 @@ template <class R> struct State {
   Layout lay[2];
   int* hist;    // particles per tile at the next sort
   int* arr;     // particles arriving from other tiles at the next (tile) sort
-  int* sort_stats;  // [incremental, rebuilt] layouts of the tile sorts
+  int* sort_stats;  // [incremental, rebuilt] layouts of the tile sorts, gathered cell sorts
   int* ccount;  // particles per cell at the next sort ([phys col][row], as the grids)
   int* ccur;    // per-cell scatter cursors of the next sort
   int* err;
@@ -248,7 +252,7 @@ template <class R> size_t plan(const envpic_params& p, const Sizes& s, bool fp64
   }
   S.hist = cv.take<int>((size_t)s.ntiles);
   S.arr = cv.take<int>((size_t)s.ntiles);
-  S.sort_stats = cv.take<int>(2);
+  S.sort_stats = cv.take<int>(3);
   S.ccount = cv.take<int>(ng);
   S.ccur = cv.take<int>(ng);
   S.err = cv.take<int>(1);
@@ -440,7 +444,7 @@ struct envpic_sim {
   virtual int poison(int f) = 0;
   virtual int check_err() = 0;
   virtual int clear_deposits() = 0;
-  virtual int sort_counts(int64_t* incremental, int64_t* rebuilt) = 0;
+  virtual int sort_counts(int64_t* incremental, int64_t* rebuilt, int64_t* gathered) = 0;
 
   // the momentum stage of the next step re-sorts the particles
   // Steps between sorts: particles drift at most one cell per step, and the
@@ -626,12 +630,13 @@ template <class R> struct SimT : envpic_sim {
     return hip_check(hipStreamSynchronize(stream), "clear deposits");
   }
 
-  int sort_counts(int64_t* incremental, int64_t* rebuilt) override {
-    int c[2] = {0, 0};
+  int sort_counts(int64_t* incremental, int64_t* rebuilt, int64_t* gathered) override {
+    int c[3] = {0, 0, 0};
     int rc = hip_check(hipMemcpyAsync(c, S.sort_stats, sizeof c, hipMemcpyDeviceToHost, stream), "sort counts");
     if (rc || (rc = hip_check(hipStreamSynchronize(stream), "sync"))) return rc;
     *incremental = c[0];
     *rebuilt = c[1];
+    *gathered = c[2];
     return ENVPIC_OK;
   }
 
@@ -658,8 +663,9 @@ template <class R> struct SimT : envpic_sim {
     // other buffer); the others move only the particles that changed tile
     const int mode = !scatter ? SCAT_NONE : (n_sorts % CELL_SORT_EVERY == 0 ? SCAT_CELL : SCAT_TILE);
     const KEvents ev = tick_events();
+    // (the position scratch's cell words are free until the position stage)
     launch_momentum<R>(g, S.grids, S.dep[d].chi, S.parts[cur], S.parts[1 - cur], S.lay[lay], S.lay[1 - lay], S.ccur,
-                       S.scr.w, S.err, sz.max_items, defer, mode, stream, ev);
+                       S.scr.w, S.scr.cell, S.err, sz.max_items, defer, mode, stream, ev);
     tick_end(0, ev);
     if (scatter) {
       if (mode == SCAT_CELL) {
@@ -1277,7 +1283,7 @@ int envpic_set_field(envpic_sim* s, int field, const double* in) {
 int envpic_sort_stats(const envpic_sim* s, int64_t* out) {
   if (!s || !out) return fail(ENVPIC_EINVAL, "NULL argument");
   out[0] = s->n_cell_sorts;
-  return const_cast<envpic_sim*>(s)->sort_counts(&out[1], &out[2]);
+  return const_cast<envpic_sim*>(s)->sort_counts(&out[1], &out[2], &out[3]);
 }
 
 int envpic_state(const envpic_sim* s, int64_t* n, int64_t* shift, int64_t* n_particles) {

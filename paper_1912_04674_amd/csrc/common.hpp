@@ -49,6 +49,9 @@ constexpr int CELL_SORT_EVERY = 8;
 // the layout a scan produced for a tile sort: incremental, or every particle
 // scattered (not enough free slots, overflow room or work items)
 constexpr int LAYOUT_MOVE = 0, LAYOUT_FULL = 1;
+// flag of a cell-sort layout: the cell-ordered copy is gathered (k_permute)
+// instead of scattered by the momentum pass
+constexpr int LAYOUT_GATHER = 2;
 // Tile columns ahead of a moving window whose segments get room for a full
 // tile when the layout is rebuilt (the window enters at most one column per
 // step, SORT_EVERY * CELL_SORT_EVERY steps between rebuilds), with the tile
@@ -147,7 +150,7 @@ struct Layout {
 // The copy back after a tile sort that rebuilt its layout (settle_copy):
 // from the other buffer into the one in use, over the used slots of L, by
 // `blocks` extra groups of the launch that carries it (none: 0)
-constexpr int SETTLE_BLOCKS = 256;
+constexpr int SETTLE_BLOCKS = 256;  // groups of 256 threads (they exit at once when no copy is due)
 template <class R> struct SettleArgs {
   Parts<R> to, from;
   Layout L;

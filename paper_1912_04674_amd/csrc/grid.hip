@@ -383,12 +383,26 @@ __global__ __launch_bounds__(SCAN_T) void k_layout_scan(FieldArgs fa) {
   __shared__ int s_w[SCAN_T / 64];
   bump_pending(fa.gn, fa.in, fa.pending);
   __syncthreads();
-  if (fa.presort == SCAT_CELL)
+  if (fa.presort == SCAT_CELL) {
     full_layout<SCAN_T>(fa.gn, fa.hist, fa.out, fa.capacity, fa.inj_max, fa.reserve, fa.entering, fa.max_items,
                         fa.err, s_w);
-  else
+    // The cell order is gathered once the overflow ranges used since the last
+    // rebuild exceed 1/32 of the segments: the particles have moved, and a
+    // direct scatter of whole records from the momentum pass would write
+    // partial cache lines of every record array.  While the particles are
+    // still close to cell order the pass scatters them directly (cheaper).
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const long long seg = fa.in.offsets[fa.gn.ntiles], over = (long long)*fa.in.fill - seg;
+      if (over * 32 > seg) {
+        *fa.out.mode = LAYOUT_FULL | LAYOUT_GATHER;
+        fa.stats[2] += 1;
+      }
+    }
+  } else {
     move_layout<SCAN_T>(fa.gn, fa.hist, fa.arr, fa.in, fa.out, fa.capacity, fa.inj_max, fa.reserve, fa.entering,
                         fa.max_items, fa.err, fa.stats, s_w);
+  }
 }
 
 // ---------------------------------------------------- initial envelope --

@@ -30,11 +30,12 @@ template <class R> struct DepositBufs {
 };
 
 // scatter (SCAT_*): re-sort into the layout Ld, by tile (cursors of Ld) or
-// by cell (per-cell cursors ccur)
+// by cell (per-cell cursors ccur); inv (one word per slot) holds the cell
+// order's source slots between the pass and the copy that follows it
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                     const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
-                     int scatter, hipStream_t st, const KEvents& ev = KEvents{});
+                     const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, unsigned* inv, int* err, int grid,
+                     bool defer, int scatter, hipStream_t st, const KEvents& ev = KEvents{});
 // the plasma of the column entering the window at this step's shift,
 // loaded by extra work groups of the position pass (blocks == 0: none)
 struct InjectArgs {
@@ -98,7 +99,7 @@ struct FieldArgs {
   int inj_max, max_items;
   int* pending;
   int* err;
-  int* stats;                  // [incremental, rebuilt] tile-sort layouts
+  int* stats;                  // [incremental, rebuilt] tile-sort layouts, gathered cell sorts
 };
 // E^{n+1}, B^{n+3/2}, Bbar^{n+1} into the second E/B copies (the caller
 // swaps them), the next deposits cleared, the window's column resets (if

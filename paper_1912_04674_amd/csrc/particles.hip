@@ -413,7 +413,8 @@ template <class R, bool M1, bool DEFER, int SCAT, int O, bool NT>
 __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void k_momentum(
     Geo g, Grids<R> f, R* __restrict__ chi_out,
                                                  Parts<R> src, Parts<R> dst, Layout Ls, Layout Ld,
-                                                 int* __restrict__ ccur, R* __restrict__ gscr, int* err) {
+                                                 int* __restrict__ ccur, R* __restrict__ gscr,
+                                                 unsigned* __restrict__ inv, int* err) {
   using C = typename cplx_of<R>::type;
   constexpr int H = (SCAT == SCAT_NONE && !DEFER) ? HALO - 1 : HALO;
   constexpr int RX = Halo<H>::X, RL = Halo<H>::R, RN = Halo<H>::N;
@@ -496,6 +497,8 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
   // particles are unrolled).  Without the scatter only the live flag is kept.
   // An incremental tile sort ranks the particles that change tile only.
   const bool move = SCAT == SCAT_TILE && *Ld.mode == LAYOUT_MOVE;
+  // a cell sort whose copy is gathered afterwards (k_permute)
+  const bool gather = SCAT == SCAT_CELL && !DEFER && (*Ld.mode & LAYOUT_GATHER) != 0;
   // the particles of an item past the segments all join their tiles' segments
   const bool fill_item = start >= Ls.offsets[g.ntiles];
   constexpr int STAY = 1 << 30;  // slot_rank of a particle that keeps its slot
@@ -726,7 +729,14 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
           Acc0<R>::add_prod(&sm.chi[(Px.i + aa) * RL + Pr.i + bb], wa, (double)(bb ? Pr.b : Pr.a));
       }
     }
-    if (SCAT != SCAT_NONE && !stay) {
+    if (gather) {
+      // the cell-ordered copy is gathered afterwards (k_permute): p is
+      // updated in place and the destination slot records where it comes from
+      pst<NT>(elem(src.px, p), pv[0]);
+      pst<NT>(elem(src.py, p), pv[1]);
+      pst<NT>(elem(src.pz, p), pv[2]);
+      *elem(inv, d) = (unsigned)p;
+    } else if (SCAT != SCAT_NONE && !stay) {
       // an incremental sort writes within the same buffer, into slots no
       // work item of this pass reads (free or overflow slots)
       const Parts<R>& out = move ? src : dst;
@@ -1634,65 +1644,126 @@ __global__ void k_init_particles(Geo g, Plasma pl, Parts<R> P, const int* __rest
   for (int k = 0; k < ppc; ++k) load_particle<R>(g, pl, P, offsets[key], local * ppc, tct * trt * ppc, col, j, k);
 }
 
+// ====================================================== cell-sort copy ==
+// The cell-ordered copy of a cell sort whose layout carries LAYOUT_GATHER:
+// slot s of the new layout's work items takes the record of slot inv[s] of
+// the buffer in use (the momentum pass wrote inv and updated p there).  One group per item moves one record
+// array after the other, so the reads of a group stay within its tile's few
+// tens of kilobytes of that array (cached in the L2) and every store is
+// contiguous.  A direct scatter of whole records from the momentum pass
+// wrote partial cache lines across every array of a tile at once once the
+// particles had moved (measured: 2.5x its bytes written, 650 us for the
+// cell sort late in the LWFA run).  A slot whose source index is not valid
+// (possible only after a count mismatch, which the pass flags) gets a
+// removed particle.
+template <bool NT, int PPT, class T>
+__device__ inline void gather_array(T* __restrict__ to, const T* __restrict__ from, const unsigned* sp, int start,
+                                    int count, T none) {
+  T v[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int k = threadIdx.x + u * WG;
+    v[u] = (k < count && sp[u] != ~0u) ? *elem(from, (int)sp[u]) : none;
+  }
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int k = threadIdx.x + u * WG;
+    if (k < count) pst<NT>(elem(to, start + k), v[u]);
+  }
+}
+template <class R, bool NT>
+__global__ __launch_bounds__(WG) void k_permute(Parts<R> src, Parts<R> dst, Layout L, const unsigned* __restrict__ inv,
+                                                long long cap) {
+  constexpr int PPT = CHUNK / WG;
+  if ((*L.mode & LAYOUT_GATHER) == 0) return;  // the momentum pass scattered the records
+  const int item = item_of(blockIdx.x, gridDim.x);
+  if (item >= *L.n_items) return;
+  const int4 it = L.items[item];
+  const int start = it.y, count = it.z;  // count <= chunk <= CHUNK
+  unsigned sp[PPT];
+#pragma unroll
+  for (int u = 0; u < PPT; ++u) {
+    const int k = threadIdx.x + u * WG;
+    const unsigned v = k < count ? *elem(inv, start + k) : ~0u;
+    sp[u] = (long long)v < cap ? v : ~0u;
+  }
+  gather_array<NT, PPT>(dst.cell, src.cell, sp, start, count, kDead);
+  gather_array<NT, PPT>(dst.fx, src.fx, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.fr, src.fr, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.th, src.th, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.px, src.px, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.py, src.py, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.pz, src.pz, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.w, src.w, sp, start, count, (R)0);
+  gather_array<NT, PPT>(dst.id, src.id, sp, start, count, 0u);
+}
+
 // ============================================================ launchers ==
 template <class R, bool M1, bool DEFER, int SCAT, int O, bool NT>
 static void launch_momentum_k(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                              const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int max_items,
-                              hipStream_t st, const KEvents& ev) {
+                              const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, unsigned* inv, int* err,
+                              int max_items, hipStream_t st, const KEvents& ev) {
   launch_k(k_momentum<R, M1, DEFER, SCAT, O, NT>, dim3(max_items), dim3(WG), st, ev, g, f, chi, src, dst, Ls, Ld,
-           ccur, gscr, err);
+           ccur, gscr, inv, err);
 }
 template <class R, bool M1, bool DEFER, int O, bool NT>
 static void launch_momentum_nt(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                               const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
-                               int scatter, hipStream_t st, const KEvents& ev) {
+                               const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, unsigned* inv, int* err,
+                               int grid, int scatter, hipStream_t st, const KEvents& ev) {
   if (scatter == SCAT_TILE && DEFER) {
     // the deferred chi deposit reads the particles before the envelope stage
-    launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st,
+    launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, st,
                                                       KEvents{ev.start, nullptr});
     launch_k(k_settle<R>, dim3(SETTLE_BLOCKS), dim3(256), st, KEvents{nullptr, ev.stop},
              SettleArgs<R>{src, dst, Ld, g.cap, SETTLE_BLOCKS});
   } else if (scatter == SCAT_TILE) {
     // (the envelope stage carries the copy back)
-    launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
+    launch_momentum_k<R, M1, DEFER, SCAT_TILE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, st, ev);
+  } else if (scatter == SCAT_CELL && !DEFER) {
+    // the pass scatters the records, or records their destinations for the
+    // gather that follows (the layout scan chose)
+    launch_momentum_k<R, M1, DEFER, SCAT_CELL, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, st,
+                                                      KEvents{ev.start, nullptr});
+    launch_k(k_permute<R, NT>, dim3(grid), dim3(WG), st, KEvents{nullptr, ev.stop}, src, dst, Ld,
+             (const unsigned*)inv, g.cap);
   } else if (scatter == SCAT_CELL) {
-    launch_momentum_k<R, M1, DEFER, SCAT_CELL, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
+    launch_momentum_k<R, M1, DEFER, SCAT_CELL, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, st, ev);
   } else {
-    launch_momentum_k<R, M1, DEFER, SCAT_NONE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, st, ev);
+    launch_momentum_k<R, M1, DEFER, SCAT_NONE, O, NT>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, st, ev);
   }
 }
 // non-temporal record access for the fused passes of large runs only
 template <class R, bool M1, bool DEFER, int O>
 static void launch_momentum_sc(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                               const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid,
-                               int scatter, hipStream_t st, const KEvents& ev) {
+                               const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, unsigned* inv, int* err,
+                               int grid, int scatter, hipStream_t st, const KEvents& ev) {
   if (!DEFER && g.stream_parts)
-    launch_momentum_nt<R, M1, DEFER, O, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+    launch_momentum_nt<R, M1, DEFER, O, true>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
   else
-    launch_momentum_nt<R, M1, DEFER, O, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+    launch_momentum_nt<R, M1, DEFER, O, false>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
 }
 
 // order 2 has no deferred-deposit variant (the library rejects the request)
 template <class R>
 void launch_momentum(const Geo& g, const Grids<R>& f, R* chi, const Parts<R>& src, const Parts<R>& dst,
-                     const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, int* err, int grid, bool defer,
-                     int scatter, hipStream_t st, const KEvents& ev) {
+                     const Layout& Ls, const Layout& Ld, int* ccur, R* gscr, unsigned* inv, int* err, int grid,
+                     bool defer, int scatter, hipStream_t st, const KEvents& ev) {
   if (grid <= 0) return;
   if (g.order == 2) {
     if (g.modes >= 2)
-      launch_momentum_sc<R, true, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+      launch_momentum_sc<R, true, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
     else
-      launch_momentum_sc<R, false, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+      launch_momentum_sc<R, false, false, 2>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
   } else if (g.modes >= 2) {
     if (defer)
-      launch_momentum_sc<R, true, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+      launch_momentum_sc<R, true, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
     else
-      launch_momentum_sc<R, true, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+      launch_momentum_sc<R, true, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
   } else {
     if (defer)
-      launch_momentum_sc<R, false, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+      launch_momentum_sc<R, false, true, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
     else
-      launch_momentum_sc<R, false, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, err, grid, scatter, st, ev);
+      launch_momentum_sc<R, false, false, 1>(g, f, chi, src, dst, Ls, Ld, ccur, gscr, inv, err, grid, scatter, st, ev);
   }
 }
 
@@ -1769,8 +1840,8 @@ void launch_init_particles(const Geo& g, const Plasma& pl, const Parts<R>& P, co
 
 #define ENVPIC_INST(R)                                                                                          \
   template void launch_momentum<R>(const Geo&, const Grids<R>&, R*, const Parts<R>&, const Parts<R>&,           \
-                                   const Layout&, const Layout&, int*, R*, int*, int, bool, int, hipStream_t,   \
-                                   const KEvents&);                                                             \
+                                   const Layout&, const Layout&, int*, R*, unsigned*, int*, int, bool, int,     \
+                                   hipStream_t, const KEvents&);                                                \
   template void launch_position<R>(const Geo&, const Grids<R>&, const DepositBufs<R>&, const Parts<R>&,         \
                                    const Layout&, const SortCounts&, int, const Parts<R>&, int*, int, bool,     \
                                    const InjectArgs&, hipStream_t, const KEvents&);                             \

@@ -236,12 +236,35 @@ __device__ inline void move_layout(const Geo& g, int* hist, int* arr, Layout in,
 // After a tile sort whose scan rebuilt the layout (LAYOUT_FULL), the sort
 // wrote every particle into the other buffer: copy the used slots back (b of
 // nb groups of 256 threads), so that the particles stay in the buffer they
-// were in.  Nothing to do after an incremental sort.
+// were in.  Nothing to do after an incremental sort.  Each lane moves four
+// consecutive slots of every record array per pass with 16-byte accesses
+// (the arrays start 256-byte aligned), so that enough bytes are in flight to
+// stream at the copy rate; the slots past the last multiple of four go one
+// by one.
+template <class T> __device__ inline void copy4(T* to, const T* from, long long i) {
+  static_assert(sizeof(T) == 4, "4-byte record arrays");
+  *reinterpret_cast<uint4*>(to + i) = *reinterpret_cast<const uint4*>(from + i);
+}
 template <class R>
 __device__ inline void settle_copy(const SettleArgs<R>& sa, int b, int nb) {
   if (*sa.L.mode != LAYOUT_FULL) return;
   const long long n = min((long long)*sa.L.fill, sa.cap);
-  for (long long i = (long long)b * 256 + threadIdx.x; i < n; i += (long long)nb * 256) {
+  const long long n4 = n & ~3LL;
+  if constexpr (sizeof(R) == 4) {
+    for (long long i = ((long long)b * 256 + threadIdx.x) * 4; i < n4; i += (long long)nb * 256 * 4) {
+      copy4(sa.to.cell, sa.from.cell, i);
+      copy4(sa.to.fx, sa.from.fx, i);
+      copy4(sa.to.fr, sa.from.fr, i);
+      copy4(sa.to.th, sa.from.th, i);
+      copy4(sa.to.px, sa.from.px, i);
+      copy4(sa.to.py, sa.from.py, i);
+      copy4(sa.to.pz, sa.from.pz, i);
+      copy4(sa.to.w, sa.from.w, i);
+      copy4(sa.to.id, sa.from.id, i);
+    }
+  }
+  const long long i0 = sizeof(R) == 4 ? n4 : 0;
+  for (long long i = i0 + (long long)b * 256 + threadIdx.x; i < n; i += (long long)nb * 256) {
     sa.to.cell[i] = sa.from.cell[i];
     sa.to.fx[i] = sa.from.fx[i];
     sa.to.fr[i] = sa.from.fr[i];

@@ -240,10 +240,11 @@ class Sim:
         """How the particle sorts ran: {"cell": sorts that rebuilt the layout
         ordered by cell, "incremental": tile sorts that moved only the
         particles that changed tile, "rebuilt": tile sorts that found no room
-        and rebuilt the layout}."""
-        out = (ctypes.c_int64 * 3)()
+        and rebuilt the layout, "gathered": cell sorts whose copy in cell
+        order was gathered after the momentum pass}."""
+        out = (ctypes.c_int64 * 4)()
         _check(lib().envpic_sort_stats(self._h, out))
-        return {"cell": out[0], "incremental": out[1], "rebuilt": out[2]}
+        return {"cell": out[0], "incremental": out[1], "rebuilt": out[2], "gathered": out[3]}
 
     def get_field(self, name):
         shape = (self.nx + 1, self.nr + 1)

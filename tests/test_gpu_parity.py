@@ -291,6 +291,33 @@ def test_incremental_and_rebuilt_tile_sorts(E, oracle_mod, room, prec, tf, tp):
     compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
 
 
+@pytest.mark.parametrize("prec,tf,tp", PRECS)
+def test_gathered_cell_sort(E, oracle_mod, prec, tf, tp):
+    """A warm plasma (momenta up to 0.5 in each direction) with room for a
+    lot of overflow: a tenth of the particles changes tile at every tile
+    sort, the overflow ranges pass 1/32 of the segments before the second
+    cell sort (step 27), and that sort copies the cell order by a gather
+    after the momentum pass (the first, at step 3, still scatters).  Thirty
+    steps against the oracle."""
+    cfg = dict(nx=96, nr=32, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=0.0, ppc=(1, 1, 1),
+               capacity=200_000)
+    say("gathered cell sort", prec)
+    parts = random_particles(cfg, 20_000, seed=2717, margin=4, pmax=0.5)
+    g = E.Sim(cfg, _prec(E, prec))
+    r = oracle_mod.OracleSim(cfg)
+    g.set_particles(parts)
+    r.set_particles(parts)
+    g.step(30)
+    r.step(30)
+    st = g.sort_stats()
+    say("sort stats", st)
+    assert st["cell"] == 2 and st["rebuilt"] == 0
+    assert st["gathered"] == 1
+    assert g.state() == r.state()
+    compare_fields(g, r, tf, names=("chi", "ex", "er", "bt", "jx", "jr"), modes=2)
+    compare_particles(g.get_particles(), r.get_particles(), tp, 1e-8 if prec == "fp64" else 1e-3)
+
+
 DIAG_KEYS = ("count", "charge", "chi_v", "kin", "uem", "env2_v", "lx", "px", "nonfinite")
 
 
