@@ -654,12 +654,13 @@ def test_tile_scatter_to_many_destinations(E, oracle_mod, prec, tf, tp):
 
 
 def test_fixed_point_sums_at_full_work_items(E, oracle_mod):
-    """The FP32 path's 64-bit fixed-point deposit sums at their bound: a
-    window of 4.2 M particle slots gives work items of 4096 particles, and
-    50 000 electrons of one weight share the axis cell (the smallest node
-    volume, which sets the scale) moving radially at 0.98 c, so every work
-    item adds 4096 contributions near the largest one (2^49) to the same LDS
-    words, about 2^61.  Three steps against the oracle at the FP32 bars."""
+    """The FP32 path's fixed-point deposit sums at their bound: a window of
+    4.2 M particle slots gives work items of 4096 particles, and 50 000
+    electrons of one weight share the axis cell (the smallest node volume,
+    which sets the scale) moving radially at 0.98 c, so every work item adds
+    4096 contributions near the largest one (2^32) to the same LDS words,
+    about 2^44 of the 2^47 that the words' low 48 bits hold.  Three steps
+    against the oracle at the FP32 bars."""
     cfg = dict(nx=256, nr=64, dx=0.8, dr=1.5, dt=0.6, n_modes=2, profile="none", a0=0.0, ppc=(4, 4, 16))
     say("fixed-point bound, 4096-particle work items")
     rng = np.random.default_rng(4096)
