@@ -870,11 +870,14 @@ __device__ inline void push_position(const Geo& g, unsigned cw, R fx, R fr, R th
 template <class R, bool M1>
 __device__ inline void deposit_current(SmemPos<R, M1>& sm, const Region& q, const Geo& g, const Move<R>& mv, R w,
                                        bool& bad) {
-  // the stencil spans min(a0, a1) .. min(a0, a1) + 2 (at most one cell moved)
+  // the stencil spans min(a0, a1) .. min(a0, a1) + 2: the push moves a
+  // particle less than a cell (dt < dx and dt < dr, checked at init), so the
+  // new cell is the old one's neighbour or itself; that step, bounded to one
+  // cell, keeps every index inside the region once the old cell is
   const int a0 = clampi(mv.ix0 - q.X0, 1, LX - 4, bad);
-  const int a1 = clampi(mv.ix1 - q.X0, a0 - 1, a0 + 1, bad);
+  const int a1 = a0 + min(max(mv.ix1 - mv.ix0, -1), 1);
   const int b0 = clampi(mv.jr0 - q.R0, 1, LR - 4, bad);
-  const int b1 = clampi(mv.jr1 - q.R0, b0 - 1, b0 + 1, bad);
+  const int b1 = b0 + min(max(mv.jr1 - mv.jr0, -1), 1);
   // node weights on the 3-node union of the old and new supports, without
   // indexing into register arrays: d = a1 - a0 in {-1, 0, 1}
   const int dxs = a1 - a0, drs = b1 - b0;
@@ -994,9 +997,9 @@ template <class R, bool M1>
 __device__ inline void deposit_current2(SmemPos<R, M1>& sm, const Region& q, const Geo& g, const Move<R>& mv, R w,
                                         bool& bad) {
   const int a0 = clampi(mv.ix0 - q.X0, 2, LX - 4, bad);
-  const int a1 = clampi(mv.ix1 - q.X0, a0 - 1, a0 + 1, bad);
+  const int a1 = a0 + min(max(mv.ix1 - mv.ix0, -1), 1);  // (a step of at most one cell, as above)
   const int b0 = clampi(mv.jr0 - q.R0, 2, LR - 4, bad);
-  const int b1 = clampi(mv.jr1 - q.R0, b0 - 1, b0 + 1, bad);
+  const int b1 = b0 + min(max(mv.jr1 - mv.jr0, -1), 1);
   const Quad<R> X0 = quad_primal<R>(a0, mv.fx0), X1 = quad_primal<R>(a1, mv.fx1);
   const Quad<R> Y0 = quad_primal<R>(b0, mv.fr0), Y1 = quad_primal<R>(b1, mv.fr1);
   // nearest nodes move by at most one (less than a cell per step)
