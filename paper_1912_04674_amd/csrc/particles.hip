@@ -1480,8 +1480,10 @@ __global__ __launch_bounds__(WG) void k_position(Geo g, Grids<R> f, R* __restric
       const int b = clampi(cell_jr(cw) - q.R0, 2, LR - 4, bad);
       ph = interp3<R>(sm.phh, quad_primal<R>(a, fx), quad_primal<R>(b, fr));
     } else {
-      const int a = clampi(cell_ix(cw) - q.X0, 0, LX - 2, bad);
-      const int b = clampi(cell_jr(cw) - q.R0, 0, LR - 2, bad);
+      // the old cell is at most two cells out of the tile: the range of the
+      // current stencil's old cell, the same clamp as the deposit's (shared)
+      const int a = clampi(cell_ix(cw) - q.X0, 1, LX - 4, bad);
+      const int b = clampi(cell_jr(cw) - q.R0, 1, LR - 4, bad);
       ph = interp2<R>(sm.phh, primal_w<R>(a, fx), primal_w<R>(b, fr));
     }
     const R ig = rsqrt_r((R)1 + px * px + py * py + pz * pz + ph);
