@@ -210,11 +210,12 @@ def cpu_baseline(cfg, cols=256, steps=100):
     workload (its last `cols` cell columns, where the pulse is; full radius,
     same loading) for `steps` steps (a fifth as many on 1 thread); beside
     it, on all threads: the mode-0 parity workload in full (100 steps), a
-    256-column slab of the bandwidth workload (20 steps) and one scan job per
+    256-column slab of the bandwidth workload (20 steps), the leading
+    256-column slab of the largest workload (5 steps) and one scan job per
     grid size for 30 of its 300 steps (the job's CPU latency is scaled from
     those)."""
     import pyoracle
-    from inputs import C1, C3, C4_GRIDS, c4_job, scaled
+    from inputs import C1, C3, C5, C4_GRIDS, c4_job, scaled
     import numpy as np
     pyoracle.build()
     nthr = pyoracle.host_threads()
@@ -224,7 +225,9 @@ def cpu_baseline(cfg, cols=256, steps=100):
     many = _oracle_rate(pyoracle, sub, steps, nthr)
     others = {"c1_parity_256x32 (full, 100 steps)": _oracle_rate(pyoracle, C1, 100, nthr),
               "c3_bandwidth_4096x512 columns [1920, 2176), 20 steps":
-                  _oracle_rate(pyoracle, scaled(C3, nx=256, start_col=1920), 20, nthr)}
+                  _oracle_rate(pyoracle, scaled(C3, nx=256, start_col=1920), 20, nthr),
+              "c5_extreme_8192x768 columns [7936, 8192), 5 steps":
+                  _oracle_rate(pyoracle, scaled(C5, nx=256, start_col=7936), 5, nthr)}
     rng = np.random.default_rng(7)
     for nx, nr in C4_GRIDS:
         job = c4_job(0, rng)
