@@ -94,6 +94,41 @@ __device__ inline C interp3c(const C* a, const Quad<R>& sx, const Quad<R>& sr) {
   return mk<C>(re, im);
 }
 
+// Phi and its centred differences (times 1/(2 dx), 1/(2 dr)) interpolated
+// with one quadratic stencil, from Phi on the 5 x 5 nodes around the 3 x 3 of
+// the stencil (corners unused).  j0 is the grid row of the stencil's first
+// node (at least -1): the radial difference is zero on the axis row and, on
+// the ghost row below it, minus its value on row 1.
+template <class R, int RL>
+__device__ inline void phi_grad3(const R* phi, const Quad<R>& sx, const Quad<R>& sr, int j0, R i2dx, R i2dr,
+                                 R& ph, R& gx, R& gr) {
+  // the differences taken through the weights: a node's Phi enters the x
+  // difference with the weight of the node behind it minus that of the node
+  // ahead; the radial weights of the axis row and the ghost row are moved
+  // (zero on the axis, the ghost row folded onto row 1 with a sign)
+  const R k0 = j0 >= 1 ? sr.w[0] : (R)0, k1 = j0 >= 0 ? sr.w[1] : (R)0;
+  const R k2 = j0 == -1 ? sr.w[2] - sr.w[0] : sr.w[2];
+  const R dx[5] = {-sx.w[0], -sx.w[1], sx.w[0] - sx.w[2], sx.w[1], sx.w[2]};
+  const R dr[5] = {-k0, -k1, k0 - k2, k1, k2};
+  const R* p = phi + sx.i * RL + sr.i;
+  R a = 0, b = 0, d = 0;
+#pragma unroll
+  for (int u = -1; u < 4; ++u) {
+    const R* c = p + u * RL;
+    if (u >= 0 && u <= 2) {
+      const R c0 = c[0], c1 = c[1], c2 = c[2];
+      a += sx.w[u] * (sr.w[0] * c0 + sr.w[1] * c1 + sr.w[2] * c2);
+      d += sx.w[u] * (dr[0] * c[-1] + dr[1] * c0 + dr[2] * c1 + dr[3] * c2 + dr[4] * c[3]);
+      b += dx[u + 1] * (sr.w[0] * c0 + sr.w[1] * c1 + sr.w[2] * c2);
+    } else {
+      b += dx[u + 1] * (sr.w[0] * c[0] + sr.w[1] * c[1] + sr.w[2] * c[2]);
+    }
+  }
+  ph = a;
+  gx = b * i2dx;
+  gr = d * i2dr;
+}
+
 // v clamped to [lo, hi]; bad is set when it was outside (one min/max and one
 // compare)
 __device__ inline int clampi(int v, int lo, int hi, bool& bad) {
@@ -329,13 +364,15 @@ __device__ inline Region region_of(const Geo& g, int key, int h = HALO) {
 template <int H> struct Halo {
   static constexpr int X = TX + 2 * H + 1, R = TR + 2 * H + 1, N = X * R;
 };
-// The staged gradient of Phi is kept for quadratic shapes only (its ghost row
-// below the axis); linear gathers difference Phi where they read it.  The
-// sort counters exist only in the scattering variants.
+// The gradient of Phi is staged only by the scattering passes with quadratic
+// shapes (their registers are the tighter limit); the others difference the
+// staged Phi where they read it.  The sort counters exist only in the
+// scattering variants.
 template <class R, bool M1, int H, int O, bool SC> struct SmemMom {
   using C = typename cplx_of<R>::type;
   static constexpr int N = Halo<H>::N;
-  R ex[N], er[N], bt[N], phi[N], gx[O == 2 ? N : 1], gr[O == 2 ? N : 1];
+  static constexpr int NG = (O == 2 && SC) ? N : 1;
+  R ex[N], er[N], bt[N], phi[N], gx[NG], gr[NG];
   typename Acc0<R>::T chi[N];
   C ex1[M1 ? N : 1], er1[M1 ? N : 1], et1[M1 ? N : 1];
   C bx1[M1 ? N : 1], br1[M1 ? N : 1], bt1[M1 ? N : 1];
@@ -401,11 +438,12 @@ __device__ inline int wave_slot_rank(int slot, int* counters) {
 // deposits' LDS atomics do not collide), at the price of strided writes.
 // O: particle shape order (1 linear, 2 quadratic; order 2 re-sorts every
 // second step, so its wider stencil stays inside the same halo).
-// Waves per SIMD the compiler must allow: the FP32 linear in-place pass fits
-// four work groups per CU in LDS (its smaller region), so its registers are
-// held to 64 per lane (eight waves per SIMD); the others are not constrained.
+// Waves per SIMD the compiler must allow: the FP32 in-place pass fits four
+// work groups per CU in LDS (its smaller region, no staged gradient), so its
+// registers are held to 64 per lane (eight waves per SIMD); the others are
+// not constrained.
 template <class R, bool DEFER, int SCAT, int O> constexpr int mom_waves_per_simd() {
-  return (sizeof(R) == 4 && !DEFER && SCAT == SCAT_NONE && O == 1) ? 8 : 1;
+  return (sizeof(R) == 4 && !DEFER && SCAT == SCAT_NONE) ? 8 : 1;
 }
 
 // Margin: a scattering pass gathers at most SORT_EVERY cells of drift from
@@ -475,11 +513,11 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
     for (int k = threadIdx.x; k < (SCAT == SCAT_CELL ? CRN : 9); k += WG) sm.ccell[k] = 0;
   __syncthreads();
   // grad Phi by centred differences on the primal nodes (zero radial
-  // derivative on the axis); the outermost ring of the region is unused.
-  // Quadratic shapes stage it (with its odd ghost row below the axis);
-  // linear gathers difference the staged Phi themselves (below).
+  // derivative on the axis, odd below it).  A scattering pass with quadratic
+  // shapes stages it (the outermost ring of the region is unused); the
+  // other gathers form it from the staged Phi (below).
   const R i2dx = (R)(0.5 / g.dx), i2dr = (R)(0.5 / g.dr);
-  if constexpr (O == 2) {
+  if constexpr (O == 2 && SCAT != SCAT_NONE) {
     for (int k = threadIdx.x; k < RN; k += WG) {
       const int a = k / RL, b = k - (k / RL) * RL;
       R vx = 0, vr = 0;
@@ -647,9 +685,13 @@ __global__ __launch_bounds__(WG, (mom_waves_per_simd<R, DEFER, SCAT, O>())) void
       ex = interp3<R, RL>(sm.ex, Ux, Qr);
       er = interp3<R, RL>(sm.er, Qx, Ur);
       bt = interp3<R, RL>(sm.bt, Ux, Ur);
-      ph = interp3<R, RL>(sm.phi, Qx, Qr);
-      gx = interp3<R, RL>(sm.gx, Qx, Qr);
-      gr = interp3<R, RL>(sm.gr, Qx, Qr);
+      if constexpr (SCAT != SCAT_NONE) {
+        ph = interp3<R, RL>(sm.phi, Qx, Qr);
+        gx = interp3<R, RL>(sm.gx, Qx, Qr);
+        gr = interp3<R, RL>(sm.gr, Qx, Qr);
+      } else {
+        phi_grad3<R, RL>(sm.phi, Qx, Qr, q.R0 + Qr.i, i2dx, i2dr, ph, gx, gr);
+      }
       if (M1) {
         ex += mode1_at<C, R>(interp3c<C, R, RL>(sm.ex1, Ux, Qr), c, s);
         er += mode1_at<C, R>(interp3c<C, R, RL>(sm.er1, Qx, Ur), c, s);
