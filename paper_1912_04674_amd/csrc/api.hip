@@ -62,9 +62,13 @@ Sizes sizes_of(const envpic_params& p) {
                               : window + window / 4 + (long long)(ENTERING_TILES + 1) * TX * column +
                                     (SORT_EVERY * (CELL_SORT_EVERY + 1LL) + 1) * column + 1024;
   // work-item size: about four items per compute unit (256 of them) so that
-  // small runs fill the device, at most CHUNK, a multiple of WG
+  // small runs fill the device, at most CHUNK (CHUNK / 2 with quadratic
+  // shapes, whose particles cost more than the staging and flush of an
+  // item: measured faster on the LWFA workload, and CHUNK / 4 slower), a
+  // multiple of WG
   const long long per = window / (4LL * 256);
-  s.chunk = (int)std::max<long long>(WG, std::min<long long>(CHUNK, per / WG * WG));
+  const long long cmax = p.shape_order == 2 ? CHUNK / 2 : CHUNK;
+  s.chunk = (int)std::max<long long>(WG, std::min<long long>(cmax, per / WG * WG));
   // items: those of any layout of the tiles' particles, and those of the
   // columns injected between two sorts (a tile sort whose overflow would
   // need more rebuilds the layout instead)
