@@ -328,14 +328,21 @@ __device__ inline int transpose_rank(int r, int R) {
 }
 
 // slot of the r-th particle (in cell order) of a tile of v particles: the
-// tile splits into ceil(v / chunk) equal work items (as the scan makes
-// them) and the particles of an item are placed as at loading
+// tile splits into nm = ceil(v / chunk) equal work items (as the scan makes
+// them).  The ranks are dealt to the items in turn (listed by r mod nm, then
+// r / nm, and cut into the items' sizes), so that every item spans all cells
+// of the tile and a wavefront's lanes stay as far apart in cell order as
+// with one item per tile; inside an item the particles are placed as at
+// loading
 __device__ inline int placed_rank(int r, int v, int chunk) {
   const int nm = (v + chunk - 1) / chunk;
-  int k = (int)((long long)r * nm / v);
-  if (k + 1 < nm && (int)((long long)(k + 1) * v / nm) <= r) ++k;
+  if (nm == 1) return transpose_rank(r, v);
+  const int a = v / nm, b = v - a * nm, m = r % nm;
+  const int t = m * a + min(m, b) + r / nm;  // (the first b residues hold a + 1 ranks)
+  int k = (int)((long long)t * nm / v);
+  if (k + 1 < nm && (int)((long long)(k + 1) * v / nm) <= t) ++k;
   const int lo = (int)((long long)k * v / nm), hi = (int)((long long)(k + 1) * v / nm);
-  return lo + transpose_rank(r - lo, hi - lo);
+  return lo + transpose_rank(t - lo, hi - lo);
 }
 
 // the tile region of a work item with a margin of h cells: lab column
