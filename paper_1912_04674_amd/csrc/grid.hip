@@ -528,9 +528,18 @@ __device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __r
                                  bool half_r, R parity, int N, const R* cw, int i0, int j0, V* A, V* B) {
   const V zero = vscale(V{}, (R)0);
   const int lo = FH - N, hi = FH + FT + N;  // the region rows and columns used
-  for (int k = threadIdx.x; k < FR * FR; k += FTH) {
+  // every lane issues all of its loads before it writes any of them to LDS,
+  // so that they are in flight together: each load reads a valid address
+  // (the array's first element stands in for a node that is not read) and
+  // the value is selected afterwards; entries outside the rows and columns
+  // used are written as zero and never read
+  constexpr int NLD = (FR * FR + FTH - 1) / FTH;
+  size_t off[NLD];
+  R sc[NLD];
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) {
+    const int k = threadIdx.x + u * FTH;
     const int a = k / FR, b = k - (k / FR) * FR;
-    if (a < lo || a >= hi || b < lo || b >= hi) continue;
     float sx = 1.0f, sr = 1.0f;
     const int i = reflect_end(i0 - FH + a, imax, sx);
     int j = j0 - FH + b;
@@ -540,7 +549,17 @@ __device__ void filter_component(const Geo& g, const V* __restrict__ src, V* __r
     }
     j = reflect_end(j, jmax, sr);
     const bool odd_axis = !half_r && parity < (R)0 && j == 0;  // an odd function's axis value
-    A[k] = (i < 0 || j < 0 || odd_axis) ? zero : vscale(src[(size_t)phys_col(g, i) * g.pitch + j], (R)(sx * sr));
+    const bool ok = k < FR * FR && a >= lo && a < hi && b >= lo && b < hi && i >= 0 && j >= 0 && !odd_axis;
+    off[u] = ok ? (size_t)phys_col(g, i) * g.pitch + j : 0;
+    sc[u] = ok ? (R)(sx * sr) : (R)0;
+  }
+  V v[NLD];
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) v[u] = src[off[u]];
+#pragma unroll
+  for (int u = 0; u < NLD; ++u) {
+    const int k = threadIdx.x + u * FTH;
+    if (k < FR * FR) A[k] = sc[u] != (R)0 ? vscale(v[u], sc[u]) : zero;
   }
   __syncthreads();
   // along x: owned columns, the rows used
